@@ -1,0 +1,311 @@
+"""FOSSILS and SPIR -- oracle side (test infrastructure only).
+
+Written from the paper's algorithms in their order and notation:
+  * Algorithm 1 (meta-algorithm): sketch [A b], QR of S A, sketch-and-solve x_0
+    (eq:sketch-and-solve-2.3), then exactly two refinement steps
+    c_i = P^T A^T (b - A x_i),  dy_i = IterativeSolver(z -> P^T A^T A P z, c_i),
+    x_{i+1} = x_i + P dy_i  (eq:precond-normal-RHSc).
+  * Algorithm 5 (Polyak heavy ball) with eq:optimal-coeffs alpha = (1 - eta^2)^2, beta = eta^2;
+    Algorithm 2 runs it a fixed q times, Theorem 7.1 (eq:iterations) gives q_0.
+  * Algorithm 4 (recommended FOSSILS): column scaling, d = 12 n, zeta = 8, SVD of the sketch,
+    rank truncation at tau = 30 u, P = V Sigma^{-1}, and the two adaptive stopping rules of
+    Section 4.2 ("Adaptive stopping"), with these readings of garbled statements:
+      - "beta <- d/n" is read as beta = eta^2 = n/d (eq:optimal-coeffs, Algorithm 2);
+      - the "+ mu^2 z" term is dropped (mu = 0; the paper implements truncation instead of
+        regularization);
+      - the "Mod(i, 5)" test of the second step is read on the inner index j;
+      - the first-step rule uses ||x_0|| and ||b - A x_0|| (Section 4.2's statement).
+  * SPIR (Algorithm 3) with conjugate gradient on the preconditioned normal equations and the
+    same stopping rules (the paper omits its practical version; Delta = a_k p_k).
+  * Unit roundoff u = 2^-52.
+
+Preconditioner choices: ``precond="svd"`` is Algorithm 4's P = V Sigma^{-1} from the SVD of S A;
+``precond="qr"`` is Algorithms 1-3's P = R^{-1} from Householder QR of S [A b], applied by back
+substitution (Section 6: triangular solves are back substitutions); Sigma and V for the
+stopping rules then come from the SVD of R (S A = (Q U_R) Sigma V^T).  A numerically
+rank-deficient sketch always falls back to the truncated SVD preconditioner (Alg 4).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+from .backward_error import kw_from_svd
+from .householder import back_substitution, forward_substitution_transposed, householder_qr
+from .sketch import sketch_Ab
+
+U_ROUND = 2.0**-52
+
+FLAG_RANK_DEFICIENT = 1
+FLAG_NOT_CONVERGED = 2
+
+
+@dataclass
+class Options:
+    d: Optional[int] = None          # sketch rows; default 12 n (Alg 4)
+    zeta: int = 8                    # nonzeros per column of S (Alg 4)
+    seed: int = 12345                # sketch seed
+    eta: Optional[float] = None      # distortion estimate; default sqrt(n/d) (Section 4.2)
+    eta_factor: float = 1.0          # 1.1 = the paper's conservative choice
+    gamma: float = 10.0              # first-step rule constants of Alg 4
+    rho: float = 0.4
+    kw_every: int = 5                # sketched-KW cadence in the second step
+    max_inner: int = 100             # iteration cap per refinement step (Alg 4)
+    tau_factor: float = 30.0         # truncation threshold tau = 30 u
+    column_scaling: bool = True
+    precond: str = "qr"              # "qr" (P = R^{-1}) or "svd" (P = V Sigma^{-1})
+    fixed_q: int = 0                 # 0 adaptive; q > 0 Algorithm 2 with q steps; -1 q_0 of Thm 7.1
+    steps: int = 2                   # refinement steps (2 = the method; 1 = "FOSSILS (1 step)")
+
+
+@dataclass
+class Result:
+    x: np.ndarray
+    iters: list
+    flags: int
+    normest: float
+    condest: float
+    rank: int
+    be_sk: float
+    x0: np.ndarray
+    xs: list = field(default_factory=list)     # iterate after each refinement step (unscaled)
+    cs: list = field(default_factory=list)     # ||c_i|| (Table 2 quantity)
+    info: dict = field(default_factory=dict)
+
+
+# ---------------------------------------------------------------- single passes over A
+
+def column_norms(A):
+    """d_j = ||a_j||_2 (Alg 4, first statement); zero columns get 1 so the scaling is defined."""
+    d = np.sqrt(np.sum(A * A, axis=0))
+    d[d == 0.0] = 1.0
+    return d
+
+
+def normal_pass(A, z):
+    """v = A^T (A z): the operator of the preconditioned normal equations (eq:precond-normal)."""
+    return A.T @ (A @ z)
+
+
+def residual_pass(A, b, x):
+    """r = b - A x, g = A^T r and ||r||^2 (Algorithm 1, the refinement right-hand side)."""
+    r = b - A @ x
+    return A.T @ r, float(r @ r)
+
+
+def polyak_coefficients(eta):
+    """eq:optimal-coeffs: alpha = (1 - eta^2)^2, beta = eta^2."""
+    beta = eta * eta
+    return (1.0 - beta) ** 2, beta
+
+
+def q0_theorem71(kappa, eta):
+    """eq:iterations: q_0 = max(1 + 2 log(1/(kappa u)) / log(1/(1.01 eta)), 11), rounded up."""
+    ku = kappa * U_ROUND
+    if ku >= 1.0:
+        return 11
+    return int(math.ceil(max(1.0 + 2.0 * math.log(1.0 / ku) / math.log(1.0 / (1.01 * eta)), 11.0)))
+
+
+# ---------------------------------------------------------------- the solver
+
+class _Precond:
+    """P and P^T for either preconditioner (R^{-1} by substitution, or V Sigma^{-1})."""
+
+    def __init__(self, kind, R=None, V=None, sigma=None):
+        self.kind, self.R, self.V, self.sigma = kind, R, V, sigma
+
+    def P(self, y):
+        if self.kind == "qr":
+            return back_substitution(self.R, y)
+        return self.V @ (y / self.sigma)
+
+    def PT(self, v):
+        if self.kind == "qr":
+            return forward_substitution_transposed(self.R, v)
+        return (self.V.T @ v) / self.sigma
+
+
+def _stop_first(Delta, thr):
+    return np.linalg.norm(Delta) <= thr
+
+
+def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
+    """FOSSILS (Algorithm 4 / Algorithm 2) or SPIR (Algorithm 3 with CG) for min ||b - A x||."""
+    opts = opts or Options()
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    m, n = A.shape
+    if not (m >= n >= 1):
+        raise ValueError("need m >= n >= 1")
+    if not (np.all(np.isfinite(A)) and np.all(np.isfinite(b))):
+        raise ValueError("non-finite input")
+    dsk = opts.d or 12 * n
+    if dsk < n or not (1 <= opts.zeta <= dsk):
+        raise ValueError("need n <= d and 1 <= zeta <= d")
+    u = U_ROUND
+    if np.linalg.norm(b) == 0.0:
+        z = np.zeros(n)
+        return Result(x=z, iters=[0, 0], flags=0, normest=0.0, condest=0.0, rank=n, be_sk=0.0, x0=z)
+
+    # Alg 4: normalize columns.
+    dcol = column_norms(A) if opts.column_scaling else np.ones(n)
+    As = A / dcol
+    # Alg 4: embedding parameters and Polyak coefficients.
+    eta = (opts.eta if opts.eta is not None else math.sqrt(n / dsk)) * opts.eta_factor
+    alpha, beta = polyak_coefficients(eta)
+    # Alg 1 / Alg 4: sketch [A b] with one embedding.
+    Y = sketch_Ab(As, b, dsk, opts.zeta, opts.seed)
+    SA, Sb = Y[:, :n], Y[:, n]
+
+    # Factor the sketch.
+    if opts.precond == "qr":
+        Qinfo, Rfull = householder_qr(Y)          # S[A b] = Q [R t; 0 rho]
+        R, t = Rfull[:n, :n], Rfull[:n, n]
+        _, sig_full, Vt = np.linalg.svd(R)         # S A = (Q U_R) Sigma V^T
+        V_full = Vt.T
+        U_R = None
+    elif opts.precond == "svd":
+        U_sk, sig_full, Vt = np.linalg.svd(SA, full_matrices=False)
+        V_full = Vt.T
+        R = t = None
+    else:
+        raise ValueError("precond must be 'qr' or 'svd'")
+    normest = float(sig_full[0])
+    condest = float(sig_full[0] / sig_full[-1]) if sig_full[-1] > 0 else math.inf
+
+    flags = 0
+    rank = n
+    kind = opts.precond
+    if condest > 1.0 / (opts.tau_factor * u):
+        # Alg 4: numerically rank deficient -> truncated SVD preconditioner.
+        flags |= FLAG_RANK_DEFICIENT
+        rank = int(np.sum(sig_full > opts.tau_factor * u * normest))
+        kind = "svd"
+        if opts.precond == "qr":
+            U_R, _, _ = np.linalg.svd(R)
+    if kind == "svd":
+        sig = sig_full[:rank]
+        V = V_full[:, :rank]
+        pre = _Precond("svd", V=V, sigma=sig)
+        if opts.precond == "svd":
+            x0 = V @ ((U_sk[:, :rank].T @ Sb) / sig)          # Alg 4 sketch-and-solve
+        else:
+            x0 = V @ ((U_R[:, :rank].T @ t) / sig)            # same with S A = (Q U_R) Sigma V^T
+    else:
+        pre = _Precond("qr", R=R)
+        x0 = back_substitution(R, t)                           # eq:sketch-and-solve-2.3
+
+    # Alg 4: r = b - A x, kept for the first-step rule.
+    r0 = b - As @ x0
+    thr_first = (opts.gamma * normest * np.linalg.norm(x0) + opts.rho * condest * np.linalg.norm(r0)) * u
+    fro = np.linalg.norm(As)
+    theta = fro / np.linalg.norm(b)
+
+    if opts.fixed_q != 0:
+        if opts.fixed_q < 0:
+            q = q0_theorem71(condest, eta)
+            alpha, beta = polyak_coefficients(1.01 * eta)      # Thm 7.1 (D)
+        else:
+            q = opts.fixed_q
+
+    def apply_M(y):
+        return pre.PT(As.T @ (As @ pre.P(y)))
+
+    x = x0.copy()
+    iters, xs, cs = [], [], []
+    be_sk = math.nan
+    converged_last = False
+    for i in range(opts.steps):
+        c = pre.PT(As.T @ (b - As @ x))
+        cs.append(float(np.linalg.norm(c)))
+        it = 0
+        converged = False
+        if method == "fossils" and opts.fixed_q != 0:
+            # Algorithm 5: dy_(1) = dy_(0) = c, then q - 1 heavy-ball updates.
+            dy = c.copy()
+            dy_old = c.copy()
+            for _ in range(1, q):
+                dy, dy_old = dy + alpha * (c - apply_M(dy)) + beta * (dy - dy_old), dy
+                it += 1
+            converged = True
+        elif method == "fossils":
+            dy = c.copy()
+            dy_old = c.copy()
+            for j in range(opts.max_inner):
+                Delta = alpha * (c - apply_M(dy)) + beta * (dy - dy_old)
+                dy, dy_old = dy + Delta, dy
+                it += 1
+                if i == 0 and _stop_first(Delta, thr_first):
+                    converged = True
+                    break
+                if i == 1 and j % opts.kw_every == 0:
+                    xh = x + pre.P(dy)
+                    rh = b - As @ xh
+                    be_sk = kw_from_svd(sig_full, V_full, As.T @ rh, theta, np.linalg.norm(rh), np.linalg.norm(xh))
+                    if be_sk < fro * u:
+                        converged = True
+                        break
+        elif method == "spir":
+            dy = np.zeros_like(c)
+            res = c.copy()
+            p = c.copy()
+            rho = float(res @ res)
+            for j in range(opts.max_inner):
+                if rho == 0.0:
+                    converged = True
+                    break
+                qv = apply_M(p)
+                pq = float(p @ qv)
+                if pq <= 0.0:
+                    break
+                a = rho / pq
+                Delta = a * p
+                dy = dy + Delta
+                res = res - a * qv
+                rho_new = float(res @ res)
+                p = res + (rho_new / rho) * p
+                rho = rho_new
+                it += 1
+                if i == 0 and _stop_first(Delta, thr_first):
+                    converged = True
+                    break
+                if i == 1 and j % opts.kw_every == 0:
+                    xh = x + pre.P(dy)
+                    rh = b - As @ xh
+                    be_sk = kw_from_svd(sig_full, V_full, As.T @ rh, theta, np.linalg.norm(rh), np.linalg.norm(xh))
+                    if be_sk < fro * u:
+                        converged = True
+                        break
+        else:
+            raise ValueError("method must be 'fossils' or 'spir'")
+        x = x + pre.P(dy)                                     # Alg 1: x_{i+1} = x_i + P dy_i
+        iters.append(it)
+        xs.append(x / dcol)
+        converged_last = converged
+    if opts.steps == 2 and opts.fixed_q == 0 and not converged_last:
+        flags |= FLAG_NOT_CONVERGED
+    return Result(x=x / dcol, iters=iters, flags=flags, normest=normest, condest=condest, rank=rank,
+                  be_sk=float(be_sk), x0=x0 / dcol, xs=xs, cs=cs,
+                  info={"alpha": alpha, "beta": beta, "eta": eta, "d": dsk, "theta": theta,
+                        "fro": fro, "dcol": dcol, "thr_first": thr_first})
+
+
+def fossils(A, b, opts: Optional[Options] = None) -> Result:
+    return solve(A, b, "fossils", opts)
+
+
+def spir(A, b, opts: Optional[Options] = None) -> Result:
+    return solve(A, b, "spir", opts)
+
+
+def sketch_and_solve(A, b, d, zeta=8, seed=12345):
+    """x_0 = R^{-1} (Q^T S b) from the QR of S [A b] (eq:sketch-and-solve-2.3), unscaled A."""
+    n = A.shape[1]
+    Y = sketch_Ab(A, b, d, zeta, seed)
+    _, Rfull = householder_qr(Y)
+    return back_substitution(Rfull[:n, :n], Rfull[:n, n])

@@ -1,0 +1,199 @@
+"""Pins for the oracle's FOSSILS / SPIR (CPU only).
+
+Each test ties the oracle to a statement of the paper or to mathematics, not to itself.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import backward_error as be
+from oracle import householder as hh
+from oracle import solvers
+from oracle.sketch import sketch, sketch_Ab
+from synth import make_problem
+
+U = 2.0**-52
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.txt")
+
+
+def _gold():
+    out = {}
+    with open(GOLD) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            k1, k2, v = line.split()
+            out[(k1, k2)] = float(v)
+    return out
+
+
+def _fe(x, P):
+    return np.linalg.norm(x - P.x_true) / np.linalg.norm(P.x_true)
+
+
+CASES = [(1e10, 1e-6), (1e12, 1e-3), (1e4, 1.0), (1e2, 1e-10), (1e13, 1e-8)]
+
+
+@pytest.mark.parametrize("kappa,rnorm", CASES)
+@pytest.mark.parametrize("method", ["fossils", "spir"])
+@pytest.mark.parametrize("precond", ["qr", "svd"])
+def test_backward_stable_and_forward_error_vs_qr(kappa, rnorm, method, precond):
+    """Theorem 7.1 / Section 5.1: backward error at the level of Householder QR."""
+    P = make_problem(4000, 50, kappa, rnorm, seed=0)
+    res = solvers.solve(P.A, P.b, method, solvers.Options(precond=precond))
+    xq = hh.qr_lstsq(P.A, P.b)
+    bex = be.relative_backward_error(P.A, P.b, res.x, P.sigma, P.V)
+    beq = be.relative_backward_error(P.A, P.b, xq, P.sigma, P.V)
+    assert res.flags == 0
+    assert bex <= 1e-14
+    assert bex <= 30 * max(beq, U)
+    # forward error within 10x of Householder QR's, floored at the Wedin scale (Fact 2.3)
+    wedin = kappa * (1 + kappa * rnorm) * U
+    assert _fe(res.x, P) <= 10 * max(_fe(xq, P), 0.01 * wedin)
+
+
+def test_table1_residual_orthogonality_magnitude():
+    """Table 1: median ||A^T(b - A x)|| ~ 4e-14 (FOSSILS), 5.3e-14 (SPIR), 5.2e-14 (QR)."""
+    g = _gold()
+    vals = {"fossils": [], "spir": [], "householder_qr": []}
+    for seed in range(9):
+        P = make_problem(4000, 50, 1e12, 1e-3, seed=100 + seed)
+        for meth in ("fossils", "spir"):
+            x = solvers.solve(P.A, P.b, meth, solvers.Options(seed=seed)).x
+            vals[meth].append(np.linalg.norm(P.A.T @ (P.b - P.A @ x)))
+        xq = hh.qr_lstsq(P.A, P.b)
+        vals["householder_qr"].append(np.linalg.norm(P.A.T @ (P.b - P.A @ xq)))
+    for k, v in vals.items():
+        med = np.median(v)
+        ref = g[("table1", k)]
+        assert ref / 10 <= med <= ref * 10, (k, med, ref)
+    # strongly-forward-stable methods sit four orders above; ours must not
+    assert np.median(vals["fossils"]) < g[("table1", "iterative_sketching_momentum")] / 100
+
+
+def test_table2_norm_of_c():
+    """Table 2: ||c|| for the sketch-and-solve start ~3.0e-7 and for x_1 ~1.9e-11 (4000x50, 1e12, 1e-6)."""
+    g = _gold()
+    P = make_problem(4000, 50, 1e12, 1e-6, seed=1)
+    res = solvers.fossils(P.A, P.b)
+    c0, c1 = res.cs
+    assert g[("table2", "sketch_and_solve")] / 10 <= c0 <= g[("table2", "sketch_and_solve")] * 10
+    assert g[("table2", "x1")] / 10 <= c1 <= g[("table2", "x1")] * 10
+    # zero initialisation: c = R^{-T} A^T b
+    Y = sketch_Ab(P.A, P.b, 600, 8, 12345)
+    _, Rf = hh.householder_qr(Y)
+    cz = np.linalg.norm(hh.forward_substitution_transposed(Rf[:50, :50], P.A.T @ P.b))
+    assert g[("table2", "zero")] / 10 <= cz <= g[("table2", "zero")] * 10
+
+
+def test_spir_iteration_ceiling_figure6():
+    """Figure 6 (Section 5.2): SPIR needs at most 30 iterations in total at 4000 x 50."""
+    limit = _gold()[("fig6", "spir_max_total_iterations")]
+    for kappa in (1e2, 1e6, 1e10, 1e13):
+        for rnorm in (1e-12, 1e-6, 1e-2, 1.0):
+            P = make_problem(4000, 50, kappa, rnorm, seed=7)
+            res = solvers.spir(P.A, P.b)
+            assert sum(res.iters) <= limit, (kappa, rnorm, res.iters)
+
+
+def test_fact22_preconditioned_conditioning():
+    """Fact 2.2: singular values of A R^{-1} lie in [1/(1+eta), 1/(1-eta)] (eta slack 1.5 sqrt(n/d))."""
+    P = make_problem(4000, 50, 1e10, 1e-6, seed=2)
+    Y = sketch(P.A, 600, 8, 12345)
+    _, R = hh.householder_qr(Y)
+    AR = np.linalg.solve(R.T, P.A.T).T
+    s = np.linalg.svd(AR, compute_uv=False)
+    eta = 1.5 * np.sqrt(50 / 600)
+    assert s[-1] >= 1 / (1 + eta) and s[0] <= 1 / (1 - eta)
+
+
+def test_fact69_sketch_and_solve_accuracy():
+    """Fact 6.9: ||A (x - x_0)|| <~ ||b - A x|| + ||x|| u."""
+    for kappa, rnorm in [(1e10, 1e-6), (1e4, 1.0), (1e12, 1e-12)]:
+        P = make_problem(4000, 50, kappa, rnorm, seed=3)
+        x0 = solvers.sketch_and_solve(P.A, P.b, 600)
+        lhs = np.linalg.norm(P.A @ (P.x_true - x0))
+        assert lhs <= 10 * (rnorm + np.linalg.norm(P.x_true) * U * 1e2)
+
+
+def test_lemma73_polyak_rate():
+    """Lemma 7.3 (no noise): ||dy_(j) - M^{-1} c|| <= 4 sqrt(2) j eta^{j-2} ||c||, alpha, beta optimal."""
+    P = make_problem(3000, 30, 10.0, 1e-2, seed=4)
+    Y = sketch(P.A, 360, 8, 9)
+    _, R = hh.householder_qr(Y)
+    AR = np.linalg.solve(R.T, P.A.T).T
+    s = np.linalg.svd(AR, compute_uv=False)
+    eta = max(1 - 1 / s[0], 1 / s[-1] - 1)          # distortion realised by this sketch
+    alpha, beta = solvers.polyak_coefficients(eta)
+    M = AR.T @ AR
+    c = AR.T @ P.b
+    ystar = np.linalg.solve(M, c)
+    dy, dy_old = c.copy(), c.copy()                 # Algorithm 5 start
+    for j in range(1, 40):
+        err = np.linalg.norm(dy - ystar)
+        bound = 4 * np.sqrt(2) * j * eta ** (j - 2) * np.linalg.norm(c)
+        assert err <= bound + 1e-13 * np.linalg.norm(ystar), j
+        dy, dy_old = dy + alpha * (c - M @ dy) + beta * (dy - dy_old), dy
+
+
+def test_one_refinement_step_is_not_backward_stable():
+    """Section 5.1: FOSSILS (1 step) is forward but not backward stable on hard problems."""
+    P = make_problem(4000, 50, 1e12, 1e12 * U, seed=5)
+    one = solvers.fossils(P.A, P.b, solvers.Options(steps=1, max_inner=100))
+    two = solvers.fossils(P.A, P.b)
+    b1 = be.relative_backward_error(P.A, P.b, one.x, P.sigma, P.V)
+    b2 = be.relative_backward_error(P.A, P.b, two.x, P.sigma, P.V)
+    assert b2 <= 1e-15 and b1 >= 30 * b2
+
+
+def test_fixed_q_algorithm2():
+    """Algorithm 2 with q_0 from Theorem 7.1 (eq:iterations) is backward stable."""
+    P = make_problem(4000, 50, 1e10, 1e-4, seed=6)
+    res = solvers.fossils(P.A, P.b, solvers.Options(fixed_q=-1))
+    assert res.iters[0] == res.iters[1] == solvers.q0_theorem71(res.condest, np.sqrt(50 / 600)) - 1
+    assert be.relative_backward_error(P.A, P.b, res.x, P.sigma, P.V) <= 1e-14
+
+
+def test_q0_formula_values():
+    eta = np.sqrt(1 / 12)
+    # eq:iterations at d = 12 n
+    assert solvers.q0_theorem71(1e10, eta) == 23
+    assert solvers.q0_theorem71(1e14, eta) == 11
+    assert solvers.q0_theorem71(1e2, eta) == 53
+
+
+def test_rank_deficient_all_ones():
+    """Section 4.2: an all-ones matrix must give a finite answer (truncated preconditioner)."""
+    m, n = 500, 10
+    A = np.ones((m, n))
+    b = np.random.default_rng(0).standard_normal(m)
+    for meth in ("fossils", "spir"):
+        res = solvers.solve(A, b, meth)
+        assert res.flags & solvers.FLAG_RANK_DEFICIENT
+        assert np.all(np.isfinite(res.x)) and res.rank == 1
+        # residual is the optimal one: b minus its mean
+        assert abs(np.linalg.norm(b - A @ res.x) - np.linalg.norm(b - b.mean())) <= 1e-10
+
+
+def test_zero_rhs_gives_zero():
+    P = make_problem(400, 10, 1e3, 1e-3, seed=1)
+    res = solvers.fossils(P.A, np.zeros(400))
+    assert np.all(res.x == 0)
+
+
+def test_first_step_rule_constants_from_text():
+    """Section 4.2 text uses gamma = 1, rho = 0.04; both settings must stay backward stable."""
+    P = make_problem(4000, 50, 1e10, 1e-6, seed=8)
+    res = solvers.fossils(P.A, P.b, solvers.Options(gamma=1.0, rho=0.04))
+    assert be.relative_backward_error(P.A, P.b, res.x, P.sigma, P.V) <= 1e-14
+
+
+def test_planted_mistakes_are_caught(monkeypatch):
+    """A plausible slip in the heavy-ball coefficients breaks the accuracy pins above."""
+    P = make_problem(4000, 50, 1e10, 1e-6, seed=0)
+    monkeypatch.setattr(solvers, "polyak_coefficients", lambda eta: ((1 - eta**2), -eta**2))
+    res = solvers.fossils(P.A, P.b)
+    bad = be.relative_backward_error(P.A, P.b, res.x, P.sigma, P.V)
+    assert res.flags & solvers.FLAG_NOT_CONVERGED or bad > 1e-14 or sum(res.iters) > 60
