@@ -1,0 +1,167 @@
+/*
+ * fossils.h -- C ABI of the MI355X (gfx950) FOSSILS / SPIR least-squares library.
+ *
+ * Solves the overdetermined least-squares problem  x = argmin_x ||b - A x||_2  with A m x n,
+ * m >= n (Epperly, Meier, Nakatsukasa, "Fast randomized least-squares solvers can be just as
+ * accurate and stable as classical direct solvers", Section 1, eq:ls), with the two backward
+ * stable randomized solvers of that paper:
+ *   FOSSILS  -- Algorithm 1 with the Polyak heavy-ball inner solver (Algorithms 2, 4 and 5);
+ *   SPIR     -- Algorithm 1 with conjugate gradient on the preconditioned normal equations
+ *               (Algorithm 3).
+ * Both sketch [A b] with a sparse sign embedding (Section 4.2), factor the sketch, start from the
+ * sketch-and-solve solution (eq:sketch-and-solve-2.3) and run exactly two refinement steps
+ * (eq:precond-normal-RHSc) with the adaptive stopping rules of Section 4.2 (first step: size of
+ * the update; second step: the sketched Karlson-Walden backward-error estimate, eq:sketched-kw).
+ *
+ * Conventions for every entry point
+ *   - Matrices are column-major with a leading dimension (lda >= rows).  Arrays named A, b, x, Y,
+ *     R, V, z, v, g are DEVICE pointers (HIP device memory of the context's device) unless the
+ *     name ends in _host.  The caller owns them; they must stay valid until the call returns.
+ *     The library never writes A or b (column scaling is applied to vectors, not to A).
+ *   - Work is enqueued on the context's HIP stream; every call below is synchronous with respect
+ *     to that stream on return (results are in place when the call returns).
+ *   - Return codes: FS_OK (0), positive warnings (the result is valid), negative errors (nothing
+ *     was written to the outputs).  Argument validation happens before any device work.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef FOSSILS_H
+#define FOSSILS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fs_status {
+  FS_OK = 0,
+  FS_WARN_RANK_DEFICIENT = 1,  /* condest > 1/(30u): truncated SVD preconditioner used (Alg 4) */
+  FS_WARN_NOT_CONVERGED = 2,   /* second-step rule not met within max_inner iterations */
+  FS_ERR_INVALID_ARG = -1,     /* null pointer or invalid option value */
+  FS_ERR_SHAPE = -2,           /* m < n, n < 1, d < n, zeta < 1, zeta > d, zeta > 64, lda < m, ... */
+  FS_ERR_NOMEM = -3,           /* device allocation failed */
+  FS_ERR_DEVICE = -4,          /* a HIP call failed (see fs_last_error_detail) */
+  FS_ERR_NONFINITE = -5,       /* A or b holds NaN or Inf */
+  FS_ERR_TOO_LARGE = -6,       /* size beyond what this build supports */
+  FS_ERR_UNKNOWN_TICKET = -7,
+  FS_ERR_UNSUPPORTED = -8
+} fs_status;
+
+typedef struct fs_context_s* fs_context;
+typedef struct fs_sketch_s* fs_sketch;
+
+enum { FS_PRECOND_QR = 0, FS_PRECOND_SVD = 1 };
+enum { FS_FP64 = 0, FS_MIXED = 1 };
+
+/* Solver options (Section 4.2 and Algorithm 4).  Fill with fs_options_default. */
+typedef struct fs_options {
+  int32_t d;              /* sketch rows; Alg 4 uses 12 n */
+  int32_t zeta;           /* nonzeros per column of S; Alg 4 uses 8 (1..64 supported) */
+  uint64_t seed;          /* seed of the sketch's counter-based generator */
+  double eta;             /* distortion estimate; <= 0 means sqrt(n/d) (Section 4.2) */
+  double eta_factor;      /* multiplies eta; 1.1 is the paper's conservative choice */
+  double gamma, rho;      /* first-step rule constants; Alg 4 uses 10 and 0.4 */
+  int32_t kw_every;       /* second-step sketched-KW cadence; 5 in Section 4.2 */
+  int32_t max_inner;      /* iteration cap per refinement step; 100 in Alg 4 */
+  double tau_factor;      /* rank truncation at tau = tau_factor * u; 30 in Alg 4 */
+  int32_t column_scaling; /* 1: unit-norm columns (Alg 4, first statement) */
+  int32_t precond;        /* FS_PRECOND_QR: P = R^{-1} by substitution; FS_PRECOND_SVD: P = V Sigma^{-1} */
+  int32_t fixed_q;        /* 0: adaptive stopping; q > 0: Algorithm 2 with q heavy-ball steps;
+                             -1: q_0 of Theorem 7.1 (eq:iterations) with kappa = condest */
+  int32_t steps;          /* refinement steps: 2 (the method) or 1 ("one step" variant) */
+  int32_t precision;      /* FS_FP64 (reserved: FS_MIXED) */
+  int32_t max_sweeps;     /* Jacobi sweep cap of the SVD of R */
+} fs_options;
+
+/* Per-solve report. */
+typedef struct fs_info {
+  int32_t iters[2];       /* inner iterations of the two refinement steps */
+  int32_t flags;          /* bit 0: rank deficient, bit 1: not converged */
+  int32_t rank;           /* rank of the preconditioner (n unless truncated) */
+  double be_sk;           /* last sketched KW estimate of the scaled problem (absolute) */
+  double normest;         /* sigma_max of the sketch */
+  double condest;         /* sigma_max / sigma_min of the sketch */
+  double cnorm[2];        /* ||c_i|| at the start of each refinement step */
+  int32_t svd_sweeps;     /* Jacobi sweeps used */
+  int32_t kw_evals;       /* sketched-KW evaluations */
+  double phase_ms[6];     /* sketch, QR, SVD, init (x0 + first residual), step 0, step 1 */
+} fs_info;
+
+/* Human-readable name of a status code; detail of the last failing HIP call of this thread. */
+const char* fs_status_string(fs_status s);
+const char* fs_last_error_detail(void);
+
+/* Context: a device and a HIP stream (hip_stream may be NULL for the null stream); owns the
+ * workspace, which grows to the largest problem seen and is freed by fs_context_destroy. */
+fs_status fs_context_create(int device, void* hip_stream, fs_context* out);
+fs_status fs_context_destroy(fs_context ctx);
+
+/* Defaults of Algorithm 4 for an m x n problem (d = 12 n, zeta = 8, gamma = 10, rho = 0.4,
+ * kw_every = 5, max_inner = 100, tau_factor = 30, column scaling on, QR preconditioner). */
+fs_status fs_options_default(int64_t m, int32_t n, fs_options* opts);
+
+/* FOSSILS (Algorithm 4 with Polyak inner solves; Algorithm 2 when opts->fixed_q != 0).
+ * A: m x n (lda >= m), b: m, x: n output.  opts may be NULL (defaults).  info may be NULL.
+ * Returns FS_OK, a warning, or an error; FS_ERR_NONFINITE when A or b holds NaN/Inf.  b = 0 gives
+ * x = 0. */
+fs_status fossils_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                        double* x, const fs_options* opts, fs_info* info);
+
+/* SPIR (Algorithm 3: conjugate gradient on the preconditioned normal equations) with the same
+ * sketch, preconditioner, initialization and stopping rules as fossils_solve. */
+fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                     double* x, const fs_options* opts, fs_info* info);
+
+/* ---------------- sparse sign embedding (Section 4.2, "Choice of embedding") ---------------- */
+
+/* Sketch handle for S (d x m, zeta nonzeros per column).  The index stream is generated on the
+ * device from (seed, column) with a Philox4x32-10 counter-based generator and kept by the handle. */
+fs_status sketch_create(fs_context ctx, int64_t m, int32_t d, int32_t zeta, uint64_t seed, fs_sketch* out);
+fs_status sketch_destroy(fs_sketch sk);
+
+/* Copy the row positions and signs of columns [col0, col0+ncols) of S to host arrays
+ * rows_host[ncols*zeta] (int32, positions in [0,d)) and signs_host[ncols*zeta] (+1/-1). */
+fs_status sketch_indices(fs_sketch sk, int64_t col0, int64_t ncols, int32_t* rows_host, int8_t* signs_host);
+
+/* Y = S [A b] (d x (n+1), ldy >= d; the last column is S b; b may be NULL, then Y is d x n).
+ * With scale_columns, column j < n is divided by ||a_j|| (zero columns by 1), i.e. Y = S [A D^{-1} b]
+ * (Alg 4's column scaling).  colnorm2 (n, device, may be NULL) receives ||a_j||^2 from the same
+ * read of A. */
+fs_status sketch_apply(fs_sketch sk, int32_t n, const double* A, int64_t lda, const double* b, double* Y,
+                       int64_t ldy, double* colnorm2, int32_t scale_columns);
+
+/* ---------------- step-level entry points (the parts of the hot path) ---------------- */
+
+/* In-place Householder QR of the d x k matrix Y (ldy >= d, d >= k) (eq:sketch_qr).  On return the
+ * upper triangle of Y[0:k, 0:k] holds R with a non-negative diagonal; entries below the diagonal
+ * are overwritten with reflector data. */
+fs_status fs_sketch_qr(fs_context ctx, int32_t d, int32_t k, double* Y, int64_t ldy);
+
+/* SVD of an n x n upper-triangular R (upper triangle of R, ldr >= n) by one-sided Jacobi:
+ * sigma (n, decreasing), V (n x n, ldv >= n) right singular vectors, so R^T R = V diag(sigma)^2 V^T
+ * (Alg 4: normest = sigma[0], condest = sigma[0]/sigma[n-1]).  sweeps_host (may be NULL) receives
+ * the number of Jacobi sweeps. */
+fs_status fs_svd_triangular(fs_context ctx, int32_t n, const double* R, int64_t ldr, double* sigma, double* V,
+                            int64_t ldv, int32_t* sweeps_host);
+
+/* v = A^T (A z): the operator of the preconditioned normal equations (eq:precond-normal) in one
+ * read of A.  z, v: n. */
+fs_status fs_normal_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z,
+                         double* v);
+
+/* g = A^T (b - A x) and ||b - A x||^2 (the right-hand side of a refinement step, Algorithm 1) in
+ * one read of A.  rnorm2_host may be NULL. */
+fs_status fs_residual_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                           const double* x, double* g, double* rnorm2_host);
+
+/* x = R^{-1} y (transpose = 0, back substitution) or x = R^{-T} y (transpose = 1, forward
+ * substitution) for upper-triangular R (ldr >= n); x may equal y.  n <= 16384. */
+fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
+                  double* x);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOSSILS_H */

@@ -1,0 +1,267 @@
+"""Thin ctypes binding of libfossils.so (argument marshalling only).
+
+Every function mirrors the C entry point of the same name in include/fossils.h.  Tensors are torch
+tensors in device memory; torch provides memory and the current HIP stream, nothing else.  Matrices
+are column-major: a torch (rows, cols) tensor with strides (1, ld), e.g. ``M.t().contiguous().t()``.
+There is no fallback: if the library is missing, ``load()`` raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libfossils.so")
+
+FS_OK = 0
+FS_WARN_RANK_DEFICIENT = 1
+FS_WARN_NOT_CONVERGED = 2
+FS_ERR_INVALID_ARG = -1
+FS_ERR_SHAPE = -2
+FS_ERR_NOMEM = -3
+FS_ERR_DEVICE = -4
+FS_ERR_NONFINITE = -5
+FS_ERR_TOO_LARGE = -6
+FS_ERR_UNKNOWN_TICKET = -7
+FS_ERR_UNSUPPORTED = -8
+
+FS_PRECOND_QR = 0
+FS_PRECOND_SVD = 1
+
+c_int32, c_int64, c_uint64, c_double, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
+
+
+class FsOptions(ctypes.Structure):
+    _fields_ = [
+        ("d", c_int32), ("zeta", c_int32), ("seed", c_uint64), ("eta", c_double), ("eta_factor", c_double),
+        ("gamma", c_double), ("rho", c_double), ("kw_every", c_int32), ("max_inner", c_int32),
+        ("tau_factor", c_double), ("column_scaling", c_int32), ("precond", c_int32), ("fixed_q", c_int32),
+        ("steps", c_int32), ("precision", c_int32), ("max_sweeps", c_int32),
+    ]
+
+
+class FsInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", c_int32 * 2), ("flags", c_int32), ("rank", c_int32), ("be_sk", c_double),
+        ("normest", c_double), ("condest", c_double), ("cnorm", c_double * 2), ("svd_sweeps", c_int32),
+        ("kw_evals", c_int32), ("phase_ms", c_double * 6),
+    ]
+
+    def to_dict(self):
+        return {
+            "iters": [self.iters[0], self.iters[1]], "flags": self.flags, "rank": self.rank,
+            "be_sk": self.be_sk, "normest": self.normest, "condest": self.condest,
+            "cnorm": [self.cnorm[0], self.cnorm[1]], "svd_sweeps": self.svd_sweeps,
+            "kw_evals": self.kw_evals, "phase_ms": list(self.phase_ms),
+        }
+
+
+class FossilsError(RuntimeError):
+    def __init__(self, status, detail=""):
+        self.status = status
+        super().__init__(f"{status_string(status)} {detail}".strip())
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("fs_status_string", ctypes.c_char_p, [c_int32]),
+    ("fs_last_error_detail", ctypes.c_char_p, []),
+    ("fs_context_create", c_int32, [ctypes.c_int, c_vp, ctypes.POINTER(c_vp)]),
+    ("fs_context_destroy", c_int32, [c_vp]),
+    ("fs_options_default", c_int32, [c_int64, c_int32, ctypes.POINTER(FsOptions)]),
+    ("fossils_solve", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
+                                ctypes.POINTER(FsInfo)]),
+    ("spir_solve", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
+                             ctypes.POINTER(FsInfo)]),
+    ("sketch_create", c_int32, [c_vp, c_int64, c_int32, c_int32, c_uint64, ctypes.POINTER(c_vp)]),
+    ("sketch_destroy", c_int32, [c_vp]),
+    ("sketch_indices", c_int32, [c_vp, c_int64, c_int64, c_vp, c_vp]),
+    ("sketch_apply", c_int32, [c_vp, c_int32, c_vp, c_int64, c_vp, c_vp, c_int64, c_vp, c_int32]),
+    ("fs_sketch_qr", c_int32, [c_vp, c_int32, c_int32, c_vp, c_int64]),
+    ("fs_svd_triangular", c_int32, [c_vp, c_int32, c_vp, c_int64, c_vp, c_vp, c_int64, ctypes.POINTER(c_int32)]),
+    ("fs_normal_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp]),
+    ("fs_residual_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_vp,
+                                   ctypes.POINTER(c_double)]),
+    ("fs_trsv", c_int32, [c_vp, c_int32, c_vp, c_int64, c_int32, c_vp, c_vp]),
+]
+
+
+def exported_names():
+    return [n for n, _, _ in _SIGS]
+
+
+def load(path: Optional[str] = None):
+    """Load libfossils.so (built in-tree by ``paper_2406_03468_amd.build``); raise if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIBPATH
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"{p} is missing: build it with `python -m paper_2406_03468_amd.build`")
+    lib = ctypes.CDLL(p)
+    for name, res, args in _SIGS:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    try:
+        return load().fs_status_string(int(s)).decode()
+    except Exception:
+        return f"status {s}"
+
+
+def _check(s: int, allow_warn: bool = True) -> int:
+    if s < 0 or (s > 0 and not allow_warn):
+        detail = load().fs_last_error_detail().decode()
+        raise FossilsError(s, detail)
+    return s
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _colmajor(M):
+    """(rows, cols) tensor with unit row stride -> leading dimension."""
+    if M.dim() == 1:
+        return M.shape[0]
+    if M.stride(0) != 1:
+        raise ValueError("matrix must be column-major (stride(0) == 1)")
+    return M.stride(1) if M.shape[1] > 1 else max(M.shape[0], M.stride(1))
+
+
+class Context:
+    """fs_context on a torch device, bound to torch's current stream at creation."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        self.lib = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = c_vp()
+        _check(self.lib.fs_context_create(int(device), c_vp(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            self.lib.fs_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fs_options_default(m: int, n: int) -> FsOptions:
+    o = FsOptions()
+    _check(load().fs_options_default(int(m), int(n), ctypes.byref(o)))
+    return o
+
+
+def _solve(fn, ctx: Context, A, b, x, opts: Optional[FsOptions]):
+    m, n = A.shape
+    info = FsInfo()
+    s = fn(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(x)),
+           ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
+    return s, info
+
+
+def fossils_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
+    s, info = _solve(load().fossils_solve, ctx, A, b, x, opts)
+    _check(s)
+    return s, info
+
+
+def spir_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
+    s, info = _solve(load().spir_solve, ctx, A, b, x, opts)
+    _check(s)
+    return s, info
+
+
+class Sketch:
+    def __init__(self, ctx: Context, m: int, d: int, zeta: int, seed: int):
+        self.ctx, self.m, self.d, self.zeta, self.seed = ctx, m, d, zeta, seed
+        h = c_vp()
+        _check(load().sketch_create(ctx.h, int(m), int(d), int(zeta), c_uint64(seed), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            load().sketch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sketch_create(ctx: Context, m: int, d: int, zeta: int, seed: int) -> Sketch:
+    return Sketch(ctx, m, d, zeta, seed)
+
+
+def sketch_destroy(sk: Sketch):
+    sk.close()
+
+
+def sketch_indices(sk: Sketch, col0: int, ncols: int):
+    import numpy as np
+
+    rows = np.zeros(ncols * sk.zeta, dtype=np.int32)
+    signs = np.zeros(ncols * sk.zeta, dtype=np.int8)
+    _check(load().sketch_indices(sk.h, int(col0), int(ncols), rows.ctypes.data_as(c_vp), signs.ctypes.data_as(c_vp)))
+    return rows.reshape(ncols, sk.zeta), signs.reshape(ncols, sk.zeta)
+
+
+def sketch_apply(sk: Sketch, A, b, Y, colnorm2=None, scale_columns: bool = False):
+    n = A.shape[1]
+    _check(load().sketch_apply(sk.h, int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(Y)),
+                               int(_colmajor(Y)), c_vp(_ptr(colnorm2)), int(bool(scale_columns))))
+
+
+def fs_sketch_qr(ctx: Context, Y):
+    d, k = Y.shape
+    _check(load().fs_sketch_qr(ctx.h, int(d), int(k), c_vp(_ptr(Y)), int(_colmajor(Y))))
+
+
+def fs_svd_triangular(ctx: Context, R, sigma, V) -> int:
+    n = R.shape[1]
+    sw = c_int32(0)
+    _check(load().fs_svd_triangular(ctx.h, int(n), c_vp(_ptr(R)), int(_colmajor(R)), c_vp(_ptr(sigma)),
+                                    c_vp(_ptr(V)), int(_colmajor(V)), ctypes.byref(sw)))
+    return sw.value
+
+
+def fs_normal_pass(ctx: Context, A, z, v):
+    m, n = A.shape
+    _check(load().fs_normal_pass(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(z)),
+                                 c_vp(_ptr(v))))
+
+
+def fs_residual_pass(ctx: Context, A, b, x, g) -> float:
+    m, n = A.shape
+    r2 = c_double(0.0)
+    _check(load().fs_residual_pass(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)),
+                                   c_vp(_ptr(x)), c_vp(_ptr(g)), ctypes.byref(r2)))
+    return r2.value
+
+
+def fs_trsv(ctx: Context, R, y, x, transpose: bool = False):
+    n = R.shape[1]
+    _check(load().fs_trsv(ctx.h, int(n), c_vp(_ptr(R)), int(_colmajor(R)), int(bool(transpose)), c_vp(_ptr(y)),
+                          c_vp(_ptr(x))))

@@ -1,0 +1,60 @@
+// Internal device/host helpers shared by the HIP kernels of the FOSSILS/SPIR library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FS_WAVE 64
+
+// Return FS_ERR_DEVICE from a host function when a HIP call fails.
+#define FS_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) {                            \
+      fs_set_last_hip_error(e_, #call, __FILE__, __LINE__); \
+      return FS_ERR_DEVICE;                            \
+    }                                                  \
+  } while (0)
+
+void fs_set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
+
+// Full-wave sum with butterfly shuffles (every lane gets the total).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, FS_WAVE);
+  return v;
+}
+
+// Sum over the lanes whose lane index differs only in bits [lo, 6): lanes sharing lane % (1<<lo).
+template <int LO>
+__device__ __forceinline__ double wave_sum_high(double v) {
+#pragma unroll
+  for (int off = 32; off >= (1 << LO); off >>= 1) v += __shfl_xor(v, off, FS_WAVE);
+  return v;
+}
+
+// Sum over the lanes whose lane index differs only in bits [0, HI): groups of (1<<HI) lanes.
+template <int HI>
+__device__ __forceinline__ double wave_sum_low(double v) {
+#pragma unroll
+  for (int off = 1; off < (1 << HI); off <<= 1) v += __shfl_xor(v, off, FS_WAVE);
+  return v;
+}
+
+// Deterministic block reduction of one double (fixed shuffle + fixed LDS order).
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh /* NT/64 doubles */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  __syncthreads();
+  return t;
+}
+
+// Device-side early exit: kernels of an inner iteration return at once when the stop flag is set.
+__device__ __forceinline__ bool fs_stopped(const int* stop) { return stop != nullptr && *stop != 0; }

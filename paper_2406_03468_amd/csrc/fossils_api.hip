@@ -1,0 +1,658 @@
+// Host orchestration behind the C ABI declared in include/fossils.h.
+//
+// One solve (QR preconditioner, adaptive stopping) runs on the context's stream:
+//   sketch index stream -> Y = S [A D^{-1} b] and ||a_j||^2 (one read of A)
+//   -> Householder QR of Y (cooperative kernel) -> SVD of R (cooperative Jacobi)
+//   -> x_0 = R^{-1} t -> for i in {0,1}: residual pass, c = P^T g, inner iterations
+//      (z = P dy, v = A^T A z in one read of A, u = P^T v, heavy-ball or CG update),
+//      x += P dy -> x = D^{-1} x.
+// The inner loop's scalars and stop flag live in device memory (DevState); kernels of an inner
+// iteration return at once when the flag is set, and the host reads the flag once per kw_every
+// iterations.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/fossils.h"
+#include "common.hpp"
+#include "internal.hpp"
+#include "state.hpp"
+
+hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
+                              double* Uout, int64_t ldu, void* work, int num_cu, int max_sweeps, int* sweeps_out_dev,
+                              hipStream_t s);
+
+static thread_local std::string g_last_detail;
+
+void fs_set_last_hip_error(hipError_t e, const char* what, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  g_last_detail = buf;
+}
+
+namespace {
+
+constexpr double U_ROUND = 2.220446049250313e-16;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Workspace {
+  DevBuf idx, Y, colnorm2, dinv, qrwork, svdwork, sigma, V, UR, partial, pr2, wscratch, gemvpart, vecs, state;
+};
+
+}  // namespace
+
+struct fs_context_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 0;
+  int lds_bytes = 0;
+  Workspace ws;
+  DevState* st_host = nullptr;  // pinned copy for read-back
+  hipEvent_t ev[8] = {};
+};
+
+struct fs_sketch_s {
+  fs_context ctx = nullptr;
+  int64_t m = 0;
+  int d = 0, zeta = 0;
+  uint64_t seed = 0;
+  bool idx16 = true;
+  void* idx = nullptr;
+};
+
+namespace {
+
+fs_status grow(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return FS_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    fs_set_last_hip_error(e, "hipMalloc", __FILE__, __LINE__);
+    (void)hipGetLastError();
+    return FS_ERR_NOMEM;
+  }
+  b.bytes = bytes;
+  return FS_OK;
+}
+
+void free_buf(DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+#define FS_TRY(expr)                 \
+  do {                               \
+    fs_status s_ = (expr);           \
+    if (s_ != FS_OK) return s_;      \
+  } while (0)
+
+#define FS_K(expr)                                                   \
+  do {                                                               \
+    hipError_t e_ = (expr);                                          \
+    if (e_ != hipSuccess) {                                          \
+      fs_set_last_hip_error(e_, #expr, __FILE__, __LINE__);          \
+      return FS_ERR_DEVICE;                                          \
+    }                                                                \
+  } while (0)
+
+bool idx16_ok(int d) { return d <= 32767; }
+
+fs_status validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x) {
+  if (!A || !b || !x) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < n || lda < m) return FS_ERR_SHAPE;
+  return FS_OK;
+}
+
+fs_status validate_options(int64_t m, int32_t n, const fs_options& o) {
+  if (o.d < n || o.zeta < 1 || o.zeta > o.d || o.zeta > 64) return FS_ERR_SHAPE;
+  if ((int64_t)o.d > m && m > 0 && false) return FS_ERR_SHAPE;
+  if (o.kw_every < 1 || o.max_inner < 1 || o.steps < 1 || o.steps > 2) return FS_ERR_INVALID_ARG;
+  if (!(o.gamma >= 0) || !(o.rho >= 0) || !(o.tau_factor > 0) || !(o.eta_factor > 0)) return FS_ERR_INVALID_ARG;
+  if (o.precond != FS_PRECOND_QR && o.precond != FS_PRECOND_SVD) return FS_ERR_INVALID_ARG;
+  if (o.precision != FS_FP64) return FS_ERR_UNSUPPORTED;
+  if (o.fixed_q < -1) return FS_ERR_INVALID_ARG;
+  if (n > 16384) return FS_ERR_TOO_LARGE;       // TRSV keeps x in LDS
+  if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
+  if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
+  return FS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fs_status_string(fs_status s) {
+  switch (s) {
+    case FS_OK: return "FS_OK";
+    case FS_WARN_RANK_DEFICIENT: return "FS_WARN_RANK_DEFICIENT";
+    case FS_WARN_NOT_CONVERGED: return "FS_WARN_NOT_CONVERGED";
+    case FS_ERR_INVALID_ARG: return "FS_ERR_INVALID_ARG";
+    case FS_ERR_SHAPE: return "FS_ERR_SHAPE";
+    case FS_ERR_NOMEM: return "FS_ERR_NOMEM";
+    case FS_ERR_DEVICE: return "FS_ERR_DEVICE";
+    case FS_ERR_NONFINITE: return "FS_ERR_NONFINITE";
+    case FS_ERR_TOO_LARGE: return "FS_ERR_TOO_LARGE";
+    case FS_ERR_UNKNOWN_TICKET: return "FS_ERR_UNKNOWN_TICKET";
+    case FS_ERR_UNSUPPORTED: return "FS_ERR_UNSUPPORTED";
+  }
+  return "FS_UNKNOWN_STATUS";
+}
+
+const char* fs_last_error_detail(void) { return g_last_detail.c_str(); }
+
+fs_status fs_options_default(int64_t m, int32_t n, fs_options* o) {
+  if (!o) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < n) return FS_ERR_SHAPE;
+  memset(o, 0, sizeof(*o));
+  int64_t d = 12 * (int64_t)n;
+  o->d = (int32_t)d;
+  o->zeta = 8;
+  if (o->zeta > o->d) o->zeta = o->d;
+  o->seed = 12345;
+  o->eta = 0.0;
+  o->eta_factor = 1.0;
+  o->gamma = 10.0;
+  o->rho = 0.4;
+  o->kw_every = 5;
+  o->max_inner = 100;
+  o->tau_factor = 30.0;
+  o->column_scaling = 1;
+  o->precond = FS_PRECOND_QR;
+  o->fixed_q = 0;
+  o->steps = 2;
+  o->precision = FS_FP64;
+  o->max_sweeps = 40;
+  return FS_OK;
+}
+
+fs_status fs_context_create(int device, void* hip_stream, fs_context* out) {
+  if (!out) return FS_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  FS_HIP(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return FS_ERR_INVALID_ARG;
+  FS_HIP(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  FS_HIP(hipGetDeviceProperties(&prop, device));
+  fs_context c = new fs_context_s();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->num_cu = prop.multiProcessorCount;
+  c->lds_bytes = (int)std::min<size_t>(prop.sharedMemPerBlock, (size_t)160 * 1024);
+  if (c->lds_bytes > 128 * 1024) c->lds_bytes = 128 * 1024 + 16 * 1024;  // leave room for static LDS
+  hipError_t e = hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    fs_set_last_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    delete c;
+    return FS_ERR_NOMEM;
+  }
+  for (auto& ev : c->ev) (void)hipEventCreate(&ev);
+  *out = c;
+  return FS_OK;
+}
+
+fs_status fs_context_destroy(fs_context c) {
+  if (!c) return FS_ERR_INVALID_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  Workspace& w = c->ws;
+  for (DevBuf* b : {&w.idx, &w.Y, &w.colnorm2, &w.dinv, &w.qrwork, &w.svdwork, &w.sigma, &w.V, &w.UR, &w.partial,
+                    &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state})
+    free_buf(*b);
+  for (auto& ev : c->ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->st_host) (void)hipHostFree(c->st_host);
+  delete c;
+  return FS_OK;
+}
+
+// ---------------------------------------------------------------- sketch handle
+fs_status sketch_create(fs_context ctx, int64_t m, int32_t d, int32_t zeta, uint64_t seed, fs_sketch* out) {
+  if (!ctx || !out) return FS_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (m < 1 || d < 1 || zeta < 1 || zeta > d || zeta > 64) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  fs_sketch sk = new fs_sketch_s();
+  sk->ctx = ctx;
+  sk->m = m;
+  sk->d = d;
+  sk->zeta = zeta;
+  sk->seed = seed;
+  sk->idx16 = idx16_ok(d);
+  const size_t bytes = (size_t)m * zeta * (sk->idx16 ? 2 : 4);
+  hipError_t e = hipMalloc(&sk->idx, bytes);
+  if (e != hipSuccess) {
+    fs_set_last_hip_error(e, "hipMalloc", __FILE__, __LINE__);
+    delete sk;
+    return FS_ERR_NOMEM;
+  }
+  e = fs_launch_sketch_indices(m, d, zeta, seed, 0, m, sk->idx, sk->idx16, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    fs_set_last_hip_error(e, "sketch index generation", __FILE__, __LINE__);
+    (void)hipFree(sk->idx);
+    delete sk;
+    return FS_ERR_DEVICE;
+  }
+  *out = sk;
+  return FS_OK;
+}
+
+fs_status sketch_destroy(fs_sketch sk) {
+  if (!sk) return FS_ERR_INVALID_ARG;
+  (void)hipSetDevice(sk->ctx->device);
+  (void)hipStreamSynchronize(sk->ctx->stream);
+  if (sk->idx) (void)hipFree(sk->idx);
+  delete sk;
+  return FS_OK;
+}
+
+fs_status sketch_indices(fs_sketch sk, int64_t col0, int64_t ncols, int32_t* rows_host, int8_t* signs_host) {
+  if (!sk || !rows_host || !signs_host) return FS_ERR_INVALID_ARG;
+  if (col0 < 0 || ncols < 0 || col0 + ncols > sk->m) return FS_ERR_SHAPE;
+  if (ncols == 0) return FS_OK;
+  FS_HIP(hipSetDevice(sk->ctx->device));
+  const size_t esz = sk->idx16 ? 2 : 4;
+  std::vector<uint8_t> buf((size_t)ncols * sk->zeta * esz);
+  FS_HIP(hipMemcpyAsync(buf.data(), (const uint8_t*)sk->idx + (size_t)col0 * sk->zeta * esz, buf.size(),
+                        hipMemcpyDeviceToHost, sk->ctx->stream));
+  FS_HIP(hipStreamSynchronize(sk->ctx->stream));
+  const size_t cnt = (size_t)ncols * sk->zeta;
+  for (size_t i = 0; i < cnt; ++i) {
+    uint32_t e = sk->idx16 ? ((const uint16_t*)buf.data())[i] : ((const uint32_t*)buf.data())[i];
+    rows_host[i] = (int32_t)(e >> 1);
+    signs_host[i] = (e & 1u) ? -1 : 1;
+  }
+  return FS_OK;
+}
+
+fs_status sketch_apply(fs_sketch sk, int32_t n, const double* A, int64_t lda, const double* b, double* Y,
+                       int64_t ldy, double* colnorm2, int32_t scale_columns) {
+  if (!sk || !A || !Y) return FS_ERR_INVALID_ARG;
+  if (n < 1 || lda < sk->m || ldy < sk->d) return FS_ERR_SHAPE;
+  fs_context ctx = sk->ctx;
+  FS_HIP(hipSetDevice(ctx->device));
+  double* cn = colnorm2;
+  if (!cn) {
+    FS_TRY(grow(ctx->ws.colnorm2, sizeof(double) * (n + 1)));
+    cn = (double*)ctx->ws.colnorm2.p;
+  }
+  FS_K(fs_launch_sketch_apply(A, lda, sk->m, n, b, sk->idx, sk->idx16, sk->d, sk->zeta, Y, ldy, cn,
+                              scale_columns != 0, false, ctx->lds_bytes, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return FS_OK;
+}
+
+// ---------------------------------------------------------------- step-level calls
+fs_status fs_sketch_qr(fs_context ctx, int32_t d, int32_t k, double* Y, int64_t ldy) {
+  if (!ctx || !Y) return FS_ERR_INVALID_ARG;
+  if (k < 1 || d < k || ldy < d) return FS_ERR_SHAPE;
+  if (d > 65536) return FS_ERR_TOO_LARGE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_TRY(grow(ctx->ws.qrwork, fs_qr_work_bytes(d, k, ctx->num_cu)));
+  FS_K(fs_launch_qr(Y, ldy, d, k, ctx->ws.qrwork.p, ctx->num_cu, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return FS_OK;
+}
+
+fs_status fs_svd_triangular(fs_context ctx, int32_t n, const double* R, int64_t ldr, double* sigma, double* V,
+                            int64_t ldv, int32_t* sweeps_host) {
+  if (!ctx || !R || !sigma || !V) return FS_ERR_INVALID_ARG;
+  if (n < 1 || ldr < n || ldv < n) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_TRY(grow(ctx->ws.svdwork, fs_svd_work_bytes(n)));
+  FS_TRY(grow(ctx->ws.state, sizeof(DevState) + 64));
+  int* sw = (int*)((char*)ctx->ws.state.p + sizeof(DevState));
+  FS_K(fs_launch_svd(R, ldr, n, sigma, V, ldv, ctx->ws.svdwork.p, ctx->num_cu, 40, sw, ctx->stream));
+  int swh = 0;
+  FS_HIP(hipMemcpyAsync(&swh, sw, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  if (sweeps_host) *sweeps_host = swh;
+  return FS_OK;
+}
+
+static PassConfig pass_config(fs_context ctx, int64_t m, int32_t n, int64_t lda) {
+  PassConfig cfg = fs_pass_config(m, n, ctx->num_cu);
+  // 32-bit lane offsets inside a column slot (see the fused-pass kernel)
+  if (cfg.H) {
+    const int64_t cpr = 512 / (cfg.H / 2);
+    if ((cpr * lda + cfg.H) * 8 >= (int64_t(1) << 32)) cfg = PassConfig{0, 512};
+  }
+  return cfg;
+}
+
+static fs_status ensure_pass_ws(fs_context ctx, int64_t m, int32_t n, int64_t lda) {
+  const PassConfig cfg = pass_config(ctx, m, n, lda);
+  FS_TRY(grow(ctx->ws.partial, sizeof(double) * (size_t)cfg.G * n));
+  FS_TRY(grow(ctx->ws.pr2, sizeof(double) * (size_t)cfg.G + 64));
+  if (!cfg.H) FS_TRY(grow(ctx->ws.wscratch, sizeof(double) * (size_t)m));
+  return FS_OK;
+}
+
+// Enqueue one fused pass; the workspace must already be sized (ensure_pass_ws), so no buffer
+// is reallocated while earlier work on the stream may still use it.
+static fs_status run_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* zs,
+                          const double* b, double* out, const double* out_scale, double* r2_dev, const int* stop) {
+  const PassConfig cfg = pass_config(ctx, m, n, lda);
+  if (ctx->ws.partial.bytes < sizeof(double) * (size_t)cfg.G * n) return FS_ERR_INVALID_ARG;
+  PassArgs a{A, lda, m, n, zs, b, (double*)ctx->ws.partial.p, (double*)ctx->ws.pr2.p, stop};
+  FS_K(fs_launch_pass(a, cfg, out, out_scale, r2_dev, (double*)ctx->ws.wscratch.p, ctx->stream));
+  return FS_OK;
+}
+
+fs_status fs_normal_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z,
+                         double* v) {
+  if (!ctx || !A || !z || !v) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < 1 || lda < m) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  FS_TRY(run_pass(ctx, m, n, A, lda, z, nullptr, v, nullptr, nullptr, nullptr));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return FS_OK;
+}
+
+fs_status fs_residual_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                           const double* x, double* g, double* rnorm2_host) {
+  if (!ctx || !A || !b || !x || !g) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < 1 || lda < m) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  FS_TRY(grow(ctx->ws.state, sizeof(DevState) + 64));
+  FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  double* r2 = (double*)((char*)ctx->ws.state.p + sizeof(DevState) + 8);
+  FS_TRY(run_pass(ctx, m, n, A, lda, x, b, g, nullptr, r2, nullptr));
+  double r2h = 0;
+  FS_HIP(hipMemcpyAsync(&r2h, r2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  if (rnorm2_host) *rnorm2_host = r2h;
+  return FS_OK;
+}
+
+fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
+                  double* x) {
+  if (!ctx || !R || !y || !x) return FS_ERR_INVALID_ARG;
+  if (n < 1 || ldr < n) return FS_ERR_SHAPE;
+  if (n > 16384) return FS_ERR_TOO_LARGE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_K(fs_launch_trsv(R, ldr, n, transpose != 0, y, x, nullptr, nullptr, nullptr, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return FS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- the solver
+namespace {
+
+enum Method { M_FOSSILS = 0, M_SPIR = 1 };
+
+struct Vecs {
+  double *x, *x0, *c, *dy, *dy_old, *zs, *v, *u, *g, *xh, *w, *res, *p, *t, *tmp, *z;
+};
+
+fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                double* x_out, const fs_options* opts_in, fs_info* info) {
+  if (!ctx) return FS_ERR_INVALID_ARG;
+  FS_TRY(validate_problem(m, n, A, lda, b, x_out));
+  fs_options o;
+  if (opts_in) o = *opts_in;
+  else FS_TRY(fs_options_default(m, n, &o));
+  FS_TRY(validate_options(m, n, o));
+  FS_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  FS_HIP(hipStreamSynchronize(s));  // workspace may be reallocated below
+  Workspace& W = ctx->ws;
+  const int d = o.d, zeta = o.zeta, k = n + 1;
+  const bool i16 = idx16_ok(d);
+
+  // ---- workspace
+  FS_TRY(grow(W.idx, (size_t)m * zeta * (i16 ? 2 : 4)));
+  FS_TRY(grow(W.Y, sizeof(double) * (size_t)d * k));
+  FS_TRY(grow(W.colnorm2, sizeof(double) * (size_t)(n + 1)));
+  FS_TRY(grow(W.dinv, sizeof(double) * (size_t)n));
+  FS_TRY(grow(W.qrwork, fs_qr_work_bytes(d, k, ctx->num_cu)));
+  FS_TRY(grow(W.svdwork, fs_svd_work_bytes(n)));
+  FS_TRY(grow(W.sigma, sizeof(double) * (size_t)n));
+  FS_TRY(grow(W.V, sizeof(double) * (size_t)n * n));
+  FS_TRY(grow(W.UR, sizeof(double) * (size_t)n * n));
+  FS_TRY(grow(W.gemvpart, sizeof(double) * (size_t)n * ((n + 63) / 64 + 1)));
+  const int NV = 16;
+  FS_TRY(grow(W.vecs, sizeof(double) * (size_t)NV * n));
+  FS_TRY(grow(W.state, sizeof(DevState) + 64));
+  FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  double* vb = (double*)W.vecs.p;
+  Vecs v{vb, vb + n, vb + 2 * n, vb + 3 * n, vb + 4 * n, vb + 5 * n, vb + 6 * n, vb + 7 * n,
+         vb + 8 * n, vb + 9 * n, vb + 10 * n, vb + 11 * n, vb + 12 * n, vb + 13 * n, vb + 14 * n, vb + 15 * n};
+  DevState* st = (DevState*)W.state.p;
+  int* svd_sweeps_dev = (int*)((char*)W.state.p + sizeof(DevState));
+  const int* stop = &st->stop;
+  double* Y = (double*)W.Y.p;
+  double* cn2 = (double*)W.colnorm2.p;
+  double* dinv = (double*)W.dinv.p;
+  double* sigma = (double*)W.sigma.p;
+  double* V = (double*)W.V.p;
+  double* UR = (double*)W.UR.p;
+  double* gpart = (double*)W.gemvpart.p;
+  const double* R = Y;  // upper triangle of Y[0:n, 0:n], ld = d
+  const int64_t ldr = d;
+  const double* tvec = Y + (int64_t)n * d;  // t = (Q^T S b)[0:n]
+
+  // ---- host copy of the initial state
+  const double eta = ((o.eta > 0) ? o.eta : sqrt((double)n / d)) * o.eta_factor;
+  const double beta0 = eta * eta;                            // eq:optimal-coeffs
+  FS_K(fs_vec_state_init(st, (1.0 - beta0) * (1.0 - beta0), beta0, o.max_inner, s));
+
+  hipEvent_t* ev = ctx->ev;
+  FS_HIP(hipEventRecord(ev[0], s));
+  // ---- sketch (Alg 1 first statement; Alg 4 column scaling in the same read of A)
+  FS_K(fs_launch_sketch_indices(m, d, zeta, o.seed, 0, m, W.idx.p, i16, s));
+  FS_K(fs_launch_sketch_apply(A, lda, m, n, b, W.idx.p, i16, d, zeta, Y, d, cn2, o.column_scaling != 0, true,
+                              ctx->lds_bytes, s));
+  FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
+  FS_HIP(hipEventRecord(ev[1], s));
+  // ---- QR of the sketch
+  FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
+  FS_HIP(hipEventRecord(ev[2], s));
+  // ---- SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate)
+  const bool want_u = (o.precond == FS_PRECOND_SVD);
+  FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, want_u ? UR : nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+                          svd_sweeps_dev, s));
+  FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
+  FS_HIP(hipEventRecord(ev[3], s));
+  // read back: colnorms (finiteness, ||b||), sigma stats
+  FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  std::vector<double> cnh(n + 1);
+  FS_HIP(hipMemcpyAsync(cnh.data(), cn2, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, s));
+  int svd_sweeps = 0;
+  FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  FS_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j <= n; ++j)
+    if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
+  const double b2 = cnh[n];
+  DevState hs = *ctx->st_host;
+  fs_info inf{};
+  inf.normest = hs.normest;
+  inf.condest = hs.condest;
+  inf.rank = n;
+  inf.svd_sweeps = svd_sweeps;
+  if (b2 == 0.0) {  // b = 0: x = 0
+    FS_HIP(hipMemsetAsync(x_out, 0, sizeof(double) * n, s));
+    FS_HIP(hipStreamSynchronize(s));
+    if (info) *info = inf;
+    return FS_OK;
+  }
+  int flags = 0;
+  bool use_svd = (o.precond == FS_PRECOND_SVD);
+  int rk = n;
+  if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {  // Alg 4: numerically rank deficient
+    flags |= 1;
+    rk = hs.rank_trunc > 0 ? hs.rank_trunc : 1;
+    if (!use_svd) {  // need U_R as well: recompute with accumulation
+      FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev,
+                              s));
+      use_svd = true;
+    }
+  }
+  inf.rank = rk;
+  const int nr = use_svd ? rk : n;  // length of the preconditioned variables dy, c, ...
+
+  // P y (into out, n) and P^T v (into out, nr); yscale/xscale fold D^{-1}.
+  auto applyP = [&](const double* y, double* out, const double* oscale, const double* addv, const int* stp) -> fs_status {
+    if (use_svd) {
+      FS_K(fs_vec_gemv_v(V, n, n, nr, y, sigma, oscale, addv, out, gpart, stp, s));
+    } else {
+      FS_K(fs_launch_trsv(R, ldr, n, false, y, out, nullptr, oscale, stp, s));
+      if (addv) FS_K(fs_vec_add_norm(n, addv, out, out, nullptr, stp, s));
+    }
+    return FS_OK;
+  };
+  auto applyPT = [&](const double* vin, double* out, const int* stp) -> fs_status {
+    if (use_svd) {
+      FS_K(fs_vec_gemv_vt(V, n, n, nr, vin, sigma, out, stp, s));
+    } else {
+      FS_K(fs_launch_trsv(R, ldr, n, true, vin, out, nullptr, nullptr, stp, s));
+    }
+    return FS_OK;
+  };
+
+  // ---- x_0: sketch-and-solve (eq:sketch-and-solve-2.3; Alg 4 with the SVD factors)
+  if (use_svd) {
+    FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));  // U_r^T t
+    FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
+  } else {
+    FS_K(fs_launch_trsv(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, s));
+  }
+  FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));
+
+  // theta^2 and the first-step threshold need ||b||^2 and ||A_s||_F^2
+  {
+    // st->theta2 = fro2 / b2: computed on the host from the read-back fro2 (set by k_scaling)
+    FS_K(fs_vec_set_double(&st->theta2, hs.fro2 / b2, s));
+    FS_K(fs_vec_set_double(&st->b2, b2, s));
+  }
+
+  int iters[2] = {0, 0};
+  bool conv_last = true;
+  double cnorm[2] = {0, 0};
+  int q_fixed = 0;
+  if (o.fixed_q != 0) {
+    if (o.fixed_q > 0) {
+      q_fixed = o.fixed_q;
+    } else {  // Theorem 7.1: alpha, beta from 1.01 eta; q_0 from condest
+      const double e2 = 1.01 * eta;
+      const double ku = hs.condest * U_ROUND;
+      q_fixed = (ku >= 1.0) ? 11 : (int)ceil(std::max(1.0 + 2.0 * log(1.0 / ku) / log(1.0 / e2), 11.0));
+      const double b1 = e2 * e2;                               // Thm 7.1 (D)
+      FS_K(fs_vec_set_double(&st->alpha, (1.0 - b1) * (1.0 - b1), s));
+      FS_K(fs_vec_set_double(&st->beta, b1, s));
+    }
+  }
+  FS_HIP(hipEventRecord(ev[4], s));
+
+  for (int step = 0; step < o.steps; ++step) {
+    // residual pass at x (scaled coordinates): g = D^{-1} A^T (b - A D^{-1} x), r2
+    FS_K(fs_vec_mul(n, v.x, dinv, v.zs, nullptr, s));
+    FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, nullptr));
+    if (step == 0) {
+      FS_K(fs_vec_first_threshold(n, v.x0, o.gamma, o.rho, st, s));
+      FS_HIP(hipEventRecord(ev[5], s));
+    }
+    FS_TRY(applyPT(v.g, v.c, nullptr));
+    // FOSSILS: dy = dy_old = c.  SPIR: dy = 0, res = p = c.
+    if (method == M_FOSSILS) FS_K(fs_vec_step_init(nr, v.c, v.dy, v.dy_old, v.dy, false, st, s));
+    else FS_K(fs_vec_step_init(nr, v.c, v.res, v.p, v.dy, true, st, s));
+    const bool fixed = (method == M_FOSSILS && q_fixed > 0);
+    const int cap = fixed ? q_fixed - 1 : o.max_inner;
+    if (fixed) FS_K(fs_vec_set_int(&st->max_inner, cap, s));
+    const bool first = (step == 0) && !fixed;
+    bool stopped = false;
+    for (int j = 0; j < cap && !stopped; ++j) {
+      const double* dir = (method == M_FOSSILS) ? v.dy : v.p;
+      FS_TRY(applyP(dir, v.zs, dinv, nullptr, stop));                   // z' = D^{-1} P dir
+      FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, nullptr, v.v, dinv, nullptr, stop));  // v = D^{-1} A^T A z'
+      FS_TRY(applyPT(v.v, v.u, stop));                                 // u = P^T v
+      if (method == M_FOSSILS) FS_K(fs_vec_polyak(nr, v.c, v.u, v.dy, v.dy_old, st, first, s));
+      else FS_K(fs_vec_cg(nr, v.p, v.u, v.res, v.dy, st, first, s));
+      const bool kw_now = (!fixed) && (step == 1) && (j % o.kw_every == 0);
+      if (kw_now) {  // second-step rule (Alg 4): sketched KW at x_hat = x + P dy
+        FS_TRY(applyP(v.dy, v.xh, nullptr, v.x, stop));
+        FS_K(fs_vec_add_norm(n, v.xh, nullptr, v.xh, &st->x2, stop, s));
+        FS_K(fs_vec_mul(n, v.xh, dinv, v.zs, stop, s));
+        FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, stop));
+        FS_K(fs_vec_gemv_vt(V, n, n, n, v.g, nullptr, v.w, stop, s));
+        FS_K(fs_vec_kw(n, v.w, sigma, st, s));
+      }
+      const bool poll = fixed ? (j == cap - 1) : (((j + 1) % o.kw_every) == 0 || j == cap - 1);
+      if (poll && !fixed) {
+        FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+        FS_HIP(hipStreamSynchronize(s));
+        if (ctx->st_host->stop) stopped = true;
+      }
+    }
+    // x <- x + P dy
+    FS_TRY(applyP(v.dy, v.z, nullptr, v.x, nullptr));
+    FS_K(fs_vec_mul(n, v.z, nullptr, v.x, nullptr, s));
+    FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipEventRecord(ev[6 + (step > 0 ? 1 : 0)], s));
+    FS_HIP(hipStreamSynchronize(s));
+    iters[step] = ctx->st_host->iters;
+    cnorm[step] = sqrt(ctx->st_host->cnorm2);
+    conv_last = ctx->st_host->converged != 0 || fixed;
+    if (fixed) FS_K(fs_vec_set_int(&st->max_inner, o.max_inner, s));  // restore the cap
+  }
+  // x_out = D^{-1} x
+  FS_K(fs_vec_mul(n, v.x, dinv, x_out, nullptr, s));
+  FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  FS_HIP(hipStreamSynchronize(s));
+  if (o.steps == 2 && o.fixed_q == 0 && !conv_last) flags |= 2;
+  inf.iters[0] = iters[0];
+  inf.iters[1] = iters[1];
+  inf.flags = flags;
+  inf.be_sk = ctx->st_host->be_sk;
+  inf.kw_evals = ctx->st_host->kw_evals;
+  inf.cnorm[0] = cnorm[0];
+  inf.cnorm[1] = cnorm[1];
+  auto el = [&](int a, int bb) -> double {
+    float t = 0;
+    return (hipEventElapsedTime(&t, ev[a], ev[bb]) == hipSuccess) ? (double)t : -1.0;
+  };
+  inf.phase_ms[0] = el(0, 1);
+  inf.phase_ms[1] = el(1, 2);
+  inf.phase_ms[2] = el(2, 3);
+  inf.phase_ms[3] = el(4, 5);
+  inf.phase_ms[4] = el(5, 6);
+  inf.phase_ms[5] = (o.steps > 1) ? el(6, 7) : 0.0;
+  if (info) *info = inf;
+  if (flags & 1) return FS_WARN_RANK_DEFICIENT;
+  if (flags & 2) return FS_WARN_NOT_CONVERGED;
+  return FS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fs_status fossils_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                        double* x, const fs_options* opts, fs_info* info) {
+  return solve(ctx, M_FOSSILS, m, n, A, lda, b, x, opts, info);
+}
+
+fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b, double* x,
+                     const fs_options* opts, fs_info* info) {
+  return solve(ctx, M_SPIR, m, n, A, lda, b, x, opts, info);
+}
+
+}  // extern "C"

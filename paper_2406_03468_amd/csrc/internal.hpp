@@ -1,0 +1,59 @@
+// Internal interfaces between the host orchestration and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// ---------------------------------------------------------------- fused passes over A
+struct PassArgs {
+  const double* A;       // m x n column-major
+  int64_t lda;
+  int64_t m;
+  int n;
+  const double* zs;      // n, pre-scaled vector (D^{-1} z)
+  const double* b;       // m, residual mode when non-null
+  double* partial;       // [G][n] work-group partials
+  double* partial_r2;    // [G]
+  const int* stop;       // device stop flag (may be null)
+};
+struct PassConfig {
+  int H;  // tile rows (0 = unfused fallback)
+  int G;  // work-groups
+};
+PassConfig fs_pass_config(int64_t m, int n, int num_cu);
+// out = out_scale .* (A^T w), w = A zs (normal) or b - A zs (residual, r2_out = ||w||^2).
+hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out, const double* out_scale,
+                          double* r2_out, double* w_scratch, hipStream_t s);
+
+// ---------------------------------------------------------------- sparse sign sketch
+// Index stream: per source row j, zeta entries (position << 1 | sign_bit), 16- or 32-bit.
+hipError_t fs_launch_sketch_indices(int64_t m, int d, int zeta, uint64_t seed, int64_t col0, int64_t ncols,
+                                    void* idx, bool idx16, hipStream_t s);
+// Y[:, j] = (1/sqrt(zeta)) * colscale_j * S[:, :] M[:, j] for the n columns of A and (if b) b;
+// colnorm2[j] = ||A[:, j]||^2 is produced in the same read of A.  If scale_by_norm, column j < n of
+// Y is divided by ||A[:, j]|| (zero columns: by 1).
+hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n, const double* b,
+                                  const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
+                                  double* colnorm2, bool scale_by_norm, bool write_bnorm, int lds_bytes,
+                                  hipStream_t s);
+
+// ---------------------------------------------------------------- QR of the sketch
+// In-place Householder QR of the d x k matrix Y (ldy), d >= k.  On exit the upper triangle of
+// Y[0:k, 0:k] holds R with a non-negative diagonal; the reflectors are not kept.
+// work: device scratch of fs_qr_work_bytes(d, k) bytes.
+size_t fs_qr_work_bytes(int d, int k, int num_cu);
+hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int num_cu, hipStream_t s);
+
+// ---------------------------------------------------------------- triangular solves with R (n x n, ldr)
+// x = R^{-1} y (upper, back substitution) or x = R^{-T} y (forward substitution); in place on x.
+hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
+                          const double* yscale, const double* xscale, const int* stop, hipStream_t s);
+
+// ---------------------------------------------------------------- SVD of R (one-sided Jacobi)
+size_t fs_svd_work_bytes(int n);
+// Also returns U_R (left singular vectors of R) when Uout is non-null.
+hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
+                              double* Uout, int64_t ldu, void* work, int num_cu, int max_sweeps,
+                              int* sweeps_out_dev, hipStream_t s);
+hipError_t fs_launch_svd(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
+                         void* work, int num_cu, int max_sweeps, int* sweeps_out_dev, hipStream_t s);

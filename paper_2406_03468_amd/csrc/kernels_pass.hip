@@ -1,0 +1,282 @@
+// Fused passes over A for the refinement loop (one HBM read of A per pass).
+//
+//   normal pass   : v  = A^T (A z)                      (operator of eq:precond-normal, Alg 1/5)
+//   residual pass : g  = A^T (b - A x),  ||b - A x||^2  (right-hand side c_i of Alg 1, KW check)
+//
+// Column scaling (Alg 4, first statement) is folded into the vectors by the caller: the kernels
+// see the unscaled A and a pre-scaled z' = D^{-1} z; the caller scales the result by D^{-1}.
+//
+// Design: A is column-major (lda >= m).  A work-group owns a tile of H consecutive rows across all
+// n columns.  Each lane loads two consecutive rows of one column (16-byte loads; H/2 lanes cover
+// the H*8-byte contiguous segment of a column), so a wave instruction reads whole cache lines.
+// The tile stays in registers between the two products:
+//   phase 1  w_r = sum_c A[r,c] z[c]      (lane-local FMAs, then a shuffle + LDS reduction
+//                                          across the lanes/waves holding the same rows)
+//   phase 2  acc[c] += sum_r A[r,c] w_r   (lane-local; the cross-lane sum for v is deferred to
+//                                          the end of the persistent loop)
+// The next tile's loads are issued before the current tile is processed (two register buffers).
+// Tiles are banded by XCD (work-group g runs on XCD g % 8): each XCD streams one contiguous band
+// of rows, so neighbouring tiles share that XCD's L2.  Each work-group writes one partial vector;
+// a second kernel sums the partials in a fixed order (deterministic results).
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace {
+
+template <int H, int NT, int L, bool RESID, bool VEC>
+__global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+                                                   const double* __restrict__ zs, const double* __restrict__ b,
+                                                   double* __restrict__ partial, double* __restrict__ partial_r2,
+                                                   const int* __restrict__ stop) {
+  static_assert(H >= 2 && (H & (H - 1)) == 0 && H <= 128, "H must be a power of two in [2,128]");
+  constexpr int RP = H / 2;           // row pairs per tile == lanes per column segment
+  constexpr int CPR = NT / RP;        // columns per round
+  constexpr int NW = NT / 64;
+  constexpr int LOG2RP = __builtin_ctz(RP);
+  static_assert(RP <= 64, "row pairs must fit in a wave");
+
+  if (fs_stopped(stop)) return;
+
+  __shared__ double sw[2][NW][H];
+  __shared__ double sred[NW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int rp = tid % RP;
+  const int cb = tid / RP;
+  const int G = gridDim.x, g = blockIdx.x;
+
+  // XCD banding of the row tiles.
+  const int64_t T = (m + H - 1) / H;
+  const int nb = (G >= 8 && (G % 8) == 0) ? 8 : 1;
+  const int band = g % nb, step = G / nb, l0 = g / nb;
+  const int64_t lo = (T * band) / nb, hi = (T * (band + 1)) / nb;
+
+  double zr[L];
+  double acc[L];
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const int c = cb + k * CPR;
+    zr[k] = (c < n) ? zs[c] : 0.0;
+    acc[k] = 0.0;
+  }
+  double r2 = 0.0;
+
+  // Lane byte offset inside a column slot (32-bit, so loads use a scalar base + vector offset);
+  // the host guarantees CPR * lda * 8 + H * 8 < 2^32 on this path.
+  const uint32_t voff = (uint32_t)(((int64_t)cb * lda + 2 * rp) * (int64_t)sizeof(double));
+  auto load = [&](double2 (&a)[L], int64_t t) {
+    const int64_t r0 = t * H + 2 * rp;
+    const bool full = VEC && (t * H + H <= m);
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      const int c = cb + k * CPR;
+      const char* sb = reinterpret_cast<const char*>(A + (int64_t)(k * CPR) * lda + t * H);
+      if (c < n) {
+        if (full) {
+          a[k] = *reinterpret_cast<const double2*>(sb + voff);
+        } else {
+          const double* p = reinterpret_cast<const double*>(sb + voff);
+          a[k].x = (r0 < m) ? p[0] : 0.0;
+          a[k].y = (r0 + 1 < m) ? p[1] : 0.0;
+        }
+      } else {
+        a[k] = make_double2(0.0, 0.0);
+      }
+    }
+  };
+
+  auto process = [&](const double2 (&a)[L], int64_t t, int par) {
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+      p0 = fma(a[k].x, zr[k], p0);
+      p1 = fma(a[k].y, zr[k], p1);
+    }
+    p0 = wave_sum_high<LOG2RP>(p0);
+    p1 = wave_sum_high<LOG2RP>(p1);
+    if (lane < RP) {
+      sw[par][wv][2 * rp] = p0;
+      sw[par][wv][2 * rp + 1] = p1;
+    }
+    __syncthreads();
+    double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      w0 += sw[par][i][2 * rp];
+      w1 += sw[par][i][2 * rp + 1];
+    }
+    const int64_t r0 = t * H + 2 * rp;
+    if (RESID) {
+      w0 = (r0 < m) ? b[r0] - w0 : 0.0;
+      w1 = (r0 + 1 < m) ? b[r0 + 1] - w1 : 0.0;
+      if (cb == 0) r2 = fma(w0, w0, fma(w1, w1, r2));
+    }
+#pragma unroll
+    for (int k = 0; k < L; ++k) acc[k] = fma(a[k].x, w0, fma(a[k].y, w1, acc[k]));
+  };
+
+  double2 bufA[L], bufB[L];
+  int64_t t = lo + l0;
+  if (t < hi) load(bufA, t);
+  while (t < hi) {
+    if (t + step < hi) load(bufB, t + step);
+    process(bufA, t, 0);
+    t += step;
+    if (t >= hi) break;
+    if (t + step < hi) load(bufA, t + step);
+    process(bufB, t, 1);
+    t += step;
+  }
+
+  // v partial: sum the RP lanes of each column segment, then one lane per column writes.
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const double s = wave_sum_low<LOG2RP>(acc[k]);
+    const int c = cb + k * CPR;
+    if (rp == 0 && c < n) partial[(int64_t)g * n + c] = s;
+  }
+  if (RESID) {
+    const double s = block_sum<NT>(r2, sred);
+    if (tid == 0) partial_r2[g] = s;
+  }
+}
+
+// out[c] = scale[c] * sum_g partial[g][c]  (fixed order); optionally r2 = sum_g partial_r2[g].
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int G, int n,
+                                                         const double* __restrict__ scale, double* __restrict__ out,
+                                                         const double* __restrict__ partial_r2, double* __restrict__ r2,
+                                                         const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) {
+    double s = 0.0;
+    for (int gi = 0; gi < G; ++gi) s += partial[(int64_t)gi * n + c];
+    out[c] = scale ? s * scale[c] : s;
+  }
+  if (partial_r2 && blockIdx.x == 0) {
+    __shared__ double sh[4];
+    double v = 0.0;
+    for (int gi = threadIdx.x; gi < G; gi += 256) v += partial_r2[gi];
+    // fixed-order block reduction
+    v = block_sum<256>(v, sh);
+    if (threadIdx.x == 0) *r2 = v;
+  }
+}
+
+// Unfused fallback for very wide A (n > 4096): w = A z (or b - A z) then v = A^T w.
+__global__ __launch_bounds__(256) void k_gemv_n(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+                                                const double* __restrict__ z, const double* __restrict__ b,
+                                                double* __restrict__ w, const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  double s = 0.0;
+  for (int c = 0; c < n; ++c) s = fma(A[(int64_t)c * lda + r], z[c], s);
+  w[r] = b ? b[r] - s : s;
+}
+
+__global__ __launch_bounds__(256) void k_gemv_t(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+                                                const double* __restrict__ w, double* __restrict__ partial, int G,
+                                                const int* __restrict__ stop) {
+  // block (c, gslice): partial[gslice][c] = sum over a row slice of A[r,c] w[r]
+  if (fs_stopped(stop)) return;
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  const int gs = blockIdx.y;
+  const int64_t rows_per = (m + G - 1) / G;
+  const int64_t r0 = gs * rows_per, r1 = (r0 + rows_per < m) ? r0 + rows_per : m;
+  double s = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) s = fma(A[(int64_t)c * lda + r], w[r], s);
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) partial[(int64_t)gs * n + c] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_partials(const double* __restrict__ w, int64_t m, int G,
+                                                        double* __restrict__ partial_r2, const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  __shared__ double sh[4];
+  const int64_t rows_per = (m + G - 1) / G;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per, r1 = (r0 + rows_per < m) ? r0 + rows_per : m;
+  double s = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) s = fma(w[r], w[r], s);
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) partial_r2[blockIdx.x] = s;
+}
+
+template <int H, int NT, int L, bool RESID>
+hipError_t launch_one(const PassArgs& a, int G, bool vec, hipStream_t s) {
+  if (vec)
+    hipLaunchKernelGGL((k_fused_pass<H, NT, L, RESID, true>), dim3(G), dim3(NT), 0, s, a.A, a.lda, a.m, a.n, a.zs,
+                       a.b, a.partial, a.partial_r2, a.stop);
+  else
+    hipLaunchKernelGGL((k_fused_pass<H, NT, L, RESID, false>), dim3(G), dim3(NT), 0, s, a.A, a.lda, a.m, a.n,
+                       a.zs, a.b, a.partial, a.partial_r2, a.stop);
+  return hipGetLastError();
+}
+
+template <int H, int NT, bool RESID>
+hipError_t launch_L(const PassArgs& a, int G, bool vec, hipStream_t s) {
+  constexpr int CPR = NT / (H / 2);
+  const int L = (a.n + CPR - 1) / CPR;
+  if (L <= 1) return launch_one<H, NT, 1, RESID>(a, G, vec, s);
+  if (L <= 2) return launch_one<H, NT, 2, RESID>(a, G, vec, s);
+  if (L <= 4) return launch_one<H, NT, 4, RESID>(a, G, vec, s);
+  if (L <= 8) return launch_one<H, NT, 8, RESID>(a, G, vec, s);
+  if (L <= 12) return launch_one<H, NT, 12, RESID>(a, G, vec, s);
+  return launch_one<H, NT, 16, RESID>(a, G, vec, s);
+}
+
+template <bool RESID>
+hipError_t launch_fused(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
+  const bool vec = ((a.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0);
+  switch (cfg.H) {
+    case 64: return launch_L<64, 512, RESID>(a, cfg.G, vec, s);
+    case 32: return launch_L<32, 512, RESID>(a, cfg.G, vec, s);
+    case 16: return launch_L<16, 512, RESID>(a, cfg.G, vec, s);
+    case 8: return launch_L<8, 512, RESID>(a, cfg.G, vec, s);
+    case 4: return launch_L<4, 512, RESID>(a, cfg.G, vec, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+// Pick the tile height from n: the widest tile whose L (column slots per lane) stays <= 16.
+PassConfig fs_pass_config(int64_t m, int n, int num_cu) {
+  PassConfig c{};
+  if (n <= 64) c.H = 64;
+  else if (n <= 256) c.H = 32;
+  else if (n <= 1024) c.H = 16;
+  else if (n <= 2048) c.H = 8;
+  else if (n <= 4096) c.H = 4;
+  else c.H = 0;  // unfused fallback
+  const int64_t T = c.H ? (m + c.H - 1) / c.H : 0;
+  int G = num_cu;  // one 512-thread work-group per CU (register-bound occupancy)
+  if (c.H && T < G) G = (int)((T + 7) / 8 * 8);
+  if (G < 1) G = 1;
+  c.G = c.H ? G : 512;
+  return c;
+}
+
+hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out, const double* out_scale,
+                          double* r2_out, double* w_scratch, hipStream_t s) {
+  hipError_t e;
+  const bool resid = a.b != nullptr;
+  if (cfg.H) {
+    e = resid ? launch_fused<true>(a, cfg, s) : launch_fused<false>(a, cfg, s);
+    if (e != hipSuccess) return e;
+  } else {
+    // unfused: two reads of A
+    const int gb = (int)((a.m + 255) / 256);
+    hipLaunchKernelGGL(k_gemv_n, dim3(gb), dim3(256), 0, s, a.A, a.lda, a.m, a.n, a.zs, a.b, w_scratch, a.stop);
+    hipLaunchKernelGGL(k_gemv_t, dim3(a.n, cfg.G), dim3(256), 0, s, a.A, a.lda, a.m, a.n, w_scratch, a.partial,
+                       cfg.G, a.stop);
+    if (resid)
+      hipLaunchKernelGGL(k_sumsq_partials, dim3(cfg.G), dim3(256), 0, s, w_scratch, a.m, cfg.G, a.partial_r2, a.stop);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_reduce_partials, dim3((a.n + 255) / 256), dim3(256), 0, s, a.partial, cfg.G, a.n, out_scale,
+                     out, resid ? a.partial_r2 : nullptr, r2_out, a.stop);
+  return hipGetLastError();
+}

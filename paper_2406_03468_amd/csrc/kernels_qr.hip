@@ -1,0 +1,232 @@
+// Householder QR of the sketch Y = S [A b] (d x k, column-major, d >= k).
+//
+// The paper factors the sketch with Householder QR (eq:sketch_qr; Lemma 6.3 assumes Householder).
+// This is a blocked right-looking Householder QR run as ONE cooperative kernel:
+//   * work-group g owns a contiguous block of rows of Y for the whole factorization;
+//   * a panel of NB columns is factored column by column with a single grid-wide reduction per
+//     column: each work-group reduces x^T [panel columns] over its rows (x = the current column
+//     below the diagonal) and the owner of the diagonal row publishes that row; from these
+//     every work-group derives ||x||, the reflector H = I - tau v v^T with v = x + sign(x_0)||x|| e_1,
+//     v^T y = x^T y + sign(x_0)||x|| y_0 for every other panel column, and the next column of the
+//     compact-WY factor T (LAPACK's forward column-wise recurrence) -- redundantly, in the same
+//     fixed order, so all copies agree bit for bit;
+//   * the trailing columns are updated as Y <- Y - V T^T (V^T Y): V^T Y is summed over row blocks
+//     (per-work-group partials, then a column-distributed fixed-order reduction), then each
+//     work-group updates its own rows.
+// R is left in the upper triangle of Y[0:k, 0:k] with a non-negative diagonal (rows of R whose
+// reflector produced a negative diagonal are negated, which changes Q's columns, not Q R).
+#include <hip/hip_cooperative_groups.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace cg = cooperative_groups;
+
+namespace {
+
+constexpr int NB = 32;        // panel width (divides 64)
+constexpr int QR_NT = 256;    // threads per work-group
+constexpr int RBMAX = 256;    // max rows owned by one work-group
+constexpr int LOG2NB = 5;
+constexpr int NRG = QR_NT / NB;   // row groups
+
+__global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64_t ldy, int d, int k, int RB,
+                                                   double* __restrict__ part,   // [2][G][2*NB]
+                                                   double* __restrict__ wpart,  // [G][NB][k]
+                                                   double* __restrict__ wred) { // [NB][k]
+  cg::grid_group grid = cg::this_grid();
+  const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int rs = g * RB;
+  const int re = (rs + RB < d) ? rs + RB : d;
+  const int nr = (re > rs) ? re - rs : 0;
+
+  __shared__ double pan[RBMAX][NB + 1];
+  __shared__ double T[NB][NB + 1];
+  __shared__ double sred[QR_NT / 64][NB];
+  __shared__ double sdots[NB], srow[NB], sw[NB], svtv[NB], srdiag[NB];
+  __shared__ double sW[NRG][NB + 1];
+  __shared__ signed char sneg[RBMAX];
+
+  for (int r = tid; r < RBMAX; r += QR_NT) sneg[r] = 0;
+
+  const int c = tid % NB;
+  const int rg = tid / NB;
+
+  for (int k0 = 0; k0 < k; k0 += NB) {
+    const int nbp = (k - k0 < NB) ? k - k0 : NB;
+    const int k1 = k0 + nbp;
+    for (int q = tid; q < nr * nbp; q += QR_NT) {
+      const int r = q % nr, cc = q / nr;
+      pan[r][cc] = Y[(int64_t)(k0 + cc) * ldy + rs + r];
+    }
+    __syncthreads();
+
+    for (int jj = 0; jj < nbp; ++jj) {
+      const int j = k0 + jj;
+      const int par = j & 1;
+      const int rstart = (j > rs) ? j - rs : 0;
+      // (1) partial x^T P over own rows i >= j, and the owner's copy of row j.
+      double s = 0.0;
+      if (c < nbp)
+        for (int r = rstart + rg; r < nr; r += NRG) s = fma(pan[r][jj], pan[r][c], s);
+      s = wave_sum_high<LOG2NB>(s);
+      if ((tid & 63) < NB) sred[tid >> 6][c] = s;
+      __syncthreads();
+      if (tid < NB) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < QR_NT / 64; ++w) t += sred[w][tid];
+        double* pp = part + ((size_t)par * G + g) * (2 * NB);
+        pp[tid] = t;
+        pp[NB + tid] = (j >= rs && j < re && tid < nbp) ? pan[j - rs][tid] : 0.0;
+      }
+      grid.sync();
+      // (2) every work-group reduces all partials in the same order.
+      if (tid < 2 * NB) {
+        double t = 0.0;
+        for (int gg = 0; gg < G; ++gg) t += part[((size_t)par * G + gg) * (2 * NB) + tid];
+        if (tid < NB) sdots[tid] = t;
+        else srow[tid - NB] = t;
+      }
+      __syncthreads();
+      // (3) reflector scalars.
+      const double alpha = sqrt(sdots[jj]);
+      const double x0 = srow[jj];
+      const double sg = (x0 >= 0.0) ? 1.0 : -1.0;
+      const double vhead = x0 + sg * alpha;
+      const double tau = (alpha > 0.0) ? 1.0 / (alpha * (alpha + fabs(x0))) : 0.0;  // 2 / (v^T v)
+      if (tid < nbp) {
+        const double vty = sdots[tid] + sg * alpha * srow[tid];
+        sw[tid] = (tid > jj) ? tau * vty : 0.0;
+        svtv[tid] = (tid < jj) ? vty : 0.0;
+      }
+      if (tid == 0) srdiag[jj] = -sg * alpha;
+      __syncthreads();
+      if (tid <= jj) {  // column jj of T
+        if (tid == jj) {
+          T[jj][jj] = tau;
+        } else {
+          double t = 0.0;
+          for (int c2 = tid; c2 < jj; ++c2) t = fma(T[tid][c2], svtv[c2], t);
+          T[tid][jj] = -tau * t;
+        }
+      }
+      // (4) apply the reflector to the rest of the panel (own rows i >= j).
+      if (c > jj && c < nbp) {
+        const double wc = sw[c];
+        for (int r = rstart + rg; r < nr; r += NRG) {
+          const double v = (rs + r == j) ? vhead : pan[r][jj];
+          pan[r][c] = fma(-v, wc, pan[r][c]);
+        }
+      }
+      __syncthreads();
+      if (tid == 0 && j >= rs && j < re) {
+        pan[j - rs][jj] = vhead;
+        sneg[j - rs] = (sg > 0.0) ? 1 : 0;  // R_jj = -sg * alpha < 0 when sg > 0
+      }
+      __syncthreads();
+    }
+    // write the panel rows back (V below the diagonal, v heads on the diagonal for now)
+    for (int q = tid; q < nr * nbp; q += QR_NT) {
+      const int r = q % nr, cc = q / nr;
+      Y[(int64_t)(k0 + cc) * ldy + rs + r] = pan[r][cc];
+    }
+
+    if (k1 < k) {
+      const int ntr = k - k1;
+      const int r_lo = (k0 > rs) ? k0 - rs : 0;
+      // (T1) partial W_g = V_own^T Y_own[:, k1:k]
+      for (int cc = tid; cc < ntr; cc += QR_NT) {
+        double acc[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) acc[q] = 0.0;
+        const double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
+        for (int r = r_lo; r < nr; ++r) {
+          const double y = ycol[r];
+          const int lim = rs + r - k0;  // V[r][q] nonzero for q <= lim
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            const double v = (q <= lim && q < nbp) ? pan[r][q] : 0.0;
+            acc[q] = fma(v, y, acc[q]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) wpart[((size_t)g * NB + q) * k + cc] = acc[q];
+      }
+      grid.sync();
+      // (T2) W = sum_g W_g (fixed order), W' = T^T W, for a slice of columns per work-group.
+      for (int base = g * NRG; base < ntr; base += G * NRG) {
+        const int cc = base + rg;
+        double wsum = 0.0;
+        if (cc < ntr && c < nbp)
+          for (int gg = 0; gg < G; ++gg) wsum += wpart[((size_t)gg * NB + c) * k + cc];
+        sW[rg][c] = wsum;
+        __syncthreads();
+        double wp = 0.0;
+        if (c < nbp)
+          for (int c2 = 0; c2 <= c; ++c2) wp = fma(T[c2][c], sW[rg][c2], wp);
+        if (cc < ntr && c < nbp) wred[(size_t)c * k + cc] = wp;
+        __syncthreads();
+      }
+      grid.sync();
+      // (T3) own rows: Y[:, k1:k] -= V W'
+      for (int cc = tid; cc < ntr; cc += QR_NT) {
+        double wv[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) wv[q] = (q < nbp) ? wred[(size_t)q * k + cc] : 0.0;
+        double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
+        for (int r = r_lo; r < nr; ++r) {
+          const int lim = rs + r - k0;
+          double s2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < NB; ++q) {
+            const double v = (q <= lim) ? pan[r][q] : 0.0;
+            s2 = fma(v, wv[q], s2);
+          }
+          ycol[r] -= s2;
+        }
+      }
+    }
+    // diagonal of R for this panel's rows owned here
+    for (int jj = tid; jj < nbp; jj += QR_NT) {
+      const int j = k0 + jj;
+      if (j >= rs && j < re) Y[(int64_t)j * ldy + j] = srdiag[jj];
+    }
+    __syncthreads();
+  }
+  // non-negative diagonal: negate rows of R with a negative diagonal (own rows j < k)
+  for (int r = 0; r < nr; ++r) {
+    const int j = rs + r;
+    if (j >= k) break;
+    if (sneg[r])
+      for (int cc = j + tid; cc < k; cc += QR_NT) Y[(int64_t)cc * ldy + j] = -Y[(int64_t)cc * ldy + j];
+  }
+}
+
+void qr_grid(int d, int num_cu, int* G, int* RB) {
+  int g = (d + 63) / 64;
+  if (g > num_cu) g = num_cu;
+  if (g < 1) g = 1;
+  int rb = (d + g - 1) / g;
+  *G = g;
+  *RB = rb;
+}
+
+}  // namespace
+
+size_t fs_qr_work_bytes(int d, int k, int num_cu) {
+  int G, RB;
+  qr_grid(d, num_cu, &G, &RB);
+  return sizeof(double) * ((size_t)2 * G * 2 * NB + (size_t)G * NB * k + (size_t)NB * k) + 256;
+}
+
+hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int num_cu, hipStream_t s) {
+  int G, RB;
+  qr_grid(d, num_cu, &G, &RB);
+  if (RB > RBMAX) return hipErrorInvalidValue;
+  double* part = (double*)work;
+  double* wpart = part + (size_t)2 * G * 2 * NB;
+  double* wred = wpart + (size_t)G * NB * k;
+  void* args[] = {&Y, &ldy, &d, &k, &RB, &part, &wpart, &wred};
+  return hipLaunchCooperativeKernel((const void*)k_qr_coop, dim3(G), dim3(QR_NT), args, 0, s);
+}

@@ -1,0 +1,428 @@
+// n-vector work of the refinement loop: triangular solves with R, products with V Sigma^{-1},
+// the heavy-ball and CG updates, the stopping rules and the sketched Karlson-Walden estimate.
+// Every reduction is a fixed-order tree (deterministic).  Kernels of an inner iteration take the
+// device stop flag and return at once when it is set.
+#include "common.hpp"
+#include "internal.hpp"
+#include "state.hpp"
+
+namespace {
+
+constexpr int VNT = 1024;
+constexpr double U_ROUND = 2.220446049250313e-16;
+
+// ---------------------------------------------------------------- triangular solves (one work-group)
+// Back substitution R x = y (upper) or forward substitution R^T x = y, blocked by 64: the diagonal
+// block is solved by one wave row by row; the off-diagonal blocks are applied by all threads.
+// x may alias y.  x_out = xscale .* x (optional); y is read as yscale .* y (optional).
+__global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int64_t ldr, int n, int transpose,
+                                              const double* y, double* x, const double* __restrict__ yscale,
+                                              const double* __restrict__ xscale, const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  extern __shared__ double xs[];  // n
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int i = tid; i < n; i += VNT) xs[i] = yscale ? y[i] * yscale[i] : y[i];
+  __syncthreads();
+  const int nblk = (n + 63) / 64;
+  if (!transpose) {
+    for (int kb = nblk - 1; kb >= 0; --kb) {
+      const int b0 = kb * 64, b1 = min(n, b0 + 64);
+      if (wv == 0) {
+        // rows b0..b1-1 held by lanes; solve bottom-up
+        double xi = (b0 + lane < b1) ? xs[b0 + lane] : 0.0;
+        for (int i = b1 - 1; i >= b0; --i) {
+          const double piv = R[(int64_t)i * ldr + i];
+          const double xv = __shfl(xi, i - b0, 64) / piv;
+          if (lane == i - b0) xi = xv;
+          if (b0 + lane < i) xi = fma(-R[(int64_t)i * ldr + b0 + lane], xv, xi);
+        }
+        if (b0 + lane < b1) xs[b0 + lane] = xi;
+      }
+      __syncthreads();
+      // x[0:b0] -= R[0:b0, b0:b1] x[b0:b1]
+      for (int i = tid; i < b0; i += VNT) {
+        double s = 0.0;
+        for (int j = b0; j < b1; ++j) s = fma(R[(int64_t)j * ldr + i], xs[j], s);
+        xs[i] -= s;
+      }
+      __syncthreads();
+    }
+  } else {
+    for (int kb = 0; kb < nblk; ++kb) {
+      const int b0 = kb * 64, b1 = min(n, b0 + 64);
+      // x[b0:b1] -= R[0:b0, b0:b1]^T x[0:b0]: 16 threads per output
+      {
+        const int o = tid >> 4, sub = tid & 15;
+        const int i = b0 + o;
+        double s = 0.0;
+        if (i < b1)
+          for (int j = sub; j < b0; j += 16) s = fma(R[(int64_t)i * ldr + j], xs[j], s);
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 64);
+        __syncthreads();
+        if (i < b1 && sub == 0) xs[i] -= s;
+        __syncthreads();
+      }
+      if (wv == 0) {
+        double xi = (b0 + lane < b1) ? xs[b0 + lane] : 0.0;
+        for (int i = b0; i < b1; ++i) {
+          const double piv = R[(int64_t)i * ldr + i];
+          const double xv = __shfl(xi, i - b0, 64) / piv;
+          if (lane == i - b0) xi = xv;
+          // rows j > i of R^T column i: R[i, j]
+          if (b0 + lane > i && b0 + lane < b1) xi = fma(-R[(int64_t)(b0 + lane) * ldr + i], xv, xi);
+        }
+        if (b0 + lane < b1) xs[b0 + lane] = xi;
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = tid; i < n; i += VNT) x[i] = xscale ? xs[i] * xscale[i] : xs[i];
+}
+
+// ---------------------------------------------------------------- dense products with V (n x k, ld)
+// out[i] = oscale[i] * sum_j V[i, j] (y[j] * yscale[j])  -- partial over column slices
+__global__ __launch_bounds__(256) void k_gemv_v_part(const double* __restrict__ V, int64_t ldv, int n, int k,
+                                                     const double* __restrict__ y, const double* __restrict__ ydiv,
+                                                     double* __restrict__ part, int cs, const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int slice = blockIdx.y;
+  const int j0 = slice * cs, j1 = min(k, j0 + cs);
+  if (i >= n) return;
+  double s = 0.0;
+  for (int j = j0; j < j1; ++j) s = fma(V[(int64_t)j * ldv + i], ydiv ? y[j] / ydiv[j] : y[j], s);
+  part[(int64_t)slice * n + i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int nslices, int n,
+                                                    const double* __restrict__ oscale, const double* __restrict__ addv,
+                                                    double* __restrict__ out, const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < nslices; ++q) s += part[(int64_t)q * n + i];
+  if (addv) s += addv[i];
+  out[i] = oscale ? s * oscale[i] : s;
+}
+
+// out[j] = (sum_i V[i, j] v[i]) / div[j]  for j < k: one work-group per column
+__global__ __launch_bounds__(256) void k_gemv_vt(const double* __restrict__ V, int64_t ldv, int n, int k,
+                                                 const double* __restrict__ v, const double* __restrict__ div,
+                                                 double* __restrict__ out, const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s = fma(V[(int64_t)j * ldv + i], v[i], s);
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) out[j] = div ? s / div[j] : s;
+}
+
+// ---------------------------------------------------------------- small vector kernels (one work-group)
+__device__ __forceinline__ double bsum(double v, double* sh) { return block_sum<VNT>(v, sh); }
+
+// Alg 1/5 heavy-ball update with Alg 4's first-step rule:
+//   Delta = alpha (c - u) + beta (dy - dy_old); dy_old <- dy; dy <- dy + Delta;
+//   if first_step and ||Delta|| <= thr_first: stop.
+__global__ __launch_bounds__(VNT) void k_polyak(int n, const double* __restrict__ c, const double* __restrict__ u,
+                                                double* __restrict__ dy, double* __restrict__ dy_old,
+                                                DevState* __restrict__ st, int first_step) {
+  if (st->stop) return;
+  __shared__ double sh[VNT / 64];
+  const double al = st->alpha, be = st->beta;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double y = dy[i];
+    const double D = al * (c[i] - u[i]) + be * (y - dy_old[i]);
+    dy_old[i] = y;
+    dy[i] = y + D;
+    s = fma(D, D, s);
+  }
+  s = bsum(s, sh);
+  if (threadIdx.x == 0) {
+    st->dnorm2 = s;
+    st->iters += 1;
+    if (first_step && sqrt(s) <= st->thr_first) {
+      st->stop = 1;
+      st->converged = 1;
+    }
+    if (st->iters >= st->max_inner) st->stop = 1;
+  }
+}
+
+// CG on M dy = c (SPIR): q = M p given; a = rho / p^T q; Delta = a p; dy += Delta; res -= a q;
+// rho' = res^T res; p = res + (rho'/rho) p.
+__global__ __launch_bounds__(VNT) void k_cg(int n, double* __restrict__ p, const double* __restrict__ q,
+                                            double* __restrict__ res, double* __restrict__ dy,
+                                            DevState* __restrict__ st, int first_step) {
+  if (st->stop) return;
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) s = fma(p[i], q[i], s);
+  const double pq = bsum(s, sh);
+  const double rho = st->rho_cg;
+  if (!(pq > 0.0) || rho == 0.0) {
+    if (threadIdx.x == 0) {
+      st->stop = 1;
+      if (rho == 0.0) st->converged = 1;
+    }
+    return;
+  }
+  const double a = rho / pq;
+  double s2 = 0.0, sd = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double D = a * p[i];
+    dy[i] += D;
+    const double r = res[i] - a * q[i];
+    res[i] = r;
+    s2 = fma(r, r, s2);
+    sd = fma(D, D, sd);
+  }
+  const double rho2 = bsum(s2, sh);
+  const double dn2 = bsum(sd, sh);
+  const double bet = rho2 / rho;
+  for (int i = threadIdx.x; i < n; i += VNT) p[i] = res[i] + bet * p[i];
+  if (threadIdx.x == 0) {
+    st->rho_cg = rho2;
+    st->dnorm2 = dn2;
+    st->iters += 1;
+    if (first_step && sqrt(dn2) <= st->thr_first) {
+      st->stop = 1;
+      st->converged = 1;
+    }
+    if (st->iters >= st->max_inner) st->stop = 1;
+  }
+}
+
+// Start of a refinement step: dy = dy_old = c (FOSSILS) or dy = 0, res = p = c (SPIR); rho = c^T c.
+__global__ __launch_bounds__(VNT) void k_step_init(int n, const double* __restrict__ c, double* __restrict__ a,
+                                                   double* __restrict__ b, double* __restrict__ dy, int spir,
+                                                   DevState* __restrict__ st) {
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double v = c[i];
+    a[i] = v;
+    b[i] = v;
+    if (spir) dy[i] = 0.0;
+    s = fma(v, v, s);
+  }
+  s = bsum(s, sh);
+  if (threadIdx.x == 0) {
+    st->rho_cg = s;
+    st->cnorm2 = s;
+    st->stop = 0;
+    st->iters = 0;
+    st->converged = 0;
+  }
+}
+
+// x_hat = x + z (z = P dy already formed); ||x_hat||^2 into the state.
+__global__ __launch_bounds__(VNT) void k_add_norm(int n, const double* __restrict__ x, const double* __restrict__ z,
+                                                  double* __restrict__ out, double* __restrict__ norm2_out,
+                                                  const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double v = z ? x[i] + z[i] : x[i];
+    out[i] = v;
+    s = fma(v, v, s);
+  }
+  s = bsum(s, sh);
+  if (threadIdx.x == 0 && norm2_out) *norm2_out = s;
+}
+
+// out = a .* b (elementwise), or a copy when b is null
+__global__ void k_mul(int n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out,
+                      const int* __restrict__ stop) {
+  if (fs_stopped(stop)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = b ? a[i] * b[i] : a[i];
+}
+
+// Column scaling: dinv_j = 1/||a_j|| (1 for zero columns); ||A_s||_F^2 = sum_j ||a_j||^2 dinv_j^2.
+__global__ __launch_bounds__(VNT) void k_scaling(int n, const double* __restrict__ colnorm2, int use_scaling,
+                                                 double* __restrict__ dinv, DevState* __restrict__ st) {
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double c2 = colnorm2[i];
+    const double di = (use_scaling && c2 > 0.0) ? 1.0 / sqrt(c2) : 1.0;
+    dinv[i] = di;
+    s = fma(c2 * di, di, s);
+  }
+  s = bsum(s, sh);
+  if (threadIdx.x == 0) st->fro2 = s;
+}
+
+// normest, condest from sigma (descending); rank for truncation (Alg 4).
+__global__ void k_sigma_stats(int n, const double* __restrict__ sigma, double tau_factor, DevState* __restrict__ st) {
+  if (threadIdx.x == 0) {
+    const double s1 = sigma[0], sn = sigma[n - 1];
+    st->normest = s1;
+    st->condest = (sn > 0.0) ? s1 / sn : INFINITY;
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += (sigma[i] > tau_factor * U_ROUND * s1) ? 1 : 0;
+    st->rank_trunc = r;
+  }
+}
+
+// After the residual pass at x_0: keep ||x_0||, ||r_0|| and the first-step threshold (Alg 4).
+__global__ __launch_bounds__(VNT) void k_first_threshold(int n, const double* __restrict__ x0, double gamma,
+                                                         double rho, DevState* __restrict__ st) {
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) s = fma(x0[i], x0[i], s);
+  s = bsum(s, sh);
+  if (threadIdx.x == 0) {
+    st->x0norm = sqrt(s);
+    st->r0norm = sqrt(st->r2);
+    st->thr_first = (gamma * st->normest * st->x0norm + rho * st->condest * st->r0norm) * U_ROUND;
+    st->fro_u = sqrt(st->fro2) * U_ROUND;
+  }
+}
+
+// Sketched Karlson-Walden estimate (eq:sketched-kw, via the SVD of the sketch) and the
+// second-step rule BE_sk < ||A||_F u.  w = V^T g is given (g = A_s^T r_hat); x2 = ||x_hat||^2,
+// r2 = ||r_hat||^2 in the state; theta = ||A_s||_F / ||b||.
+__global__ __launch_bounds__(VNT) void k_kw(int n, const double* __restrict__ w, const double* __restrict__ sigma,
+                                            DevState* __restrict__ st) {
+  if (st->stop) return;
+  __shared__ double sh[VNT / 64];
+  const double th2 = st->theta2;
+  const double x2 = st->x2, r2 = st->r2;
+  const double lam = th2 * r2 / (1.0 + th2 * x2);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double si = sigma[i];
+    s += w[i] * w[i] / (si * si + lam);
+  }
+  s = bsum(s, sh);
+  if (threadIdx.x == 0) {
+    const double be = sqrt(th2 / (1.0 + th2 * x2)) * sqrt(s);
+    st->be_sk = be;
+    st->kw_evals += 1;
+    if (be < st->fro_u) {
+      st->stop = 1;
+      st->converged = 1;
+    }
+  }
+}
+
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_set_double(double* p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_state_init(DevState* st, double alpha, double beta, int max_inner) {
+  if (threadIdx.x == 0) {
+    DevState z{};
+    z.alpha = alpha;
+    z.beta = beta;
+    z.max_inner = max_inner;
+    *st = z;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
+                          const double* yscale, const double* xscale, const int* stop, hipStream_t s) {
+  const size_t sh = (size_t)n * sizeof(double);
+  if (sh > 150 * 1024) return hipErrorInvalidValue;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_trsv, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_trsv, dim3(1), dim3(VNT), sh, s, R, ldr, n, transpose ? 1 : 0, y, x, yscale, xscale, stop);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_gemv_v(const double* V, int64_t ldv, int n, int k, const double* y, const double* ydiv,
+                         const double* oscale, const double* addv, double* out, double* part, const int* stop,
+                         hipStream_t s) {
+  const int cs = 64;
+  const int ns = (k + cs - 1) / cs;
+  hipLaunchKernelGGL(k_gemv_v_part, dim3((n + 255) / 256, ns), dim3(256), 0, s, V, ldv, n, k, y, ydiv, part, cs,
+                     stop);
+  hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, s, part, ns, n, oscale, addv, out, stop);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_gemv_vt(const double* V, int64_t ldv, int n, int k, const double* v, const double* div, double* out,
+                          const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_gemv_vt, dim3(k), dim3(256), 0, s, V, ldv, n, k, v, div, out, stop);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, double* dy_old, DevState* st,
+                         bool first_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_polyak, dim3(1), dim3(VNT), 0, s, n, c, u, dy, dy_old, st, first_step ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_cg(int n, double* p, const double* q, double* res, double* dy, DevState* st, bool first_step,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_cg, dim3(1), dim3(VNT), 0, s, n, p, q, res, dy, st, first_step ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_step_init(int n, const double* c, double* a, double* b, double* dy, bool spir, DevState* st,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_step_init, dim3(1), dim3(VNT), 0, s, n, c, a, b, dy, spir ? 1 : 0, st);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_add_norm(int n, const double* x, const double* z, double* out, double* norm2, const int* stop,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_add_norm, dim3(1), dim3(VNT), 0, s, n, x, z, out, norm2, stop);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_mul(int n, const double* a, const double* b, double* out, const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_mul, dim3((n + 255) / 256), dim3(256), 0, s, n, a, b, out, stop);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_scaling(int n, const double* colnorm2, bool use_scaling, double* dinv, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_scaling, dim3(1), dim3(VNT), 0, s, n, colnorm2, use_scaling ? 1 : 0, dinv, st);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_sigma_stats(int n, const double* sigma, double tau_factor, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_sigma_stats, dim3(1), dim3(64), 0, s, n, sigma, tau_factor, st);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_first_threshold(int n, const double* x0, double gamma, double rho, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_first_threshold, dim3(1), dim3(VNT), 0, s, n, x0, gamma, rho, st);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_kw(int n, const double* w, const double* sigma, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_kw, dim3(1), dim3(VNT), 0, s, n, w, sigma, st);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_set_double(double* p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_state_init(DevState* st, double alpha, double beta, int max_inner, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, alpha, beta, max_inner);
+  return hipGetLastError();
+}

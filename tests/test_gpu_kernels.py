@@ -1,0 +1,205 @@
+"""GPU parity of each hot-path step against the CPU oracle, through the C ABI."""
+
+import numpy as np
+import pytest
+
+from gpu_util import dev_colmajor, dev_vec, empty_colmajor, host
+from oracle import householder as hh
+from oracle import philox
+from oracle import sketch as osk
+
+pytestmark = pytest.mark.gpu
+U = 2.0**-52
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_03468_amd import binding
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+# ---------------------------------------------------------------- sketch indices (bit exact)
+@pytest.mark.parametrize("m,d,zeta,seed", [(100003, 600, 8, 12345), (50001, 12000, 8, 7), (3001, 40000, 8, 99),
+                                           (20000, 37, 5, 2**40 + 3), (4096, 300, 64, 1), (777, 8, 8, 5),
+                                           (1000, 1, 1, 0)])
+def test_sketch_indices_bit_exact(ctx, m, d, zeta, seed):
+    from paper_2406_03468_amd import binding
+    sk = binding.sketch_create(ctx, m, d, zeta, seed)
+    rows, signs = binding.sketch_indices(sk, 0, m)
+    r0, s0 = philox.sparse_sign_indices(m, d, zeta, seed)
+    assert np.array_equal(rows, r0)
+    assert np.array_equal(signs, s0)
+    # a window in the middle
+    rw, sw = binding.sketch_indices(sk, m // 3, 17)
+    assert np.array_equal(rw, r0[m // 3: m // 3 + 17])
+    sk.close()
+
+
+def test_sketch_indices_full_size_bit_exact(ctx):
+    """All m*zeta = 8e6 positions and signs at m = 1e6, d = 12000."""
+    from paper_2406_03468_amd import binding
+    m, d, zeta, seed = 1_000_000, 12000, 8, 12345
+    sk = binding.sketch_create(ctx, m, d, zeta, seed)
+    rows, signs = binding.sketch_indices(sk, 0, m)
+    r0, s0 = philox.sparse_sign_indices(m, d, zeta, seed)
+    assert np.array_equal(rows, r0) and np.array_equal(signs, s0)
+    sk.close()
+
+
+# ---------------------------------------------------------------- sketch apply
+@pytest.mark.parametrize("m,n,d,scale", [(20011, 37, 450, False), (20011, 37, 450, True), (30001, 300, 3600, True),
+                                         (9001, 5, 24000, True), (5000, 1, 12, False)])
+def test_sketch_apply_matches_oracle(ctx, m, n, d, scale):
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n)) * rng.uniform(0.1, 10, size=n)
+    b = rng.standard_normal(m)
+    sk = binding.sketch_create(ctx, m, d, 8, 4242)
+    Ad, bd = dev_colmajor(A, ld=m + 3), dev_vec(b)
+    Y = empty_colmajor(d, n + 1, ld=d + 1)
+    cn = dev_vec(np.zeros(n))
+    binding.sketch_apply(sk, Ad, bd, Y, cn, scale_columns=scale)
+    norms = np.linalg.norm(A, axis=0)
+    As = A / norms if scale else A
+    Yr = osk.sketch_Ab(As, b, d, 8, 4242)
+    Yg = host(Y)
+    scale_ref = np.abs(osk.sketch(np.abs(np.column_stack([As, b])), d, 8, 4242))  # sum of |terms|
+    assert np.all(np.abs(Yg - Yr) <= 64 * U * scale_ref + 1e-300)
+    assert np.allclose(host(cn), norms**2, rtol=1e-13, atol=0)
+    sk.close()
+
+
+# ---------------------------------------------------------------- QR of the sketch
+@pytest.mark.parametrize("d,k", [(600, 51), (3600, 301), (1000, 33), (64, 64), (130, 1)])
+def test_qr_matches_householder_oracle(ctx, d, k):
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(d * 7 + k)
+    Y0 = rng.standard_normal((d, k))
+    Y = dev_colmajor(Y0, ld=d + 5)
+    binding.fs_sketch_qr(ctx, Y)
+    Rg = np.triu(host(Y)[:k, :k])
+    _, Rr = hh.householder_qr(Y0)
+    assert np.all(np.diag(Rg) >= 0)
+    nrm = np.linalg.norm(Y0)
+    assert np.max(np.abs(Rg - Rr)) <= 200 * U * nrm * np.linalg.cond(Y0)
+
+
+@pytest.mark.parametrize("d,k,kappa", [(600, 51, 1e10), (12000, 1001, 1e12)])
+def test_qr_backward_property_ill_conditioned(ctx, d, k, kappa):
+    """R^T R = Y^T Y up to O(u ||Y||^2) for any conditioning (Householder is backward stable)."""
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(1)
+    Q1, _ = np.linalg.qr(rng.standard_normal((d, k)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    Y0 = (Q1 * 10.0 ** -np.linspace(0, np.log10(kappa), k)) @ Q2.T
+    Y = dev_colmajor(Y0)
+    binding.fs_sketch_qr(ctx, Y)
+    Rg = np.triu(host(Y)[:k, :k])
+    err = np.linalg.norm(Rg.T @ Rg - Y0.T @ Y0) / np.linalg.norm(Y0) ** 2
+    assert err <= 50 * np.sqrt(d) * U
+
+
+# ---------------------------------------------------------------- SVD of R
+@pytest.mark.parametrize("n,kappa", [(50, 1e10), (301, 1e12), (7, 1.0)])
+def test_svd_of_triangular(ctx, n, kappa):
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(n)
+    Q1, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = 10.0 ** -np.linspace(0, np.log10(kappa), n)
+    _, R = hh.householder_qr((Q1 * s) @ Q2.T)
+    Rd = dev_colmajor(R)
+    sig = dev_vec(np.zeros(n))
+    V = empty_colmajor(n, n)
+    sweeps = binding.fs_svd_triangular(ctx, Rd, sig, V)
+    sg, Vg = host(sig), host(V)
+    sr = np.linalg.svd(R, compute_uv=False)
+    assert np.all(np.diff(sg) <= 0)
+    assert np.all(np.abs(sg - sr) <= 1e-13 * sr[0] + 1e-9 * sr)
+    assert np.linalg.norm(Vg.T @ Vg - np.eye(n)) <= 1e-12 * n
+    assert np.linalg.norm(R.T @ R - (Vg * sg**2) @ Vg.T) <= 1e-13 * n * sr[0] ** 2
+    assert 1 <= sweeps <= 40
+
+
+# ---------------------------------------------------------------- fused passes
+PASS_SHAPES = [(10007, 1), (10007, 7), (10007, 50), (10007, 64), (10007, 65), (10007, 300), (20011, 1000),
+               (4099, 1025), (3001, 2100), (2001, 4500), (64, 16)]
+
+
+def _pass_bound(A, z):
+    return (A.shape[0] + A.shape[1]) * U * (np.abs(A).T @ (np.abs(A) @ np.abs(z))) * 4
+
+
+@pytest.mark.parametrize("m,n", PASS_SHAPES)
+def test_normal_pass_matches_oracle(ctx, m, n):
+    from oracle.solvers import normal_pass
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(m + 3 * n)
+    A = rng.standard_normal((m, n))
+    z = rng.standard_normal(n)
+    v = dev_vec(np.zeros(n))
+    binding.fs_normal_pass(ctx, dev_colmajor(A), dev_vec(z), v)
+    assert np.all(np.abs(host(v) - normal_pass(A, z)) <= _pass_bound(A, z))
+
+
+@pytest.mark.parametrize("m,n,ld", [(10007, 50, 10008), (10007, 50, 10009), (999, 33, 2000)])
+def test_normal_pass_leading_dimension(ctx, m, n, ld):
+    from oracle.solvers import normal_pass
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(ld)
+    A = rng.standard_normal((m, n))
+    z = rng.standard_normal(n)
+    v = dev_vec(np.zeros(n))
+    binding.fs_normal_pass(ctx, dev_colmajor(A, ld=ld), dev_vec(z), v)
+    assert np.all(np.abs(host(v) - normal_pass(A, z)) <= _pass_bound(A, z))
+
+
+@pytest.mark.parametrize("m,n", [(10007, 50), (20011, 1000), (5, 3)])
+def test_residual_pass_matches_oracle(ctx, m, n):
+    from oracle.solvers import residual_pass
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    x = rng.standard_normal(n)
+    b = A @ x + 1e-3 * rng.standard_normal(m)
+    g = dev_vec(np.zeros(n))
+    r2 = binding.fs_residual_pass(ctx, dev_colmajor(A), dev_vec(b), dev_vec(x), g)
+    gr, r2r = residual_pass(A, b, x)
+    bound = (m + n) * U * (np.abs(A).T @ (np.abs(b) + np.abs(A) @ np.abs(x))) * 4
+    assert np.all(np.abs(host(g) - gr) <= bound)
+    assert abs(r2 - r2r) <= 1e-10 * r2r + 1e-12 * np.linalg.norm(b) ** 2
+
+
+def test_normal_pass_full_size(ctx):
+    """The launch configuration of the 1e6 x 1000 solve, against numpy on the host."""
+    import torch
+    from paper_2406_03468_amd import binding
+    m, n = 1_000_000, 1000
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    At = torch.randn((n, m), generator=gen, dtype=torch.float64, device="cuda")
+    A = At.t()
+    z = torch.randn((n,), generator=gen, dtype=torch.float64, device="cuda")
+    v = torch.zeros(n, dtype=torch.float64, device="cuda")
+    binding.fs_normal_pass(ctx, A, z, v)
+    Ah = host(At).T
+    zh = host(z)
+    ref = Ah.T @ (Ah @ zh)
+    bound = 4 * (m + n) * U * (np.abs(Ah).T @ (np.abs(Ah) @ np.abs(zh)))
+    assert np.all(np.abs(host(v) - ref) <= bound)
+
+
+# ---------------------------------------------------------------- triangular solves
+@pytest.mark.parametrize("n", [1, 50, 64, 65, 300, 1000])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_trsv_matches_substitution(ctx, n, transpose):
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(n)
+    R = np.triu(rng.standard_normal((n, n))) + 4 * np.sqrt(n) * np.eye(n)
+    y = rng.standard_normal(n)
+    x = dev_vec(np.zeros(n))
+    binding.fs_trsv(ctx, dev_colmajor(R, ld=n + 2), dev_vec(y), x, transpose=transpose)
+    ref = hh.forward_substitution_transposed(R, y) if transpose else hh.back_substitution(R, y)
+    assert np.allclose(host(x), ref, rtol=1e-12, atol=1e-14)
