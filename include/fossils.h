@@ -43,7 +43,7 @@ typedef enum fs_status {
   FS_ERR_NOMEM = -3,           /* device allocation failed */
   FS_ERR_DEVICE = -4,          /* a HIP call failed (see fs_last_error_detail) */
   FS_ERR_NONFINITE = -5,       /* A or b holds NaN or Inf */
-  FS_ERR_TOO_LARGE = -6,       /* size beyond what this build supports */
+  FS_ERR_TOO_LARGE = -6,       /* size beyond what this build supports (n > 15000, d > 65536) */
   FS_ERR_UNKNOWN_TICKET = -7,
   FS_ERR_UNSUPPORTED = -8
 } fs_status;
@@ -155,8 +155,15 @@ fs_status fs_normal_pass(fs_context ctx, int64_t m, int32_t n, const double* A, 
 fs_status fs_residual_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                            const double* x, double* g, double* rnorm2_host);
 
+/* Measurement helper: run fs_normal_pass `repeats` times back to back on the context stream,
+ * bracketed by HIP events; *ms_per_pass_host = average time of one pass (fused kernel + its
+ * fixed-order partial reduction), *ms_kernel_host (may be NULL) = average of the fused kernel
+ * alone.  v receives A^T (A z). */
+fs_status fs_time_normal_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z,
+                              double* v, int32_t repeats, double* ms_per_pass_host, double* ms_kernel_host);
+
 /* x = R^{-1} y (transpose = 0, back substitution) or x = R^{-T} y (transpose = 1, forward
- * substitution) for upper-triangular R (ldr >= n); x may equal y.  n <= 16384. */
+ * substitution) for upper-triangular R (ldr >= n); x may equal y.  n <= 15000. */
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
                   double* x);
 

@@ -97,6 +97,16 @@ def residual_pass(A, b, x):
     return A.T @ r, float(r @ r)
 
 
+def polyak(apply_M, c, alpha, beta, q):
+    """Algorithm 5: dy_(1) = dy_(0) = c, then q - 1 heavy-ball updates
+    dy_(j+1) = dy_(j) + alpha (c - M dy_(j)) + beta (dy_(j) - dy_(j-1))."""
+    dy = c.copy()
+    dy_old = c.copy()
+    for _ in range(1, q):
+        dy, dy_old = dy + alpha * (c - apply_M(dy)) + beta * (dy - dy_old), dy
+    return dy
+
+
 def polyak_coefficients(eta):
     """eq:optimal-coeffs: alpha = (1 - eta^2)^2, beta = eta^2."""
     beta = eta * eta
@@ -226,12 +236,8 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
         it = 0
         converged = False
         if method == "fossils" and opts.fixed_q != 0:
-            # Algorithm 5: dy_(1) = dy_(0) = c, then q - 1 heavy-ball updates.
-            dy = c.copy()
-            dy_old = c.copy()
-            for _ in range(1, q):
-                dy, dy_old = dy + alpha * (c - apply_M(dy)) + beta * (dy - dy_old), dy
-                it += 1
+            dy = polyak(apply_M, c, alpha, beta, q)               # Algorithm 5
+            it = q - 1
             converged = True
         elif method == "fossils":
             dy = c.copy()

@@ -10,8 +10,10 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Optional
 
+_is_finalizing = sys.is_finalizing
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libfossils.so")
 
@@ -87,6 +89,8 @@ _SIGS = [
     ("fs_residual_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_vp,
                                    ctypes.POINTER(c_double)]),
     ("fs_trsv", c_int32, [c_vp, c_int32, c_vp, c_int64, c_int32, c_vp, c_vp]),
+    ("fs_time_normal_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_int32,
+                                      ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
 ]
 
 
@@ -160,6 +164,9 @@ class Context:
             self.h = None
 
     def __del__(self):
+        # At interpreter shutdown the HIP runtime may already be gone: leave the memory to the OS.
+        if _is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -205,6 +212,8 @@ class Sketch:
             self.h = None
 
     def __del__(self):
+        if _is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -265,3 +274,12 @@ def fs_trsv(ctx: Context, R, y, x, transpose: bool = False):
     n = R.shape[1]
     _check(load().fs_trsv(ctx.h, int(n), c_vp(_ptr(R)), int(_colmajor(R)), int(bool(transpose)), c_vp(_ptr(y)),
                           c_vp(_ptr(x))))
+
+
+def fs_time_normal_pass(ctx: Context, A, z, v, repeats: int = 20):
+    """(ms per pass incl. reduction, ms of the fused kernel alone), averaged over `repeats`."""
+    m, n = A.shape
+    t, tk = c_double(0.0), c_double(0.0)
+    _check(load().fs_time_normal_pass(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(z)),
+                                      c_vp(_ptr(v)), int(repeats), ctypes.byref(t), ctypes.byref(tk)))
+    return t.value, tk.value

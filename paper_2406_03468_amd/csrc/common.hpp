@@ -58,3 +58,42 @@ __device__ __forceinline__ double block_sum(double v, double* sh /* NT/64 double
 
 // Device-side early exit: kernels of an inner iteration return at once when the stop flag is set.
 __device__ __forceinline__ bool fs_stopped(const int* stop) { return stop != nullptr && *stop != 0; }
+
+// Grid-wide barrier for kernels launched cooperatively (every work-group co-resident).  A central
+// arrival counter and a generation word in device memory: the last work-group to arrive resets
+// the counter and advances the generation, the others spin on it.  The agent-scope fences make
+// each work-group's earlier global writes visible to the others after the barrier.  The spin is
+// bounded: on expiry *err is set and the work-group proceeds, so a broken launch cannot hang.
+struct GridBarrier {
+  unsigned* count;
+  unsigned* gen;
+  int* err;
+};
+
+__device__ __forceinline__ void grid_barrier(const GridBarrier& b, unsigned nblocks, unsigned& local_gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned g = local_gen;
+    const unsigned arrived = __hip_atomic_fetch_add(b.count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == nblocks) {
+      __hip_atomic_store(b.count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(b.gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned long long spins = 0;
+      while (__hip_atomic_load(b.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ull << 26)) {
+          __hip_atomic_store(b.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    local_gen = g + 1u;
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+// Zero the barrier words before a cooperative launch (a kernel, so it is also graph-safe).
+__global__ void k_barrier_reset(unsigned* words, int n);

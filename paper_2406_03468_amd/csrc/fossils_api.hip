@@ -123,7 +123,7 @@ fs_status validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (o.precond != FS_PRECOND_QR && o.precond != FS_PRECOND_SVD) return FS_ERR_INVALID_ARG;
   if (o.precision != FS_FP64) return FS_ERR_UNSUPPORTED;
   if (o.fixed_q < -1) return FS_ERR_INVALID_ARG;
-  if (n > 16384) return FS_ERR_TOO_LARGE;       // TRSV keeps x in LDS
+  if (n > 15000) return FS_ERR_TOO_LARGE;       // TRSV keeps x in LDS
   if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
   if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
   return FS_OK;
@@ -381,11 +381,38 @@ fs_status fs_residual_pass(fs_context ctx, int64_t m, int32_t n, const double* A
   return FS_OK;
 }
 
+fs_status fs_time_normal_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z,
+                              double* v, int32_t repeats, double* ms_per_pass_host, double* ms_kernel_host) {
+  if (!ctx || !A || !z || !v || !ms_per_pass_host) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < 1 || lda < m || repeats < 1) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  FS_TRY(run_pass(ctx, m, n, A, lda, z, nullptr, v, nullptr, nullptr, nullptr));  // warm-up
+  hipEvent_t* ev = ctx->ev;
+  FS_HIP(hipEventRecord(ev[0], ctx->stream));
+  for (int r = 0; r < repeats; ++r) FS_TRY(run_pass(ctx, m, n, A, lda, z, nullptr, v, nullptr, nullptr, nullptr));
+  FS_HIP(hipEventRecord(ev[1], ctx->stream));
+  // the fused kernel alone: same launches without the partial-sum reduction
+  const PassConfig cfg = pass_config(ctx, m, n, lda);
+  PassArgs a{A, lda, m, n, z, nullptr, (double*)ctx->ws.partial.p, (double*)ctx->ws.pr2.p, nullptr};
+  FS_HIP(hipEventRecord(ev[2], ctx->stream));
+  for (int r = 0; r < repeats; ++r) FS_K(fs_launch_pass_kernel_only(a, cfg, ctx->stream));
+  FS_HIP(hipEventRecord(ev[3], ctx->stream));
+  FS_HIP(hipEventSynchronize(ev[3]));
+  float t01 = 0, t23 = 0;
+  FS_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
+  FS_HIP(hipEventElapsedTime(&t23, ev[2], ev[3]));
+  *ms_per_pass_host = (double)t01 / repeats;
+  if (ms_kernel_host) *ms_kernel_host = (double)t23 / repeats;
+  return FS_OK;
+}
+
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
                   double* x) {
   if (!ctx || !R || !y || !x) return FS_ERR_INVALID_ARG;
   if (n < 1 || ldr < n) return FS_ERR_SHAPE;
-  if (n > 16384) return FS_ERR_TOO_LARGE;
+  if (n > 15000) return FS_ERR_TOO_LARGE;
   FS_HIP(hipSetDevice(ctx->device));
   FS_K(fs_launch_trsv(R, ldr, n, transpose != 0, y, x, nullptr, nullptr, nullptr, ctx->stream));
   FS_HIP(hipStreamSynchronize(ctx->stream));

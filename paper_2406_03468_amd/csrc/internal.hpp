@@ -24,6 +24,8 @@ PassConfig fs_pass_config(int64_t m, int n, int num_cu);
 // out = out_scale .* (A^T w), w = A zs (normal) or b - A zs (residual, r2_out = ||w||^2).
 hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out, const double* out_scale,
                           double* r2_out, double* w_scratch, hipStream_t s);
+// Only the fused kernel (per-work-group partials, no final reduction); fused configurations only.
+hipError_t fs_launch_pass_kernel_only(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
 
 // ---------------------------------------------------------------- sparse sign sketch
 // Index stream: per source row j, zeta entries (position << 1 | sign_bit), 16- or 32-bit.

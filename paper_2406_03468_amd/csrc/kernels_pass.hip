@@ -242,6 +242,10 @@ hipError_t launch_fused(const PassArgs& a, const PassConfig& cfg, hipStream_t s)
 
 }  // namespace
 
+__global__ void k_barrier_reset(unsigned* words, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) words[i] = 0u;
+}
+
 // Pick the tile height from n: the widest tile whose L (column slots per lane) stays <= 16.
 PassConfig fs_pass_config(int64_t m, int n, int num_cu) {
   PassConfig c{};
@@ -279,4 +283,9 @@ hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out,
   hipLaunchKernelGGL(k_reduce_partials, dim3((a.n + 255) / 256), dim3(256), 0, s, a.partial, cfg.G, a.n, out_scale,
                      out, resid ? a.partial_r2 : nullptr, r2_out, a.stop);
   return hipGetLastError();
+}
+
+hipError_t fs_launch_pass_kernel_only(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
+  if (!cfg.H) return hipErrorInvalidValue;
+  return a.b ? launch_fused<true>(a, cfg, s) : launch_fused<false>(a, cfg, s);
 }

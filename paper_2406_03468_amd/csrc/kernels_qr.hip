@@ -15,12 +15,8 @@
 //     work-group updates its own rows.
 // R is left in the upper triangle of Y[0:k, 0:k] with a non-negative diagonal (rows of R whose
 // reflector produced a negative diagonal are negated, which changes Q's columns, not Q R).
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.hpp"
 #include "internal.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace {
 
@@ -33,8 +29,9 @@ constexpr int NRG = QR_NT / NB;   // row groups
 __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64_t ldy, int d, int k, int RB,
                                                    double* __restrict__ part,   // [2][G][2*NB]
                                                    double* __restrict__ wpart,  // [G][NB][k]
-                                                   double* __restrict__ wred) { // [NB][k]
-  cg::grid_group grid = cg::this_grid();
+                                                   double* __restrict__ wred,   // [NB][k]
+                                                   GridBarrier bar) {
+  unsigned bgen = 0;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int rs = g * RB;
   const int re = (rs + RB < d) ? rs + RB : d;
@@ -80,7 +77,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         pp[tid] = t;
         pp[NB + tid] = (j >= rs && j < re && tid < nbp) ? pan[j - rs][tid] : 0.0;
       }
-      grid.sync();
+      grid_barrier(bar, (unsigned)G, bgen);
       // (2) every work-group reduces all partials in the same order.
       if (tid < 2 * NB) {
         double t = 0.0;
@@ -153,7 +150,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
 #pragma unroll
         for (int q = 0; q < NB; ++q) wpart[((size_t)g * NB + q) * k + cc] = acc[q];
       }
-      grid.sync();
+      grid_barrier(bar, (unsigned)G, bgen);
       // (T2) W = sum_g W_g (fixed order), W' = T^T W, for a slice of columns per work-group.
       for (int base = g * NRG; base < ntr; base += G * NRG) {
         const int cc = base + rg;
@@ -168,7 +165,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         if (cc < ntr && c < nbp) wred[(size_t)c * k + cc] = wp;
         __syncthreads();
       }
-      grid.sync();
+      grid_barrier(bar, (unsigned)G, bgen);
       // (T3) own rows: Y[:, k1:k] -= V W'
       for (int cc = tid; cc < ntr; cc += QR_NT) {
         double wv[NB];
@@ -217,7 +214,7 @@ void qr_grid(int d, int num_cu, int* G, int* RB) {
 size_t fs_qr_work_bytes(int d, int k, int num_cu) {
   int G, RB;
   qr_grid(d, num_cu, &G, &RB);
-  return sizeof(double) * ((size_t)2 * G * 2 * NB + (size_t)G * NB * k + (size_t)NB * k) + 256;
+  return sizeof(double) * ((size_t)2 * G * 2 * NB + (size_t)G * NB * k + (size_t)NB * k) + 512;
 }
 
 hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int num_cu, hipStream_t s) {
@@ -227,6 +224,11 @@ hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int nu
   double* part = (double*)work;
   double* wpart = part + (size_t)2 * G * 2 * NB;
   double* wred = wpart + (size_t)G * NB * k;
-  void* args[] = {&Y, &ldy, &d, &k, &RB, &part, &wpart, &wred};
+  unsigned* words = (unsigned*)(wred + (size_t)NB * k);
+  GridBarrier bar{words, words + 1, (int*)(words + 2)};
+  hipLaunchKernelGGL(k_barrier_reset, dim3(1), dim3(64), 0, s, words, 4);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  void* args[] = {&Y, &ldy, &d, &k, &RB, &part, &wpart, &wred, &bar};
   return hipLaunchCooperativeKernel((const void*)k_qr_coop, dim3(G), dim3(QR_NT), args, 0, s);
 }

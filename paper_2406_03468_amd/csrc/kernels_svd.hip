@@ -11,12 +11,8 @@
 // are separated by grid-wide barriers.  A pair is rotated when |g_i^T g_j| > tol ||g_i|| ||g_j||;
 // the sweep loop ends after a sweep without rotations (or at max_sweeps).  A final kernel sorts
 // the singular values in decreasing order and writes sigma, V (and U_R).
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.hpp"
 #include "internal.hpp"
-
-namespace cg = cooperative_groups;
 
 namespace {
 
@@ -28,8 +24,8 @@ __device__ __forceinline__ int rr_player(int pos, int r, int npl) {
 
 __global__ __launch_bounds__(SVD_NT) void k_jacobi_coop(double* __restrict__ Gm, double* __restrict__ U, int n,
                                                         int max_sweeps, double tol, int* __restrict__ rotcount,
-                                                        int* __restrict__ sweeps_out) {
-  cg::grid_group grid = cg::this_grid();
+                                                        int* __restrict__ sweeps_out, GridBarrier bar) {
+  unsigned bgen = 0;
   const int G = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int npl = n + (n & 1);
   const int npairs = npl / 2;
@@ -95,10 +91,10 @@ __global__ __launch_bounds__(SVD_NT) void k_jacobi_coop(double* __restrict__ Gm,
           ++myrot;
         }
       }
-      grid.sync();
+      grid_barrier(bar, (unsigned)G, bgen);
     }
     if (tid == 0 && myrot) atomicAdd(&rotcount[sweep], myrot);
-    grid.sync();
+    grid_barrier(bar, (unsigned)G, bgen);
     const int tot = __hip_atomic_load(&rotcount[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tot == 0) {
       ++sweep;
@@ -158,7 +154,7 @@ __global__ void k_svd_sort_write(const double* __restrict__ Gm, const double* __
 
 }  // namespace
 
-size_t fs_svd_work_bytes(int n) { return sizeof(double) * ((size_t)2 * n * n + n) + sizeof(int) * 128 + 512; }
+size_t fs_svd_work_bytes(int n) { return sizeof(double) * ((size_t)2 * n * n + n) + sizeof(int) * 160 + 512; }
 
 // work layout: Gm (n*n) | Uacc (n*n) | norms (n) | rotcount (64 ints) | sweeps (int)
 hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, double* Uout,
@@ -169,7 +165,8 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   double* Uacc = Gm + (size_t)n * n;
   double* norms = Uacc + (size_t)n * n;
   int* rot = (int*)(norms + n);
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, rot, 64, 0);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, rot, 80, 0);  // rotation counts + barrier words
+  GridBarrier bar{(unsigned*)(rot + 64), (unsigned*)(rot + 65), rot + 66};
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nn = (int64_t)n * n;
@@ -181,7 +178,7 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   if (G < 1) G = 1;
   double tol = (double)(n > 1 ? n : 1) * 2.220446049250313e-16;
   double* Uarg = Uout ? Uacc : nullptr;
-  void* args[] = {&Gm, &Uarg, &n, &max_sweeps, &tol, &rot, &sweeps_out_dev};
+  void* args[] = {&Gm, &Uarg, &n, &max_sweeps, &tol, &rot, &sweeps_out_dev, &bar};
   e = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(G), dim3(SVD_NT), args, 0, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_svd_norms, dim3(n), dim3(256), 0, s, Gm, n, norms);

@@ -19,22 +19,29 @@ __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int6
                                               const double* y, double* x, const double* __restrict__ yscale,
                                               const double* __restrict__ xscale, const int* __restrict__ stop) {
   if (fs_stopped(stop)) return;
-  extern __shared__ double xs[];  // n
+  extern __shared__ double xs[];   // n
+  __shared__ double dblk[64][65];  // current 64 x 64 diagonal block of R (padded)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = tid; i < n; i += VNT) xs[i] = yscale ? y[i] * yscale[i] : y[i];
-  __syncthreads();
   const int nblk = (n + 63) / 64;
+  auto load_diag = [&](int b0, int b1) {
+    // dblk[r][c] = R[b0 + r, b0 + c] for r <= c (coalesced down each column)
+    for (int q = tid; q < 64 * 64; q += VNT) {
+      const int r = q & 63, c = q >> 6;
+      dblk[r][c] = (b0 + r < b1 && b0 + c < b1 && r <= c) ? R[(int64_t)(b0 + c) * ldr + b0 + r] : 0.0;
+    }
+  };
   if (!transpose) {
     for (int kb = nblk - 1; kb >= 0; --kb) {
       const int b0 = kb * 64, b1 = min(n, b0 + 64);
-      if (wv == 0) {
-        // rows b0..b1-1 held by lanes; solve bottom-up
+      load_diag(b0, b1);
+      __syncthreads();
+      if (wv == 0) {  // rows b0..b1-1 held by lanes; solve bottom-up from LDS
         double xi = (b0 + lane < b1) ? xs[b0 + lane] : 0.0;
-        for (int i = b1 - 1; i >= b0; --i) {
-          const double piv = R[(int64_t)i * ldr + i];
-          const double xv = __shfl(xi, i - b0, 64) / piv;
-          if (lane == i - b0) xi = xv;
-          if (b0 + lane < i) xi = fma(-R[(int64_t)i * ldr + b0 + lane], xv, xi);
+        for (int i = b1 - 1 - b0; i >= 0; --i) {
+          const double xv = __shfl(xi, i, 64) / dblk[i][i];
+          if (lane == i) xi = xv;
+          if (lane < i) xi = fma(-dblk[lane][i], xv, xi);
         }
         if (b0 + lane < b1) xs[b0 + lane] = xi;
       }
@@ -50,6 +57,7 @@ __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int6
   } else {
     for (int kb = 0; kb < nblk; ++kb) {
       const int b0 = kb * 64, b1 = min(n, b0 + 64);
+      load_diag(b0, b1);
       // x[b0:b1] -= R[0:b0, b0:b1]^T x[0:b0]: 16 threads per output
       {
         const int o = tid >> 4, sub = tid & 15;
@@ -63,14 +71,12 @@ __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int6
         if (i < b1 && sub == 0) xs[i] -= s;
         __syncthreads();
       }
-      if (wv == 0) {
+      if (wv == 0) {  // forward substitution with R^T (lower) from LDS
         double xi = (b0 + lane < b1) ? xs[b0 + lane] : 0.0;
-        for (int i = b0; i < b1; ++i) {
-          const double piv = R[(int64_t)i * ldr + i];
-          const double xv = __shfl(xi, i - b0, 64) / piv;
-          if (lane == i - b0) xi = xv;
-          // rows j > i of R^T column i: R[i, j]
-          if (b0 + lane > i && b0 + lane < b1) xi = fma(-R[(int64_t)(b0 + lane) * ldr + i], xv, xi);
+        for (int i = 0; i < b1 - b0; ++i) {
+          const double xv = __shfl(xi, i, 64) / dblk[i][i];
+          if (lane == i) xi = xv;
+          if (lane > i) xi = fma(-dblk[i][lane], xv, xi);  // (R^T)[lane][i] = R[i][lane]
         }
         if (b0 + lane < b1) xs[b0 + lane] = xi;
       }
@@ -336,10 +342,10 @@ __global__ void k_state_init(DevState* st, double alpha, double beta, int max_in
 hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
                           const double* yscale, const double* xscale, const int* stop, hipStream_t s) {
   const size_t sh = (size_t)n * sizeof(double);
-  if (sh > 150 * 1024) return hipErrorInvalidValue;
+  if (sh > 120 * 1024) return hipErrorInvalidValue;
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_trsv, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_trsv, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
     attr = true;
   }
   hipLaunchKernelGGL(k_trsv, dim3(1), dim3(VNT), sh, s, R, ldr, n, transpose ? 1 : 0, y, x, yscale, xscale, stop);

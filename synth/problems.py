@@ -130,7 +130,8 @@ def make_problem_torch(m: int, n: int, kappa: float, resid_norm: float, seed: in
     for _ in range(2):
         C = Ut @ Ut.T                                   # n x n Gram
         L = torch.linalg.cholesky(C)                    # C = L L^T
-        Ut = torch.linalg.solve_triangular(L, Ut, upper=False)   # L^{-1} U^T = (U L^{-T})^T
+        Linv = torch.linalg.inv(L)                      # n x n, well conditioned (C ~ m I)
+        Ut = Linv @ Ut                                  # L^{-1} U^T = (U L^{-T})^T
     Vt = torch.as_tensor(V, device=device)
     sig = torch.as_tensor(sigma, device=device)
     # A^T = V diag(sigma) U^T  (n x m row-major == A column-major)

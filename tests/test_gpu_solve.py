@@ -46,6 +46,12 @@ def _fe(x, P):
     return np.linalg.norm(x - P.x_true) / np.linalg.norm(P.x_true)
 
 
+def _fe_ref(P, *xs):
+    """Forward-error reference: the largest of the given solvers' errors, floored at kappa * u (the
+    forward error a backward-stable solver may have on a consistent problem, Fact 2.3)."""
+    return max([_fe(x, P) for x in xs] + [P.kappa * U])
+
+
 C1_CASES = [(1e10, 1e-6), (1e12, 1e-3), (1e4, 1.0), (1e2, 1e-10), (1e13, 1e-8), (1.0, 1e-2)]
 
 
@@ -60,13 +66,14 @@ def test_c1_backward_stable_vs_oracle(ctx, kappa, rnorm, method, precond):
     xq = hh.qr_lstsq(P.A, P.b)
     bg = be.relative_backward_error(P.A, P.b, x, P.sigma, P.V)
     assert bg <= 1e-14, (bg, info.to_dict())
-    fq = _fe(xq, P)
-    assert _fe(x, P) <= 10 * max(fq, _fe(ref.x, P)), (_fe(x, P), fq)
+    fref = _fe_ref(P, xq)
+    assert _fe(x, P) <= 10 * fref, (_fe(x, P), fref)
     # the GPU and oracle iterates agree to the forward-error scale
-    assert np.linalg.norm(x - ref.x) / np.linalg.norm(P.x_true) <= 10 * max(fq, _fe(ref.x, P)) + 1e-15
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(P.x_true) <= 10 * _fe_ref(P, xq, ref.x)
     assert abs(info.iters[0] - ref.iters[0]) <= 3 and abs(info.iters[1] - ref.iters[1]) <= 5
-    # sketch statistics agree with the oracle's (same sketch bits, same factorization up to rounding)
-    assert abs(info.condest - ref.condest) <= 1e-6 * ref.condest
+    # sketch statistics agree with the oracle's (same sketch bits; the sketches differ by summation
+    # order, so sigma_min, hence condest, agrees only to about condest * u relative)
+    assert abs(info.condest - ref.condest) <= (1e-9 + 1e3 * ref.condest * U) * ref.condest
     assert abs(info.normest - ref.normest) <= 1e-12 * ref.normest
 
 
@@ -103,7 +110,7 @@ def test_ragged_and_small_shapes(ctx, m, n):
         assert status == 0
         assert be.relative_backward_error(P.A, P.b, x, P.sigma, P.V) <= 1e-14
         xq = hh.qr_lstsq(P.A, P.b)
-        assert _fe(x, P) <= 10 * max(_fe(xq, P), 1e-16 * 1e8)
+        assert _fe(x, P) <= 10 * _fe_ref(P, xq)
 
 
 def test_zero_rhs(ctx):
@@ -162,7 +169,7 @@ def test_c2_full_size(ctx):
     """1e5 x 1e3, kappa 1e12, ||r|| 1e-3: FOSSILS and SPIR vs LAPACK-Householder forward error."""
     P = make_problem(100_000, 1000, 1e12, 1e-3, seed=0)
     xq = hh.qr_lstsq_lapack(P.A, P.b)
-    fq = _fe(xq, P)
+    fq = _fe_ref(P, xq)
     for method in ("fossils", "spir"):
         status, info, x = _solve(ctx, P, method)
         assert status == 0, info.to_dict()
