@@ -13,7 +13,6 @@ import os
 import sys
 from typing import Optional
 
-_is_finalizing = sys.is_finalizing
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libfossils.so")
 
@@ -163,12 +162,12 @@ class Context:
             self.lib.fs_context_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        # At interpreter shutdown the HIP runtime may already be gone: leave the memory to the OS.
-        if _is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # At interpreter shutdown the HIP runtime (and this module's globals) may already be gone:
+        # leave the memory to the OS.
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass
 
@@ -211,11 +210,10 @@ class Sketch:
             load().sketch_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if _is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass
 

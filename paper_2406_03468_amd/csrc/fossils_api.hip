@@ -471,8 +471,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   double* dinv = (double*)W.dinv.p;
   double* sigma = (double*)W.sigma.p;
   double* V = (double*)W.V.p;
-  double* UR = (double*)W.UR.p;
   double* gpart = (double*)W.gemvpart.p;
+  double* UR = (double*)W.UR.p;
   const double* R = Y;  // upper triangle of Y[0:n, 0:n], ld = d
   const int64_t ldr = d;
   const double* tvec = Y + (int64_t)n * d;  // t = (Q^T S b)[0:n]
@@ -494,8 +494,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
   FS_HIP(hipEventRecord(ev[2], s));
   // ---- SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate)
-  const bool want_u = (o.precond == FS_PRECOND_SVD);
-  FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, want_u ? UR : nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+  FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
                           svd_sweeps_dev, s));
   FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
   FS_HIP(hipEventRecord(ev[3], s));
@@ -527,11 +526,10 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {  // Alg 4: numerically rank deficient
     flags |= 1;
     rk = hs.rank_trunc > 0 ? hs.rank_trunc : 1;
-    if (!use_svd) {  // need U_R as well: recompute with accumulation
-      FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev,
-                              s));
-      use_svd = true;
-    }
+    use_svd = true;
+    // the truncated start x_0 = V_r Sigma_r^{-1} U_r^T t needs U_R: redo the SVD accumulating it
+    // (rank-deficient problems only)
+    FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev, s));
   }
   inf.rank = rk;
   const int nr = use_svd ? rk : n;  // length of the preconditioned variables dy, c, ...
@@ -556,10 +554,11 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   };
 
   // ---- x_0: sketch-and-solve (eq:sketch-and-solve-2.3; Alg 4 with the SVD factors)
-  if (use_svd) {
-    FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));  // U_r^T t
+  if (flags & 1) {
+    // truncated SVD start (Alg 4): x_0 = V_r Sigma_r^{-1} U_r^T t
+    FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));
     FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
-  } else {
+  } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
     FS_K(fs_launch_trsv(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, s));
   }
   FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));

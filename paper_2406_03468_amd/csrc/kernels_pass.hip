@@ -65,9 +65,13 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
   // Lane byte offset inside a column slot (32-bit, so loads use a scalar base + vector offset);
   // the host guarantees CPR * lda * 8 + H * 8 < 2^32 on this path.
   const uint32_t voff = (uint32_t)(((int64_t)cb * lda + 2 * rp) * (int64_t)sizeof(double));
-  auto load = [&](double2 (&a)[L], int64_t t) {
+  auto load = [&](double2 (&a)[L + 1], int64_t t) {
     const int64_t r0 = t * H + 2 * rp;
     const bool full = VEC && (t * H + H <= m);
+    if (RESID) {  // b for this lane's two rows, fetched with the tile
+      a[L].x = (r0 < m) ? b[r0] : 0.0;
+      a[L].y = (r0 + 1 < m) ? b[r0 + 1] : 0.0;
+    }
 #pragma unroll
     for (int k = 0; k < L; ++k) {
       const int c = cb + k * CPR;
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
     }
   };
 
-  auto process = [&](const double2 (&a)[L], int64_t t, int par) {
+  auto process = [&](const double2 (&a)[L + 1], int64_t t, int par) {
     double p0 = 0.0, p1 = 0.0;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
@@ -108,15 +112,15 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
     }
     const int64_t r0 = t * H + 2 * rp;
     if (RESID) {
-      w0 = (r0 < m) ? b[r0] - w0 : 0.0;
-      w1 = (r0 + 1 < m) ? b[r0 + 1] - w1 : 0.0;
+      w0 = (r0 < m) ? a[L].x - w0 : 0.0;
+      w1 = (r0 + 1 < m) ? a[L].y - w1 : 0.0;
       if (cb == 0) r2 = fma(w0, w0, fma(w1, w1, r2));
     }
 #pragma unroll
     for (int k = 0; k < L; ++k) acc[k] = fma(a[k].x, w0, fma(a[k].y, w1, acc[k]));
   };
 
-  double2 bufA[L], bufB[L];
+  double2 bufA[L + 1], bufB[L + 1];
   int64_t t = lo + l0;
   if (t < hi) load(bufA, t);
   while (t < hi) {
@@ -142,25 +146,42 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
   }
 }
 
-// out[c] = scale[c] * sum_g partial[g][c]  (fixed order); optionally r2 = sum_g partial_r2[g].
-__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ partial, int G, int n,
-                                                         const double* __restrict__ scale, double* __restrict__ out,
-                                                         const double* __restrict__ partial_r2, double* __restrict__ r2,
-                                                         const int* __restrict__ stop) {
+// out[c] = scale[c] * sum_g partial[g][c]; optionally r2 = sum_g partial_r2[g].  A work-group
+// takes 64 columns; its 16 row groups each sum every 16th partial, then the 16 sums are added in a
+// fixed order (deterministic, and 16 independent loads in flight per thread instead of G).
+__global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restrict__ partial, int G, int n,
+                                                          const double* __restrict__ scale, double* __restrict__ out,
+                                                          const double* __restrict__ partial_r2, double* __restrict__ r2,
+                                                          const int* __restrict__ stop) {
   if (fs_stopped(stop)) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double sh[16][65];
+  __shared__ double sr[16];
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  double s = 0.0;
   if (c < n) {
-    double s = 0.0;
-    for (int gi = 0; gi < G; ++gi) s += partial[(int64_t)gi * n + c];
-    out[c] = scale ? s * scale[c] : s;
+#pragma unroll 4
+    for (int gi = grp; gi < G; gi += 16) s += partial[(int64_t)gi * n + c];
+  }
+  sh[grp][cl] = s;
+  __syncthreads();
+  if (grp == 0 && c < n) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += sh[q][cl];
+    out[c] = scale ? t * scale[c] : t;
   }
   if (partial_r2 && blockIdx.x == 0) {
-    __shared__ double sh[4];
     double v = 0.0;
-    for (int gi = threadIdx.x; gi < G; gi += 256) v += partial_r2[gi];
-    // fixed-order block reduction
-    v = block_sum<256>(v, sh);
-    if (threadIdx.x == 0) *r2 = v;
+    for (int gi = threadIdx.x; gi < G; gi += 1024) v += partial_r2[gi];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sr[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < 16; ++q) t += sr[q];
+      *r2 = t;
+    }
   }
 }
 
@@ -280,7 +301,7 @@ hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out,
       hipLaunchKernelGGL(k_sumsq_partials, dim3(cfg.G), dim3(256), 0, s, w_scratch, a.m, cfg.G, a.partial_r2, a.stop);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_reduce_partials, dim3((a.n + 255) / 256), dim3(256), 0, s, a.partial, cfg.G, a.n, out_scale,
+  hipLaunchKernelGGL(k_reduce_partials, dim3((a.n + 63) / 64), dim3(1024), 0, s, a.partial, cfg.G, a.n, out_scale,
                      out, resid ? a.partial_r2 : nullptr, r2_out, a.stop);
   return hipGetLastError();
 }

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
   __shared__ double sred[QR_NT / 64][NB];
   __shared__ double sdots[NB], srow[NB], sw[NB], svtv[NB], srdiag[NB];
   __shared__ double sW[NRG][NB + 1];
+  __shared__ double sred4[QR_NT / 64][2 * NB + 1];
   __shared__ signed char sneg[RBMAX];
 
   for (int r = tid; r < RBMAX; r += QR_NT) sneg[r] = 0;
@@ -78,12 +79,22 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         pp[NB + tid] = (j >= rs && j < re && tid < nbp) ? pan[j - rs][tid] : 0.0;
       }
       grid_barrier(bar, (unsigned)G, bgen);
-      // (2) every work-group reduces all partials in the same order.
-      if (tid < 2 * NB) {
+      // (2) every work-group reduces all partials in the same order: entry e = tid % 64, four
+      //     groups of work-groups per entry (independent loads in flight), then a fixed-order sum.
+      {
+        const int e = tid & 63, grp = tid >> 6;
         double t = 0.0;
-        for (int gg = 0; gg < G; ++gg) t += part[((size_t)par * G + gg) * (2 * NB) + tid];
-        if (tid < NB) sdots[tid] = t;
-        else srow[tid - NB] = t;
+#pragma unroll 4
+        for (int gg = grp; gg < G; gg += QR_NT / 64) t += part[((size_t)par * G + gg) * (2 * NB) + e];
+        sred4[grp][e] = t;
+        __syncthreads();
+        if (tid < 2 * NB) {
+          double t2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < QR_NT / 64; ++q) t2 += sred4[q][tid];
+          if (tid < NB) sdots[tid] = t2;
+          else srow[tid - NB] = t2;
+        }
       }
       __syncthreads();
       // (3) reflector scalars.
@@ -151,18 +162,28 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         for (int q = 0; q < NB; ++q) wpart[((size_t)g * NB + q) * k + cc] = acc[q];
       }
       grid_barrier(bar, (unsigned)G, bgen);
-      // (T2) W = sum_g W_g (fixed order), W' = T^T W, for a slice of columns per work-group.
-      for (int base = g * NRG; base < ntr; base += G * NRG) {
-        const int cc = base + rg;
+      // (T2) W = sum_g W_g (fixed order), W' = T^T W, for a slice of columns per work-group: thread
+      //      (c, rg) sums every NRG-th work-group's partial of entry c, then the NRG sums are added.
+      for (int cc = g; cc < ntr; cc += G) {
         double wsum = 0.0;
-        if (cc < ntr && c < nbp)
-          for (int gg = 0; gg < G; ++gg) wsum += wpart[((size_t)gg * NB + c) * k + cc];
+        if (c < nbp) {
+#pragma unroll 4
+          for (int gg = rg; gg < G; gg += NRG) wsum += wpart[((size_t)gg * NB + c) * k + cc];
+        }
         sW[rg][c] = wsum;
         __syncthreads();
-        double wp = 0.0;
-        if (c < nbp)
-          for (int c2 = 0; c2 <= c; ++c2) wp = fma(T[c2][c], sW[rg][c2], wp);
-        if (cc < ntr && c < nbp) wred[(size_t)c * k + cc] = wp;
+        if (tid < NB) {
+          double w = 0.0;
+#pragma unroll
+          for (int q = 0; q < NRG; ++q) w += sW[q][tid];
+          sred4[0][tid] = w;
+        }
+        __syncthreads();
+        if (tid < nbp) {
+          double wp = 0.0;
+          for (int c2 = 0; c2 <= tid; ++c2) wp = fma(T[c2][tid], sred4[0][c2], wp);
+          wred[(size_t)tid * k + cc] = wp;
+        }
         __syncthreads();
       }
       grid_barrier(bar, (unsigned)G, bgen);

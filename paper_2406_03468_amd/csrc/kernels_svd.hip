@@ -104,6 +104,187 @@ __global__ __launch_bounds__(SVD_NT) void k_jacobi_coop(double* __restrict__ Gm,
   if (g == 0 && tid == 0 && sweeps_out) *sweeps_out = sweep;
 }
 
+// ---------------------------------------------------------------- block (systolic) variant
+// Columns are grouped in NBLK blocks of b columns (padded to an even count with an empty block).
+// Work-group p holds two blocks in LDS, at circle positions p ("top") and NBLK-1-p ("bottom").
+// In a round it orthogonalizes every column of its top block against every column of its bottom
+// block (b sub-rounds of b disjoint pairs, one wave per pair); the first round of a sweep also
+// does the pairs inside each block.  Between rounds the blocks move one position around the
+// circle (position 0 fixed): top blocks travel to work-group p+1, bottom blocks to p-1, through
+// double-buffered mailboxes in global memory with point-to-point ready flags, so only the
+// neighbours synchronize.  After NBLK-1 rounds every pair of columns has met once (one sweep) and
+// the blocks are back where they started; a grid barrier then sums the sweep's rotation count.
+__device__ __forceinline__ void jac_rotate_pair(double* __restrict__ x, double* __restrict__ y, int n, double tol,
+                                                int lane, int& nrot) {
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+  for (int q = lane; q < n; q += 64) {
+    const double a = x[q], bq = y[q];
+    sa = fma(a, a, sa);
+    sb = fma(bq, bq, sb);
+    sc = fma(a, bq, sc);
+  }
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  sc = wave_sum(sc);
+  if (sa > 0.0 && sb > 0.0 && fabs(sc) > tol * sqrt(sa) * sqrt(sb)) {
+    const double zeta = (sb - sa) / (2.0 * sc);
+    double t;
+    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+    else t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    for (int q = lane; q < n; q += 64) {
+      const double a = x[q], bq = y[q];
+      x[q] = cs * a - sn * bq;
+      y[q] = sn * a + cs * bq;
+    }
+    ++nrot;
+  }
+}
+
+__device__ __forceinline__ int circle_player(int pos, int r, int nb) {
+  return (pos == 0) ? 0 : 1 + (pos - 1 + r) % (nb - 1);
+}
+
+__device__ __forceinline__ void wait_flag(unsigned* f, unsigned target, int* err) {
+  unsigned long long spins = 0;
+  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > (1ull << 26)) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
+                                                      double tol, double* __restrict__ mbox, unsigned* __restrict__ flags,
+                                                      int* __restrict__ rotcount, int* __restrict__ sweeps_out,
+                                                      GridBarrier bar) {
+  extern __shared__ double lds[];  // [2][b][n]
+  const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const size_t blk = (size_t)b * n;
+  double* slot[2] = {lds, lds + blk};
+  unsigned bgen = 0;
+  auto ncols = [&](int id) { const int c = n - id * b; return c < 0 ? 0 : (c > b ? b : c); };
+  // initial arrangement: top = block p, bottom = block NBLK-1-p
+  int id[2] = {p, NBLK - 1 - p};
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int nc = ncols(id[s2]);
+    for (size_t q = tid; q < blk; q += blockDim.x) {
+      const int c = (int)(q / n);
+      slot[s2][q] = (c < nc) ? Gm[(size_t)(id[s2] * b + c) * n + (q % n)] : 0.0;
+    }
+  }
+  __syncthreads();
+  // mailbox layout: [P][2 slots][2 parities][b*n]
+  auto mb = [&](int wg, int sl, int par) { return mbox + (((size_t)wg * 2 + sl) * 2 + par) * blk; };
+  __shared__ int s_nrot[16];
+  int sweep = 0;
+  unsigned rr = 0;  // global round counter
+  for (; sweep < max_sweeps; ++sweep) {
+    int nrot = 0;
+    for (int r = 0; r < NBLK - 1; ++r, ++rr) {
+      const int nc0 = ncols(id[0]), nc1 = ncols(id[1]);
+      if (r == 0) {
+        // pairs inside each block: round-robin over b' = b rounded up to even
+        const int be = b + (b & 1);
+        for (int sr = 0; sr < be - 1; ++sr) {
+          for (int pp = wv; pp < be; pp += nw) {  // be/2 pairs per block, two blocks
+            const int s2 = pp / (be / 2), k = pp % (be / 2);
+            int a = circle_player(k, sr, be), c2 = circle_player(be - 1 - k, sr, be);
+            const int nc = s2 ? nc1 : nc0;
+            if (a < nc && c2 < nc) jac_rotate_pair(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, lane, nrot);
+          }
+          __syncthreads();
+        }
+      }
+      // pairs between the two blocks: sub-round s pairs top column t with bottom column (t+s) mod b
+      for (int sr = 0; sr < b; ++sr) {
+        for (int t = wv; t < b; t += nw) {
+          const int c2 = (t + sr) % b;
+          if (t < nc0 && c2 < nc1) jac_rotate_pair(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, lane, nrot);
+        }
+        __syncthreads();
+      }
+      if (NBLK == 2) continue;  // a single work-group holds every column: nothing moves
+      // ---- exchange.  In the next round position q >= 2 holds the block now at q + 1... i.e. blocks
+      // move from position q to q - 1 (q >= 2), position 1 wraps to NBLK - 1, position 0 is fixed:
+      //   top (position p):          p >= 2 -> top of p-1;  p == 1 -> bottom of 0
+      //   bottom (position NBLK-1-p): p <= P-2 -> bottom of p+1;  p == P-1 -> own top (local)
+      const int par = rr & 1;
+      int dst_top = -1, dst_top_slot = 0, dst_bot = -1;
+      if (p >= 2) { dst_top = p - 1; dst_top_slot = 0; }
+      if (p == 1) { dst_top = 0; dst_top_slot = 1; }
+      if (p <= P - 2) dst_bot = p + 1;
+      if (dst_top >= 0) {
+        double* o = mb(dst_top, dst_top_slot, par);
+        for (size_t q = tid; q < blk; q += blockDim.x) o[q] = slot[0][q];
+      }
+      if (dst_bot >= 0) {
+        double* o = mb(dst_bot, 1, par);
+        for (size_t q = tid; q < blk; q += blockDim.x) o[q] = slot[1][q];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        __threadfence();
+        if (dst_top >= 0)
+          __hip_atomic_store(&flags[dst_top * 2 + dst_top_slot], rr + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (dst_bot >= 0)
+          __hip_atomic_store(&flags[dst_bot * 2 + 1], rr + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // local move: the last work-group's bottom becomes its top (its old top was sent above)
+      if (p == P - 1 && p >= 1) {
+        for (size_t q = tid; q < blk; q += blockDim.x) slot[0][q] = slot[1][q];
+      }
+      // receives: top from p+1 (p <= P-2, p >= 1); bottom from p-1's bottom (p >= 1) or 1's top (p == 0)
+      const bool recv_top = (p >= 1 && p <= P - 2);
+      const bool recv_bot = true;
+      if (tid == 0) {
+        if (recv_top) wait_flag(&flags[p * 2 + 0], rr + 1, bar.err);
+        if (recv_bot) wait_flag(&flags[p * 2 + 1], rr + 1, bar.err);
+        __threadfence();
+      }
+      __syncthreads();
+      if (recv_top) {
+        const double* src = mb(p, 0, par);
+        for (size_t q = tid; q < blk; q += blockDim.x) slot[0][q] = src[q];
+      }
+      if (recv_bot) {
+        const double* src = mb(p, 1, par);
+        for (size_t q = tid; q < blk; q += blockDim.x) slot[1][q] = src[q];
+      }
+      __syncthreads();
+      // block ids after the move (round r + 1 of this sweep)
+      id[0] = circle_player(p, r + 1, NBLK);
+      id[1] = circle_player(NBLK - 1 - p, r + 1, NBLK);
+    }
+    // sweep total
+    if (lane == 0) s_nrot[wv] = nrot;
+    __syncthreads();
+    if (tid == 0) {
+      int t = 0;
+      for (int w = 0; w < nw; ++w) t += s_nrot[w];
+      if (t) atomicAdd(&rotcount[sweep], t);
+    }
+    grid_barrier(bar, (unsigned)P, bgen);
+    const int tot = __hip_atomic_load(&rotcount[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tot == 0) {
+      ++sweep;
+      break;
+    }
+  }
+  // write the blocks back (after a full sweep they are at their starting positions)
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int nc = ncols(id[s2]);
+    for (size_t q = tid; q < blk; q += blockDim.x) {
+      const int c = (int)(q / n);
+      if (c < nc) Gm[(size_t)(id[s2] * b + c) * n + (q % n)] = slot[s2][q];
+    }
+  }
+  if (p == 0 && tid == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
 // G0 = R^T (n x n, ld n) from the upper triangle of R (ldr); U = I.
 __global__ void k_svd_init(const double* __restrict__ R, int64_t ldr, int n, double* __restrict__ Gm,
                            double* __restrict__ U) {
@@ -154,7 +335,30 @@ __global__ void k_svd_sort_write(const double* __restrict__ Gm, const double* __
 
 }  // namespace
 
-size_t fs_svd_work_bytes(int n) { return sizeof(double) * ((size_t)2 * n * n + n) + sizeof(int) * 160 + 512; }
+namespace {
+constexpr int SVD_LDS_BYTES = 144 * 1024;
+// Block width for the systolic kernel: two blocks of b columns must fit in LDS.
+int svd_block_width(int n) {
+  const int bmax = SVD_LDS_BYTES / (2 * 8 * n);
+  if (bmax < 1) return 0;                 // too large: pairwise fallback
+  if (2 * bmax >= n) return (n + 1) / 2;  // everything in one work-group
+  return bmax < 8 ? bmax : 8;
+}
+}  // namespace
+
+size_t fs_svd_work_bytes(int n) {
+  // Gm | Uacc | norms | counters | mailboxes [P][2][2][b*n] | flags [P][2]
+  const int b = svd_block_width(n);
+  size_t mbox = 0, nflags = 0;
+  if (b > 0) {
+    const int nblk = (n + b - 1) / b;
+    const int NBLK = nblk + (nblk & 1);
+    const int P = NBLK / 2;
+    mbox = (size_t)P * 4 * b * n;
+    nflags = (size_t)P * 2;
+  }
+  return sizeof(double) * ((size_t)2 * n * n + n + 64 + mbox) + sizeof(int) * nflags + 1024;
+}
 
 // work layout: Gm (n*n) | Uacc (n*n) | norms (n) | rotcount (64 ints) | sweeps (int)
 hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, double* Uout,
@@ -165,7 +369,7 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   double* Uacc = Gm + (size_t)n * n;
   double* norms = Uacc + (size_t)n * n;
   int* rot = (int*)(norms + n);
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, s, rot, 80, 0);  // rotation counts + barrier words
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(128), 0, s, rot, 80, 0);  // rotation counts + barrier words
   GridBarrier bar{(unsigned*)(rot + 64), (unsigned*)(rot + 65), rot + 66};
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -173,14 +377,34 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   hipLaunchKernelGGL(k_svd_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, R, ldr, n, Gm,
                      Uout ? Uacc : (double*)nullptr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  int G = (n + 1) / 2;
-  if (G > num_cu) G = num_cu;
-  if (G < 1) G = 1;
   double tol = (double)(n > 1 ? n : 1) * 2.220446049250313e-16;
   double* Uarg = Uout ? Uacc : nullptr;
-  void* args[] = {&Gm, &Uarg, &n, &max_sweeps, &tol, &rot, &sweeps_out_dev, &bar};
-  e = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(G), dim3(SVD_NT), args, 0, s);
-  if (e != hipSuccess) return e;
+  const int bw = svd_block_width(n);
+  if (!Uout && bw > 0) {
+    // systolic block Jacobi (no accumulation of U_R)
+    const int nblk = (n + bw - 1) / bw;
+    const int NBLK = nblk + (nblk & 1);
+    const int P = NBLK / 2;
+    if (P > num_cu) return hipErrorInvalidValue;
+    double* mbox = norms + n + 64;  // after the counters
+    unsigned* flg = (unsigned*)(mbox + (size_t)P * 4 * bw * n);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, (int*)flg, 2 * P, 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t shmem = (size_t)2 * bw * n * sizeof(double);
+    (void)hipFuncSetAttribute((const void*)k_jacobi_block, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    int NB2 = NBLK;
+    int bw2 = bw;
+    void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar};
+    e = hipLaunchCooperativeKernel((const void*)k_jacobi_block, dim3(P), dim3(1024), args, shmem, s);
+    if (e != hipSuccess) return e;
+  } else {
+    int G = (n + 1) / 2;
+    if (G > num_cu) G = num_cu;
+    if (G < 1) G = 1;
+    void* args[] = {&Gm, &Uarg, &n, &max_sweeps, &tol, &rot, &sweeps_out_dev, &bar};
+    e = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(G), dim3(SVD_NT), args, 0, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_svd_norms, dim3(n), dim3(256), 0, s, Gm, n, norms);
   hipLaunchKernelGGL(k_svd_sort_write, dim3(n), dim3(256), 0, s, Gm, Uarg, n, norms, sigma, V, ldv, Uout, ldu);
   return hipGetLastError();

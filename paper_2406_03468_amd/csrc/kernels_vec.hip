@@ -126,6 +126,17 @@ __global__ __launch_bounds__(256) void k_gemv_vt(const double* __restrict__ V, i
   if (threadIdx.x == 0) out[j] = div ? s / div[j] : s;
 }
 
+// out[j] = sum_{i <= j} R[i, j] t[i]  (R^T t for upper-triangular R): one work-group per output
+__global__ __launch_bounds__(256) void k_trmv_t(const double* __restrict__ R, int64_t ldr, int n,
+                                                const double* __restrict__ t, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i <= j; i += 256) s = fma(R[(int64_t)j * ldr + i], t[i], s);
+  s = block_sum<256>(s, sh);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
 // ---------------------------------------------------------------- small vector kernels (one work-group)
 __device__ __forceinline__ double bsum(double v, double* sh) { return block_sum<VNT>(v, sh); }
 
@@ -430,5 +441,10 @@ hipError_t fs_vec_set_double(double* p, double v, hipStream_t s) {
 
 hipError_t fs_vec_state_init(DevState* st, double alpha, double beta, int max_inner, hipStream_t s) {
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, alpha, beta, max_inner);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_trmv_t(const double* R, int64_t ldr, int n, const double* t, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_trmv_t, dim3(n), dim3(256), 0, s, R, ldr, n, t, out);
   return hipGetLastError();
 }

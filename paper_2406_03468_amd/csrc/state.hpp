@@ -49,3 +49,4 @@ hipError_t fs_vec_kw(int n, const double* w, const double* sigma, DevState* st, 
 hipError_t fs_vec_set_int(int* p, int v, hipStream_t s);
 hipError_t fs_vec_set_double(double* p, double v, hipStream_t s);
 hipError_t fs_vec_state_init(DevState* st, double alpha, double beta, int max_inner, hipStream_t s);
+hipError_t fs_vec_trmv_t(const double* R, int64_t ldr, int n, const double* t, double* out, hipStream_t s);

@@ -114,14 +114,15 @@ def test_qr_backward_property_ill_conditioned(ctx, d, k, kappa):
 
 
 # ---------------------------------------------------------------- SVD of R
-@pytest.mark.parametrize("n,kappa", [(50, 1e10), (301, 1e12), (7, 1.0)])
+@pytest.mark.parametrize("n,kappa", [(50, 1e10), (301, 1e12), (7, 1.0), (1000, 1e10), (1999, 1e6), (130, 1e14)])
 def test_svd_of_triangular(ctx, n, kappa):
     from paper_2406_03468_amd import binding
     rng = np.random.default_rng(n)
     Q1, _ = np.linalg.qr(rng.standard_normal((n, n)))
     Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
     s = 10.0 ** -np.linspace(0, np.log10(kappa), n)
-    _, R = hh.householder_qr((Q1 * s) @ Q2.T)
+    R = np.linalg.qr((Q1 * s) @ Q2.T, mode="r")
+    R = R * np.where(np.diag(R) < 0, -1.0, 1.0)[:, None]
     Rd = dev_colmajor(R)
     sig = dev_vec(np.zeros(n))
     V = empty_colmajor(n, n)
