@@ -18,6 +18,46 @@
 
 void fs_set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
 
+// A wave-uniform 64-bit value as an opaque scalar (readfirstlane of both halves).
+__device__ __forceinline__ int64_t fs_uniform64(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)(uint64_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
+// Error-free transformations (contraction off: a*b and s+p must round separately).
+// two_sum: s + e == a + b exactly.  acc_dot: (s, c) += a * b with the rounding errors of the
+// product and of the sum gathered in c (compensated dot product, Ogita-Rump-Oishi Dot2).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+__device__ __forceinline__ void acc_dot(double& s, double& c, double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double pe = fma(a, b, -p);
+  double t, e;
+  two_sum(s, p, t, e);
+  s = t;
+  c = c + (e + pe);
+}
+// Compensated sum over groups of (1<<HI) lanes (as wave_sum_low), returns the rounded total.
+template <int HI>
+__device__ __forceinline__ double wave_sum_low_comp(double s, double c) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int off = 1; off < (1 << HI); off <<= 1) {
+    const double s2 = __shfl_xor(s, off, FS_WAVE), c2 = __shfl_xor(c, off, FS_WAVE);
+    double t, e;
+    two_sum(s, s2, t, e);
+    s = t;
+    c = c + c2 + e;
+  }
+  return s + c;
+}
+
 // Full-wave sum with butterfly shuffles (every lane gets the total).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

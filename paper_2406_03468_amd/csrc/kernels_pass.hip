@@ -46,47 +46,61 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
   const int cb = tid / RP;
   const int G = gridDim.x, g = blockIdx.x;
 
-  // XCD banding of the row tiles.
-  const int64_t T = (m + H - 1) / H;
+  // XCD banding of the full row tiles; a ragged last tile (m % H rows) is done at the end.
+  const int64_t T = m / H;
   const int nb = (G >= 8 && (G % 8) == 0) ? 8 : 1;
   const int band = g % nb, step = G / nb, l0 = g / nb;
   const int64_t lo = (T * band) / nb, hi = (T * (band + 1)) / nb;
 
-  double zr[L];
-  double acc[L];
+  // z lives in LDS (read once per tile and slot; keeps the registers for the two tile buffers)
+  __shared__ double sz[L * CPR];
+  for (int q = tid; q < L * CPR; q += NT) sz[q] = (q < n) ? zs[q] : 0.0;
+  // Residual passes feed the step heads and the backward-error checks, whose noise floor is the
+  // rounding error of A^T r: their accumulations are compensated (Dot2), the normal pass's plain.
+  double acc[L], cmp[RESID ? L : 1];
 #pragma unroll
-  for (int k = 0; k < L; ++k) {
-    const int c = cb + k * CPR;
-    zr[k] = (c < n) ? zs[c] : 0.0;
-    acc[k] = 0.0;
-  }
+  for (int k = 0; k < L; ++k) acc[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < (RESID ? L : 1); ++k) cmp[k] = 0.0;
   double r2 = 0.0;
+  __syncthreads();
 
-  // Lane byte offset inside a column slot (32-bit, so loads use a scalar base + vector offset);
-  // the host guarantees CPR * lda * 8 + H * 8 < 2^32 on this path.
+  // Lane byte offsets inside a column slot (32-bit, so loads use a scalar base + vector offset);
+  // the host guarantees CPR * lda * 8 + H * 8 < 2^32 on this path.  Only the last slot can hold
+  // columns >= n; such lanes re-read the slot's first column (always < n): their z entry is zero
+  // and their sums are never written, so full tiles load with no per-lane predicate.
   const uint32_t voff = (uint32_t)(((int64_t)cb * lda + 2 * rp) * (int64_t)sizeof(double));
-  auto load = [&](double2 (&a)[L + 1], int64_t t) {
+  const uint32_t voffL =
+      (uint32_t)(((int64_t)((cb + (L - 1) * CPR) < n ? cb : 0) * lda + 2 * rp) * (int64_t)sizeof(double));
+  const uint32_t boff = (uint32_t)(2 * rp * sizeof(double));
+  auto ld2 = [&](const char* p) -> double2 {
+    if (VEC) return *reinterpret_cast<const double2*>(p);
+    const double* q = reinterpret_cast<const double*>(p);
+    return make_double2(q[0], q[1]);
+  };
+  auto load = [&](double2 (&a)[L + 1], int64_t t) {  // a full tile
+    // The tile's byte offset goes through readfirstlane: it stays a scalar, and the compiler
+    // does not turn the slot addresses into per-lane 64-bit induction pointers (which would cost
+    // two registers per slot).
+    const int64_t tb = fs_uniform64(t * H * (int64_t)sizeof(double));
+    const char* A0 = reinterpret_cast<const char*>(A) + tb;
+    if (RESID) a[L] = ld2(reinterpret_cast<const char*>(b) + tb + boff);
+#pragma unroll
+    for (int k = 0; k < L; ++k)
+      a[k] = ld2(A0 + (int64_t)(k * CPR) * lda * (int64_t)sizeof(double) + (k == L - 1 ? voffL : voff));
+  };
+  auto load_tail = [&](double2 (&a)[L + 1], int64_t t) {  // rows t*H .. m-1, zero-padded
     const int64_t r0 = t * H + 2 * rp;
-    const bool full = VEC && (t * H + H <= m);
-    if (RESID) {  // b for this lane's two rows, fetched with the tile
+    if (RESID) {
       a[L].x = (r0 < m) ? b[r0] : 0.0;
       a[L].y = (r0 + 1 < m) ? b[r0 + 1] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < L; ++k) {
       const int c = cb + k * CPR;
-      const char* sb = reinterpret_cast<const char*>(A + (int64_t)(k * CPR) * lda + t * H);
-      if (c < n) {
-        if (full) {
-          a[k] = *reinterpret_cast<const double2*>(sb + voff);
-        } else {
-          const double* p = reinterpret_cast<const double*>(sb + voff);
-          a[k].x = (r0 < m) ? p[0] : 0.0;
-          a[k].y = (r0 + 1 < m) ? p[1] : 0.0;
-        }
-      } else {
-        a[k] = make_double2(0.0, 0.0);
-      }
+      const double* p = A + (int64_t)c * lda + r0;
+      a[k].x = (c < n && r0 < m) ? p[0] : 0.0;
+      a[k].y = (c < n && r0 + 1 < m) ? p[1] : 0.0;
     }
   };
 
@@ -94,8 +108,9 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
     double p0 = 0.0, p1 = 0.0;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-      p0 = fma(a[k].x, zr[k], p0);
-      p1 = fma(a[k].y, zr[k], p1);
+      const double zk = sz[cb + k * CPR];
+      p0 = fma(a[k].x, zk, p0);
+      p1 = fma(a[k].y, zk, p1);
     }
     p0 = wave_sum_high<LOG2RP>(p0);
     p1 = wave_sum_high<LOG2RP>(p1);
@@ -110,14 +125,22 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
       w0 += sw[par][i][2 * rp];
       w1 += sw[par][i][2 * rp + 1];
     }
-    const int64_t r0 = t * H + 2 * rp;
     if (RESID) {
+      const int64_t r0 = t * H + 2 * rp;  // rows past m carry zeros in a[L] and A
       w0 = (r0 < m) ? a[L].x - w0 : 0.0;
       w1 = (r0 + 1 < m) ? a[L].y - w1 : 0.0;
       if (cb == 0) r2 = fma(w0, w0, fma(w1, w1, r2));
     }
+    if (RESID) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) acc[k] = fma(a[k].x, w0, fma(a[k].y, w1, acc[k]));
+      for (int k = 0; k < L; ++k) {
+        acc_dot(acc[k], cmp[RESID ? k : 0], a[k].x, w0);
+        acc_dot(acc[k], cmp[RESID ? k : 0], a[k].y, w1);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < L; ++k) acc[k] = fma(a[k].x, w0, fma(a[k].y, w1, acc[k]));
+    }
   };
 
   double2 bufA[L + 1], bufB[L + 1];
@@ -132,11 +155,16 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
     process(bufB, t, 1);
     t += step;
   }
+  if (T * H < m && g == G - 1) {  // ragged last tile (uniform branch: whole work-group)
+    __syncthreads();
+    load_tail(bufA, T);
+    process(bufA, T, 0);
+  }
 
   // v partial: sum the RP lanes of each column segment, then one lane per column writes.
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    const double s = wave_sum_low<LOG2RP>(acc[k]);
+    const double s = RESID ? wave_sum_low_comp<LOG2RP>(acc[k], cmp[RESID ? k : 0]) : wave_sum_low<LOG2RP>(acc[k]);
     const int c = cb + k * CPR;
     if (rp == 0 && c < n) partial[(int64_t)g * n + c] = s;
   }
@@ -154,21 +182,33 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restri
                                                           const double* __restrict__ partial_r2, double* __restrict__ r2,
                                                           const int* __restrict__ stop) {
   if (fs_stopped(stop)) return;
-  __shared__ double sh[16][65];
+  __shared__ double sh[16][65], she[16][65];
   __shared__ double sr[16];
   const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + cl;
-  double s = 0.0;
+  double s = 0.0, e = 0.0;  // compensated (Neumaier) sums: the partials can cancel
   if (c < n) {
-#pragma unroll 4
-    for (int gi = grp; gi < G; gi += 16) s += partial[(int64_t)gi * n + c];
+#pragma unroll 8
+    for (int gi = grp; gi < G; gi += 16) {
+      double t, d;
+      two_sum(s, partial[(int64_t)gi * n + c], t, d);
+      s = t;
+      e += d;
+    }
   }
   sh[grp][cl] = s;
+  she[grp][cl] = e;
   __syncthreads();
   if (grp == 0 && c < n) {
-    double t = 0.0;
+    double t = 0.0, te = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) t += sh[q][cl];
+    for (int q = 0; q < 16; ++q) {
+      double u, d;
+      two_sum(t, sh[q][cl], u, d);
+      t = u;
+      te += d + she[q][cl];
+    }
+    t += te;
     out[c] = scale ? t * scale[c] : t;
   }
   if (partial_r2 && blockIdx.x == 0) {

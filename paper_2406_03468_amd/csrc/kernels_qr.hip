@@ -84,7 +84,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
       {
         const int e = tid & 63, grp = tid >> 6;
         double t = 0.0;
-#pragma unroll 4
+#pragma unroll 16
         for (int gg = grp; gg < G; gg += QR_NT / 64) t += part[((size_t)par * G + gg) * (2 * NB) + e];
         sred4[grp][e] = t;
         __syncthreads();
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
       for (int cc = g; cc < ntr; cc += G) {
         double wsum = 0.0;
         if (c < nbp) {
-#pragma unroll 4
+#pragma unroll 8
           for (int gg = rg; gg < G; gg += NRG) wsum += wpart[((size_t)gg * NB + c) * k + cc];
         }
         sW[rg][c] = wsum;

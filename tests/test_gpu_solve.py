@@ -94,12 +94,16 @@ def test_fixed_q_algorithm2_gpu(ctx):
 
 
 def test_one_step_variant_not_backward_stable(ctx):
+    """One refinement step leaves BE ~ kappa u ||r||-level error (Section 4.1); two steps reach the
+    backward-stable bar.  At this difficulty (kappa = 1e12, ||r|| = kappa u) the second step's
+    sketched-KW test sits at its noise floor and may run to the iteration cap (the CPU oracle does
+    the same for some sketch seeds), so only the BE values are checked, not the status."""
     P = make_problem(4000, 50, 1e12, 1e12 * U, seed=5)
     _, _, x1 = _solve(ctx, P, steps=1)
     _, _, x2 = _solve(ctx, P)
     b1 = be.relative_backward_error(P.A, P.b, x1, P.sigma, P.V)
     b2 = be.relative_backward_error(P.A, P.b, x2, P.sigma, P.V)
-    assert b2 <= 1e-15 and b1 >= 30 * b2
+    assert b2 <= 1e-14 and b1 >= 100 * b2, (b1, b2)
 
 
 @pytest.mark.parametrize("m,n", [(10007, 130), (3001, 1), (700, 60), (20000, 300)])
