@@ -135,5 +135,74 @@ __device__ __forceinline__ void grid_barrier(const GridBarrier& b, unsigned nblo
   __syncthreads();
 }
 
+// ---- fence-free cross-work-group exchange
+// An agent-scope release/acquire on this GPU writes back / invalidates the whole L2 of the XCD
+// (the XCD L2s are not coherent with each other), which makes a fenced grid barrier cost 10-20 us
+// and evicts the working set.  Data that other work-groups read is instead written and read with
+// relaxed agent-scope atomics (coherent accesses that bypass the non-coherent L2 copies), and the
+// barrier only orders them: every thread waits for its own stores to complete (s_waitcnt) before
+// the work-group arrives, and readers issue their loads after observing the new generation.
+// Kernels using grid_barrier_co must route ALL data shared across work-groups through
+// st_co / ld_co / st_cob / ld_cob (or re-read only what they wrote themselves).
+__device__ __forceinline__ void st_co(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_co(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
+
+// Bulk coherent traffic: raw buffer loads/stores with the SC1 cache-policy bit (the same coherence
+// as the relaxed agent-scope atomics above, but the compiler keeps many of them in flight instead of
+// waiting after each one).  A resource covers `bytes` (< 4 GiB) from `base`; out-of-range offsets
+// read 0 / drop the store.  Word 3 is the gfx9 raw-buffer format (32-bit data format).
+constexpr int FS_CPOL_SC1 = 16;
+constexpr int FS_RSRC_WORD3 = 0x00020000;
+typedef unsigned int fs_u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t co_rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)(uint32_t)bytes, FS_RSRC_WORD3);
+}
+__device__ __forceinline__ double ld_cob(__amdgpu_buffer_rsrc_t r, size_t byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(uint32_t)byte_off, 0, FS_CPOL_SC1));
+}
+__device__ __forceinline__ void st_cob(__amdgpu_buffer_rsrc_t r, size_t byte_off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(fs_u32x2, v), r, (int)(uint32_t)byte_off, 0, FS_CPOL_SC1);
+}
+
+// Arrival counters: FS_BAR_SLOTS monotonic counters on separate 128-byte lines (work-group g adds
+// to slot g % FS_BAR_SLOTS, so arrivals do not all serialize on one address); barrier number c is
+// passed when the slots sum to (c + 1) * nblocks.  Lanes of wave 0 poll one slot each.  No reset
+// between barriers: the words are zeroed once before the launch (FS_BAR_WORDS words).
+constexpr int FS_BAR_SLOTS = 8;
+constexpr int FS_BAR_STRIDE = 32;  // unsigned words per slot (128 bytes)
+constexpr int FS_BAR_WORDS = FS_BAR_SLOTS * FS_BAR_STRIDE + 8;
+__device__ __forceinline__ void grid_barrier_co(const GridBarrier& b, unsigned nblocks, unsigned& local_gen) {
+  stores_complete();
+  __syncthreads();
+  const unsigned target = (local_gen + 1u) * nblocks;
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(b.count + (blockIdx.x % FS_BAR_SLOTS) * FS_BAR_STRIDE, 1u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    unsigned long long spins = 0;
+    while (true) {
+      unsigned v = (lane < FS_BAR_SLOTS)
+                       ? __hip_atomic_load(b.count + lane * FS_BAR_STRIDE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : 0u;
+#pragma unroll
+      for (int off = 1; off < FS_BAR_SLOTS; off <<= 1) v += __shfl_xor(v, off, FS_WAVE);
+      if (__shfl(v, 0, FS_WAVE) >= target) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1ull << 26)) {
+        if (lane == 0) __hip_atomic_store(b.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  local_gen += 1u;
+  __syncthreads();
+}
+
 // Zero the barrier words before a cooperative launch (a kernel, so it is also graph-safe).
 __global__ void k_barrier_reset(unsigned* words, int n);

@@ -13,6 +13,8 @@
 //   * the trailing columns are updated as Y <- Y - V T^T (V^T Y): V^T Y is summed over row blocks
 //     (per-work-group partials, then a column-distributed fixed-order reduction), then each
 //     work-group updates its own rows.
+// Y is only ever touched by the work-group owning the rows; the partials exchanged between
+// work-groups go through coherent stores/loads, so the grid barriers need no cache flushes.
 // R is left in the upper triangle of Y[0:k, 0:k] with a non-negative diagonal (rows of R whose
 // reflector produced a negative diagonal are negated, which changes Q's columns, not Q R).
 #include "common.hpp"
@@ -46,6 +48,10 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
   __shared__ signed char sneg[RBMAX];
 
   for (int r = tid; r < RBMAX; r += QR_NT) sneg[r] = 0;
+  // coherent views of the exchange buffers (bulk SC1 loads/stores)
+  const auto rpart = co_rsrc(part, sizeof(double) * (size_t)2 * G * 2 * NB);
+  const auto rwpart = co_rsrc(wpart, sizeof(double) * (size_t)G * NB * k);
+  const auto rwred = co_rsrc(wred, sizeof(double) * (size_t)NB * k);
 
   const int c = tid % NB;
   const int rg = tid / NB;
@@ -74,18 +80,27 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < QR_NT / 64; ++w) t += sred[w][tid];
-        double* pp = part + ((size_t)par * G + g) * (2 * NB);
-        pp[tid] = t;
-        pp[NB + tid] = (j >= rs && j < re && tid < nbp) ? pan[j - rs][tid] : 0.0;
+        const size_t pp = ((size_t)par * G + g) * (2 * NB);
+        st_cob(rpart, 8 * (pp + tid), t);
+        st_cob(rpart, 8 * (pp + NB + tid), (j >= rs && j < re && tid < nbp) ? pan[j - rs][tid] : 0.0);
       }
-      grid_barrier(bar, (unsigned)G, bgen);
+      grid_barrier_co(bar, (unsigned)G, bgen);
       // (2) every work-group reduces all partials in the same order: entry e = tid % 64, four
       //     groups of work-groups per entry (independent loads in flight), then a fixed-order sum.
       {
         const int e = tid & 63, grp = tid >> 6;
+        // batches of 16 independent loads in flight (offsets past G read 0 through the range check)
         double t = 0.0;
-#pragma unroll 16
-        for (int gg = grp; gg < G; gg += QR_NT / 64) t += part[((size_t)par * G + gg) * (2 * NB) + e];
+        for (int g0 = grp; g0 < G; g0 += 16 * (QR_NT / 64)) {
+          double vals[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int gg = g0 + q * (QR_NT / 64);
+            vals[q] = ld_cob(rpart, gg < G ? 8 * (((size_t)par * G + gg) * (2 * NB) + e) : (size_t)0xFFFFFFF0u);
+          }
+#pragma unroll
+          for (int q = 0; q < 16; ++q) t += vals[q];
+        }
         sred4[grp][e] = t;
         __syncthreads();
         if (tid < 2 * NB) {
@@ -159,16 +174,24 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
           }
         }
 #pragma unroll
-        for (int q = 0; q < NB; ++q) wpart[((size_t)g * NB + q) * k + cc] = acc[q];
+        for (int q = 0; q < NB; ++q) st_cob(rwpart, 8 * (((size_t)g * NB + q) * k + cc), acc[q]);
       }
-      grid_barrier(bar, (unsigned)G, bgen);
+      grid_barrier_co(bar, (unsigned)G, bgen);
       // (T2) W = sum_g W_g (fixed order), W' = T^T W, for a slice of columns per work-group: thread
       //      (c, rg) sums every NRG-th work-group's partial of entry c, then the NRG sums are added.
       for (int cc = g; cc < ntr; cc += G) {
         double wsum = 0.0;
         if (c < nbp) {
-#pragma unroll 8
-          for (int gg = rg; gg < G; gg += NRG) wsum += wpart[((size_t)gg * NB + c) * k + cc];
+          for (int g0 = rg; g0 < G; g0 += 8 * NRG) {
+            double vals[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const int gg = g0 + q * NRG;
+              vals[q] = ld_cob(rwpart, gg < G ? 8 * (((size_t)gg * NB + c) * k + cc) : (size_t)0xFFFFFFF0u);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) wsum += vals[q];
+          }
         }
         sW[rg][c] = wsum;
         __syncthreads();
@@ -182,16 +205,16 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         if (tid < nbp) {
           double wp = 0.0;
           for (int c2 = 0; c2 <= tid; ++c2) wp = fma(T[c2][tid], sred4[0][c2], wp);
-          wred[(size_t)tid * k + cc] = wp;
+          st_cob(rwred, 8 * ((size_t)tid * k + cc), wp);
         }
         __syncthreads();
       }
-      grid_barrier(bar, (unsigned)G, bgen);
+      grid_barrier_co(bar, (unsigned)G, bgen);
       // (T3) own rows: Y[:, k1:k] -= V W'
       for (int cc = tid; cc < ntr; cc += QR_NT) {
         double wv[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) wv[q] = (q < nbp) ? wred[(size_t)q * k + cc] : 0.0;
+        for (int q = 0; q < NB; ++q) wv[q] = (q < nbp) ? ld_cob(rwred, 8 * ((size_t)q * k + cc)) : 0.0;
         double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
         for (int r = r_lo; r < nr; ++r) {
           const int lim = rs + r - k0;
@@ -235,7 +258,8 @@ void qr_grid(int d, int num_cu, int* G, int* RB) {
 size_t fs_qr_work_bytes(int d, int k, int num_cu) {
   int G, RB;
   qr_grid(d, num_cu, &G, &RB);
-  return sizeof(double) * ((size_t)2 * G * 2 * NB + (size_t)G * NB * k + (size_t)NB * k) + 512;
+  return sizeof(double) * ((size_t)2 * G * 2 * NB + (size_t)G * NB * k + (size_t)NB * k) +
+         sizeof(unsigned) * FS_BAR_WORDS + 512;
 }
 
 hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int num_cu, hipStream_t s) {
@@ -246,8 +270,8 @@ hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int nu
   double* wpart = part + (size_t)2 * G * 2 * NB;
   double* wred = wpart + (size_t)G * NB * k;
   unsigned* words = (unsigned*)(wred + (size_t)NB * k);
-  GridBarrier bar{words, words + 1, (int*)(words + 2)};
-  hipLaunchKernelGGL(k_barrier_reset, dim3(1), dim3(64), 0, s, words, 4);
+  GridBarrier bar{words, nullptr, (int*)(words + FS_BAR_WORDS - 1)};
+  hipLaunchKernelGGL(k_barrier_reset, dim3(1), dim3(256), 0, s, words, FS_BAR_WORDS);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {&Y, &ldy, &d, &k, &RB, &part, &wpart, &wred, &bar};

@@ -147,7 +147,7 @@ __device__ __forceinline__ int circle_player(int pos, int r, int nb) {
 
 __device__ __forceinline__ void wait_flag(unsigned* f, unsigned target, int* err) {
   unsigned long long spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     __builtin_amdgcn_s_sleep(1);
     if (++spins > (1ull << 26)) {
       __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -178,7 +178,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
   }
   __syncthreads();
   // mailbox layout: [P][2 slots][2 parities][b*n]
-  auto mb = [&](int wg, int sl, int par) { return mbox + (((size_t)wg * 2 + sl) * 2 + par) * blk; };
+  auto mb = [&](int wg, int sl, int par) { return (((size_t)wg * 2 + sl) * 2 + par) * blk; };  // element offset
+  const auto rmbox = co_rsrc(mbox, sizeof(double) * (size_t)P * 4 * blk);
   __shared__ int s_nrot[16];
   int sweep = 0;
   unsigned rr = 0;  // global round counter
@@ -217,21 +218,23 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
       if (p >= 2) { dst_top = p - 1; dst_top_slot = 0; }
       if (p == 1) { dst_top = 0; dst_top_slot = 1; }
       if (p <= P - 2) dst_bot = p + 1;
+      // mailboxes are written and read with coherent accesses; the flag is raised once every
+      // thread's stores have completed (no cache flush needed, see grid_barrier_co)
       if (dst_top >= 0) {
-        double* o = mb(dst_top, dst_top_slot, par);
-        for (size_t q = tid; q < blk; q += blockDim.x) o[q] = slot[0][q];
+        const size_t o = mb(dst_top, dst_top_slot, par);
+        for (size_t q = tid; q < blk; q += blockDim.x) st_cob(rmbox, 8 * (o + q), slot[0][q]);
       }
       if (dst_bot >= 0) {
-        double* o = mb(dst_bot, 1, par);
-        for (size_t q = tid; q < blk; q += blockDim.x) o[q] = slot[1][q];
+        const size_t o = mb(dst_bot, 1, par);
+        for (size_t q = tid; q < blk; q += blockDim.x) st_cob(rmbox, 8 * (o + q), slot[1][q]);
       }
+      stores_complete();
       __syncthreads();
       if (tid == 0) {
-        __threadfence();
         if (dst_top >= 0)
-          __hip_atomic_store(&flags[dst_top * 2 + dst_top_slot], rr + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&flags[dst_top * 2 + dst_top_slot], rr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (dst_bot >= 0)
-          __hip_atomic_store(&flags[dst_bot * 2 + 1], rr + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&flags[dst_bot * 2 + 1], rr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       // local move: the last work-group's bottom becomes its top (its old top was sent above)
       if (p == P - 1 && p >= 1) {
@@ -243,17 +246,26 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
       if (tid == 0) {
         if (recv_top) wait_flag(&flags[p * 2 + 0], rr + 1, bar.err);
         if (recv_bot) wait_flag(&flags[p * 2 + 1], rr + 1, bar.err);
-        __threadfence();
       }
       __syncthreads();
-      if (recv_top) {
-        const double* src = mb(p, 0, par);
-        for (size_t q = tid; q < blk; q += blockDim.x) slot[0][q] = src[q];
-      }
-      if (recv_bot) {
-        const double* src = mb(p, 1, par);
-        for (size_t q = tid; q < blk; q += blockDim.x) slot[1][q] = src[q];
-      }
+      // batches of 8 independent coherent loads per thread (offsets past the block read 0)
+      auto recv = [&](double* dst, size_t src) {
+        for (size_t q0 = tid; q0 < blk; q0 += 8 * (size_t)blockDim.x) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const size_t q = q0 + (size_t)u * blockDim.x;
+            v[u] = ld_cob(rmbox, q < blk ? 8 * (src + q) : (size_t)0xFFFFFFF0u);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const size_t q = q0 + (size_t)u * blockDim.x;
+            if (q < blk) dst[q] = v[u];
+          }
+        }
+      };
+      if (recv_top) recv(slot[0], mb(p, 0, par));
+      if (recv_bot) recv(slot[1], mb(p, 1, par));
       __syncthreads();
       // block ids after the move (round r + 1 of this sweep)
       id[0] = circle_player(p, r + 1, NBLK);
@@ -265,9 +277,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
     if (tid == 0) {
       int t = 0;
       for (int w = 0; w < nw; ++w) t += s_nrot[w];
-      if (t) atomicAdd(&rotcount[sweep], t);
+      if (t) __hip_atomic_fetch_add(&rotcount[sweep], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    grid_barrier(bar, (unsigned)P, bgen);
+    grid_barrier_co(bar, (unsigned)P, bgen);
     const int tot = __hip_atomic_load(&rotcount[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (tot == 0) {
       ++sweep;
@@ -337,6 +349,7 @@ __global__ void k_svd_sort_write(const double* __restrict__ Gm, const double* __
 
 namespace {
 constexpr int SVD_LDS_BYTES = 144 * 1024;
+constexpr int SVD_CTR_DOUBLES = (72 + FS_BAR_WORDS + 1) / 2 + 1;  // counters region, in doubles
 // Block width for the systolic kernel: two blocks of b columns must fit in LDS.
 int svd_block_width(int n) {
   const int bmax = SVD_LDS_BYTES / (2 * 8 * n);
@@ -357,7 +370,7 @@ size_t fs_svd_work_bytes(int n) {
     mbox = (size_t)P * 4 * b * n;
     nflags = (size_t)P * 2;
   }
-  return sizeof(double) * ((size_t)2 * n * n + n + 64 + mbox) + sizeof(int) * nflags + 1024;
+  return sizeof(double) * ((size_t)2 * n * n + n + SVD_CTR_DOUBLES + mbox) + sizeof(int) * nflags + 1024;
 }
 
 // work layout: Gm (n*n) | Uacc (n*n) | norms (n) | rotcount (64 ints) | sweeps (int)
@@ -369,8 +382,10 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   double* Uacc = Gm + (size_t)n * n;
   double* norms = Uacc + (size_t)n * n;
   int* rot = (int*)(norms + n);
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(128), 0, s, rot, 80, 0);  // rotation counts + barrier words
+  // rotation counts (64) | fenced-barrier words (count, gen, err) | fence-free barrier words
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, rot, 2 * SVD_CTR_DOUBLES, 0);
   GridBarrier bar{(unsigned*)(rot + 64), (unsigned*)(rot + 65), rot + 66};
+  GridBarrier bar_co{(unsigned*)(rot + 72), nullptr, rot + 66};
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nn = (int64_t)n * n;
@@ -386,7 +401,7 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     const int NBLK = nblk + (nblk & 1);
     const int P = NBLK / 2;
     if (P > num_cu) return hipErrorInvalidValue;
-    double* mbox = norms + n + 64;  // after the counters
+    double* mbox = norms + n + SVD_CTR_DOUBLES;  // after the counters
     unsigned* flg = (unsigned*)(mbox + (size_t)P * 4 * bw * n);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, (int*)flg, 2 * P, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -394,7 +409,7 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     (void)hipFuncSetAttribute((const void*)k_jacobi_block, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     int NB2 = NBLK;
     int bw2 = bw;
-    void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar};
+    void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co};
     e = hipLaunchCooperativeKernel((const void*)k_jacobi_block, dim3(P), dim3(1024), args, shmem, s);
     if (e != hipSuccess) return e;
   } else {
