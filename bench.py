@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--method", default="fossils", choices=["fossils", "spir"])
-    ap.add_argument("--precond", default="qr", choices=["qr", "svd"])
+    ap.add_argument("--precond", default="svd", choices=["qr", "svd"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=8)

@@ -98,7 +98,8 @@ fs_status fs_context_create(int device, void* hip_stream, fs_context* out);
 fs_status fs_context_destroy(fs_context ctx);
 
 /* Defaults of Algorithm 4 for an m x n problem (d = 12 n, zeta = 8, gamma = 10, rho = 0.4,
- * kw_every = 5, max_inner = 100, tau_factor = 30, column scaling on, QR preconditioner). */
+ * kw_every = 5, max_inner = 100, tau_factor = 30, column scaling on, SVD preconditioner
+ * P = V Sigma^{-1} as in Algorithm 4). */
 fs_status fs_options_default(int64_t m, int32_t n, fs_options* opts);
 
 /* FOSSILS (Algorithm 4 with Polyak inner solves; Algorithm 2 when opts->fixed_q != 0).

@@ -1,9 +1,9 @@
 // Host orchestration behind the C ABI declared in include/fossils.h.
 //
-// One solve (QR preconditioner, adaptive stopping) runs on the context's stream:
+// One solve (adaptive stopping) runs on the context's stream:
 //   sketch index stream -> Y = S [A D^{-1} b] and ||a_j||^2 (one read of A)
 //   -> Householder QR of Y (cooperative kernel) -> SVD of R (cooperative Jacobi)
-//   -> x_0 = R^{-1} t -> for i in {0,1}: residual pass, c = P^T g, inner iterations
+//   -> x_0 = R^{-1} t -> for i in {0,1}: residual pass, c = P^T g (P = V Sigma^{-1} or R^{-1}), inner iterations
 //      (z = P dy, v = A^T A z in one read of A, u = P^T v, heavy-ball or CG update),
 //      x += P dy -> x = D^{-1} x.
 // The inner loop's scalars and stop flag live in device memory (DevState); kernels of an inner
@@ -169,7 +169,7 @@ fs_status fs_options_default(int64_t m, int32_t n, fs_options* o) {
   o->max_inner = 100;
   o->tau_factor = 30.0;
   o->column_scaling = 1;
-  o->precond = FS_PRECOND_QR;
+  o->precond = FS_PRECOND_SVD;  // Alg 4: P = V Sigma^{-1} (two GEMVs per iteration instead of two TRSVs)
   o->fixed_q = 0;
   o->steps = 2;
   o->precision = FS_FP64;

@@ -46,6 +46,7 @@ def test_options_default_is_algorithm4(clib):
     assert (o.d, o.zeta, o.kw_every, o.max_inner) == (12000, 8, 5, 100)
     assert (o.gamma, o.rho, o.tau_factor) == (10.0, 0.4, 30.0)
     assert o.column_scaling == 1 and o.steps == 2 and o.fixed_q == 0
+    assert o.precond == binding.FS_PRECOND_SVD  # Alg 4: P = V Sigma^{-1}
 
 
 def test_status_strings(clib):
