@@ -114,6 +114,18 @@ fs_status fossils_solve(fs_context ctx, int64_t m, int32_t n, const double* A, i
 fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                      double* x, const fs_options* opts, fs_info* info);
 
+/* FOSSILS for k (1..64) right-hand sides sharing A: column j of X (n x k, ldx >= n) solves the
+ * least-squares problem with column j of B (m x k, ldb >= m), both column-major device arrays.
+ * One sketch S [A B], one QR and one SVD serve every column (x_0 = R^{-1} t_j); the inner
+ * heavy-ball iterations of all columns run together, each pass A^T (A Z) over the k columns on the
+ * FP64 matrix cores, and every column keeps Algorithm 4's stopping rules of its own (a column
+ * that has stopped is frozen).  Adaptive mode only (opts->fixed_q must be 0); P = V Sigma^{-1}.
+ * info, if not NULL, points to k fs_info records (per right-hand side).  Returns
+ * FS_WARN_NOT_CONVERGED if any column hit the iteration cap in the second step. */
+fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, int32_t k,
+                              const double* B, int64_t ldb, double* X, int64_t ldx, const fs_options* opts,
+                              fs_info* info);
+
 /* ---------------- sparse sign embedding (Section 4.2, "Choice of embedding") ---------------- */
 
 /* Sketch handle for S (d x m, zeta nonzeros per column).  The index stream is generated on the

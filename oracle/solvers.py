@@ -305,6 +305,15 @@ def fossils(A, b, opts: Optional[Options] = None) -> Result:
     return solve(A, b, "fossils", opts)
 
 
+def fossils_multi(A, B, opts: Optional[Options] = None):
+    """Several right-hand sides sharing A: column j of B solved by Algorithm 4 on its own, with the
+    same embedding S for every column (the multi-RHS form sketches [A B] with one S, so each
+    column sees exactly the sketch [S A, S b_j] of the single-column method).  Returns the list of
+    per-column Results."""
+    B = np.asarray(B)
+    return [fossils(A, B[:, j], opts) for j in range(B.shape[1])]
+
+
 def spir(A, b, opts: Optional[Options] = None) -> Result:
     return solve(A, b, "spir", opts)
 

@@ -78,6 +78,8 @@ _SIGS = [
                                 ctypes.POINTER(FsInfo)]),
     ("spir_solve", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
                              ctypes.POINTER(FsInfo)]),
+    ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
+                                      ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
     ("sketch_create", c_int32, [c_vp, c_int64, c_int32, c_int32, c_uint64, ctypes.POINTER(c_vp)]),
     ("sketch_destroy", c_int32, [c_vp]),
     ("sketch_indices", c_int32, [c_vp, c_int64, c_int64, c_vp, c_vp]),
@@ -196,6 +198,20 @@ def spir_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
     s, info = _solve(load().spir_solve, ctx, A, b, x, opts)
     _check(s)
     return s, info
+
+
+def fossils_solve_multi(ctx: Context, A, B, X, opts: Optional[FsOptions] = None):
+    """B: (m, k) column-major right-hand sides, X: (n, k) column-major output; returns (status, [FsInfo] * k)."""
+    m, n = A.shape
+    k = B.shape[1]
+    if B.shape[0] != m or X.shape != (n, k):
+        raise ValueError("shape mismatch")
+    infos = (FsInfo * k)()
+    s = load().fossils_solve_multi(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), int(k), c_vp(_ptr(B)),
+                                   int(_colmajor(B)), c_vp(_ptr(X)), int(_colmajor(X)),
+                                   ctypes.byref(opts) if opts is not None else None, infos)
+    _check(s)
+    return s, list(infos)
 
 
 class Sketch:

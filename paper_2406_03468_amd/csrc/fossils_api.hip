@@ -19,6 +19,7 @@
 
 #include "../../include/fossils.h"
 #include "common.hpp"
+#include "context.hpp"
 #include "internal.hpp"
 #include "state.hpp"
 
@@ -35,42 +36,17 @@ void fs_set_last_hip_error(hipError_t e, const char* what, const char* file, int
 }
 
 namespace {
-
-constexpr double U_ROUND = 2.220446049250313e-16;
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
-struct Workspace {
-  DevBuf idx, Y, colnorm2, dinv, qrwork, svdwork, sigma, V, UR, partial, pr2, wscratch, gemvpart, vecs, state;
-};
-
+constexpr double U_ROUND = FS_U_ROUND;
+fs_status grow(DevBuf& b, size_t bytes) { return fs_grow(b, bytes); }
+void free_buf(DevBuf& b) { fs_free_buf(b); }
+bool idx16_ok(int d) { return fs_idx16_ok(d); }
+fs_status validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x) {
+  return fs_validate_problem(m, n, A, lda, b, x);
+}
+fs_status validate_options(int64_t m, int32_t n, const fs_options& o) { return fs_validate_options(m, n, o); }
 }  // namespace
 
-struct fs_context_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  int num_cu = 0;
-  int lds_bytes = 0;
-  Workspace ws;
-  DevState* st_host = nullptr;  // pinned copy for read-back
-  hipEvent_t ev[8] = {};
-};
-
-struct fs_sketch_s {
-  fs_context ctx = nullptr;
-  int64_t m = 0;
-  int d = 0, zeta = 0;
-  uint64_t seed = 0;
-  bool idx16 = true;
-  void* idx = nullptr;
-};
-
-namespace {
-
-fs_status grow(DevBuf& b, size_t bytes) {
+fs_status fs_grow(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return FS_OK;
   if (b.p) (void)hipFree(b.p);
@@ -86,38 +62,20 @@ fs_status grow(DevBuf& b, size_t bytes) {
   return FS_OK;
 }
 
-void free_buf(DevBuf& b) {
+void fs_free_buf(DevBuf& b) {
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
 }
 
-#define FS_TRY(expr)                 \
-  do {                               \
-    fs_status s_ = (expr);           \
-    if (s_ != FS_OK) return s_;      \
-  } while (0)
-
-#define FS_K(expr)                                                   \
-  do {                                                               \
-    hipError_t e_ = (expr);                                          \
-    if (e_ != hipSuccess) {                                          \
-      fs_set_last_hip_error(e_, #expr, __FILE__, __LINE__);          \
-      return FS_ERR_DEVICE;                                          \
-    }                                                                \
-  } while (0)
-
-bool idx16_ok(int d) { return d <= 32767; }
-
-fs_status validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x) {
+fs_status fs_validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x) {
   if (!A || !b || !x) return FS_ERR_INVALID_ARG;
   if (n < 1 || m < n || lda < m) return FS_ERR_SHAPE;
   return FS_OK;
 }
 
-fs_status validate_options(int64_t m, int32_t n, const fs_options& o) {
+fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (o.d < n || o.zeta < 1 || o.zeta > o.d || o.zeta > 64) return FS_ERR_SHAPE;
-  if ((int64_t)o.d > m && m > 0 && false) return FS_ERR_SHAPE;
   if (o.kw_every < 1 || o.max_inner < 1 || o.steps < 1 || o.steps > 2) return FS_ERR_INVALID_ARG;
   if (!(o.gamma >= 0) || !(o.rho >= 0) || !(o.tau_factor > 0) || !(o.eta_factor > 0)) return FS_ERR_INVALID_ARG;
   if (o.precond != FS_PRECOND_QR && o.precond != FS_PRECOND_SVD) return FS_ERR_INVALID_ARG;
@@ -126,10 +84,9 @@ fs_status validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (n > 15000) return FS_ERR_TOO_LARGE;       // TRSV keeps x in LDS
   if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
   if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
+  (void)m;
   return FS_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -289,7 +246,7 @@ fs_status sketch_apply(fs_sketch sk, int32_t n, const double* A, int64_t lda, co
     FS_TRY(grow(ctx->ws.colnorm2, sizeof(double) * (n + 1)));
     cn = (double*)ctx->ws.colnorm2.p;
   }
-  FS_K(fs_launch_sketch_apply(A, lda, sk->m, n, b, sk->idx, sk->idx16, sk->d, sk->zeta, Y, ldy, cn,
+  FS_K(fs_launch_sketch_apply(A, lda, sk->m, n, b, sk->m, 1, sk->idx, sk->idx16, sk->d, sk->zeta, Y, ldy, cn,
                               scale_columns != 0, false, ctx->lds_bytes, ctx->stream));
   FS_HIP(hipStreamSynchronize(ctx->stream));
   return FS_OK;
@@ -486,7 +443,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_HIP(hipEventRecord(ev[0], s));
   // ---- sketch (Alg 1 first statement; Alg 4 column scaling in the same read of A)
   FS_K(fs_launch_sketch_indices(m, d, zeta, o.seed, 0, m, W.idx.p, i16, s));
-  FS_K(fs_launch_sketch_apply(A, lda, m, n, b, W.idx.p, i16, d, zeta, Y, d, cn2, o.column_scaling != 0, true,
+  FS_K(fs_launch_sketch_apply(A, lda, m, n, b, m, 1, W.idx.p, i16, d, zeta, Y, d, cn2, o.column_scaling != 0, true,
                               ctx->lds_bytes, s));
   FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
   FS_HIP(hipEventRecord(ev[1], s));

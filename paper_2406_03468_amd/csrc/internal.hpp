@@ -31,11 +31,12 @@ hipError_t fs_launch_pass_kernel_only(const PassArgs& a, const PassConfig& cfg, 
 // Index stream: per source row j, zeta entries (position << 1 | sign_bit), 16- or 32-bit.
 hipError_t fs_launch_sketch_indices(int64_t m, int d, int zeta, uint64_t seed, int64_t col0, int64_t ncols,
                                     void* idx, bool idx16, hipStream_t s);
-// Y[:, j] = (1/sqrt(zeta)) * colscale_j * S[:, :] M[:, j] for the n columns of A and (if b) b;
-// colnorm2[j] = ||A[:, j]||^2 is produced in the same read of A.  If scale_by_norm, column j < n of
-// Y is divided by ||A[:, j]|| (zero columns: by 1).
-hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n, const double* b,
-                                  const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
+// Y[:, j] = (1/sqrt(zeta)) * colscale_j * S M[:, j] for the n columns of A and the nb columns of B
+// (ldb; none when B is null); colnorm2[j] = ||M[:, j]||^2 is produced in the same read (columns of
+// B only if write_bnorm).  If scale_by_norm, column j < n of Y is divided by ||A[:, j]|| (zero
+// columns: by 1).
+hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb,
+                                  int nb, const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
                                   double* colnorm2, bool scale_by_norm, bool write_bnorm, int lds_bytes,
                                   hipStream_t s);
 
@@ -50,6 +51,9 @@ hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int nu
 // x = R^{-1} y (upper, back substitution) or x = R^{-T} y (forward substitution); in place on x.
 hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
                           const double* yscale, const double* xscale, const int* stop, hipStream_t s);
+// nrhs independent solves (one work-group each): Xb[:, r] = R^{-1} Yb[:, r] (or R^{-T}).
+hipError_t fs_launch_trsv_batched(const double* R, int64_t ldr, int n, bool transpose, const double* Yb, int64_t ldy,
+                                  double* Xb, int64_t ldx, int nrhs, hipStream_t s);
 
 // ---------------------------------------------------------------- SVD of R (one-sided Jacobi)
 size_t fs_svd_work_bytes(int n);
@@ -59,3 +63,26 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
                               int* sweeps_out_dev, hipStream_t s);
 hipError_t fs_launch_svd(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
                          void* work, int num_cu, int max_sweeps, int* sweeps_out_dev, hipStream_t s);
+
+// ---------------------------------------------------------------- multi-RHS passes (k <= 64)
+struct MultiPassArgs {
+  const double* A;     // m x n column-major
+  int64_t lda;
+  int64_t m;
+  int n;
+  int k;               // right-hand sides (<= 64); kp = 16 * ceil(k / 16)
+  const double* Zs;    // n x kp row-major, pre-scaled (D^{-1} Z), zero columns beyond k
+  const double* B;     // m x k column-major (ldb): residual mode when non-null
+  int64_t ldb;
+  double* W;           // m x kp row-major scratch
+  double* Vpart;       // [nchunk][n][kp] scratch
+  double* r2part;      // [ceil(m/256)][kp] scratch
+  int64_t rc;          // rows per gather chunk
+  const double* scale; // n (may be null): V rows scaled by it
+  double* V;           // n x kp row-major output
+  double* r2;          // kp output (residual mode): ||b_j - A z_j||^2
+  const int* stop;     // device stop flag (may be null)
+};
+int fs_multi_blocks(int k);
+size_t fs_multi_work_doubles(int64_t m, int n, int k, int64_t* rc_out);
+hipError_t fs_launch_multi_pass(const MultiPassArgs& a, hipStream_t s);

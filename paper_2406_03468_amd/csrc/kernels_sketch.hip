@@ -82,14 +82,20 @@ __global__ __launch_bounds__(256) void k_sketch_indices(int64_t col0, int64_t nc
   }
 }
 
-// One work-group per (column panel, sketch-row chunk).  Column index n denotes b.  PW is the
-// compile-time panel width (columns held in LDS at once); np <= PW columns are active.
-template <typename IDX, int NT, int PW>
+// One work-group per (column panel, sketch-row chunk).  Columns c < n come from A, columns
+// n <= c < ncols from B (ldb).  PW is the compile-time panel width (columns held in LDS at once);
+// np <= PW columns are active.  Each thread walks RU rows per step with all their loads issued
+// before the LDS atomics (memory-level parallelism); for zeta = 8 with 16-bit entries the eight
+// entries of a row come in one 16-byte load.
+template <typename IDX, int NT, int PW, bool Z8>
 __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ A, int64_t lda, int64_t m, int n,
-                                                     const double* __restrict__ b, const IDX* __restrict__ idx,
-                                                     int d, int zeta, int chunk, int ncols,
-                                                     double* __restrict__ Y, int64_t ldy,
-                                                     double* __restrict__ colnorm2, int scale_by_norm, int write_bnorm) {
+                                                     const double* __restrict__ B, int64_t ldb,
+                                                     const IDX* __restrict__ idx, int d, int zeta, int chunk,
+                                                     int ncols, double* __restrict__ Y, int64_t ldy,
+                                                     double* __restrict__ colnorm2, int scale_by_norm,
+                                                     int write_bnorm) {
+  static_assert(!Z8 || sizeof(IDX) == 2, "the 16-byte index load packs eight 16-bit entries");
+  constexpr int RU = PW >= 16 ? 1 : (PW >= 8 ? 2 : 4);  // rows in flight per thread (register budget)
   extern __shared__ double ysh[];  // [PW][chunk]
   __shared__ double sred[NT / 64];
   const int npanels = (ncols + PW - 1) / PW;
@@ -109,26 +115,46 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
 #pragma unroll
   for (int p = 0; p < PW; ++p) {
     const int col = c0 + p;
-    colp[p] = (p < np) ? ((col < n) ? A + (int64_t)col * lda : b) : nullptr;
+    colp[p] = (p < np) ? ((col < n) ? A + (int64_t)col * lda : B + (int64_t)(col - n) * ldb) : nullptr;
     ss[p] = 0.0;
   }
-
-  for (int64_t i = tid; i < m; i += NT) {
-    const IDX* e = idx + i * zeta;
-    double a[PW];
+  auto scatter = [&](uint32_t ev, const double (&a)[PW]) {
+    const int pos = (int)(ev >> 1) - h0;
+    if (pos >= 0 && pos < hc) {
+      const bool neg = (ev & 1u) != 0;
 #pragma unroll
-    for (int p = 0; p < PW; ++p) {
-      a[p] = (p < np) ? colp[p][i] : 0.0;
-      ss[p] = fma(a[p], a[p], ss[p]);
+      for (int p = 0; p < PW; ++p)
+        if (p < np) atomicAdd(&ysh[p * chunk + pos], neg ? -a[p] : a[p]);
     }
-    for (int k = 0; k < zeta; ++k) {
-      const uint32_t ev = (uint32_t)e[k];
-      const int pos = (int)(ev >> 1) - h0;
-      if (pos >= 0 && pos < hc) {
-        const bool neg = (ev & 1u) != 0;
+  };
+
+  for (int64_t i0 = tid; i0 < m; i0 += (int64_t)NT * RU) {
+    double a[RU][PW];
+    uint4 e8[RU];
 #pragma unroll
-        for (int p = 0; p < PW; ++p)
-          if (p < np) atomicAdd(&ysh[p * chunk + pos], neg ? -a[p] : a[p]);
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      const bool ok = i < m;
+#pragma unroll
+      for (int p = 0; p < PW; ++p) a[u][p] = (ok && p < np) ? colp[p][i] : 0.0;
+      if (Z8) e8[u] = ok ? *reinterpret_cast<const uint4*>(idx + i * 8) : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = i0 + (int64_t)u * NT;
+      if (i >= m) break;
+#pragma unroll
+      for (int p = 0; p < PW; ++p) ss[p] = fma(a[u][p], a[u][p], ss[p]);
+      if (Z8) {
+        const uint32_t w4[4] = {e8[u].x, e8[u].y, e8[u].z, e8[u].w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          scatter(w4[q] & 0xFFFFu, a[u]);
+          scatter(w4[q] >> 16, a[u]);
+        }
+      } else {
+        const IDX* e = idx + i * zeta;
+        for (int k = 0; k < zeta; ++k) scatter((uint32_t)e[k], a[u]);
       }
     }
   }
@@ -149,28 +175,40 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
 }
 
 template <typename IDX, int PW>
-void launch_apply_pw(const double* A, int64_t lda, int64_t m, int n, const double* b, const void* idx, int d,
-                     int zeta, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
+void launch_apply_pw(const double* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx,
+                     int d, int zeta, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
                      int nchunks, hipStream_t s) {
   constexpr int NT = 1024;
   const int npanels = (ncols + PW - 1) / PW;
   const size_t shmem = (size_t)PW * chunk * sizeof(double);
-  (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)shmem);
-  hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW>), dim3((unsigned)(npanels * nchunks)), dim3(NT), shmem, s, A, lda,
-                     m, n, b, (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
+  const dim3 grid((unsigned)(npanels * nchunks));
+  if constexpr (sizeof(IDX) == 2) {
+    if (zeta == 8) {
+      (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+      hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, true>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
+                         (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
+      return;
+    }
+  }
+  {
+    (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, false>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
+                       (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
+  }
 }
 
 template <typename IDX>
-void launch_apply(const double* A, int64_t lda, int64_t m, int n, const double* b, const void* idx, int d, int zeta,
-                  int pw, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
+void launch_apply(const double* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx, int d,
+                  int zeta, int pw, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
                   int nchunks, hipStream_t s) {
   switch (pw) {
-    case 16: launch_apply_pw<IDX, 16>(A, lda, m, n, b, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 8: launch_apply_pw<IDX, 8>(A, lda, m, n, b, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 4: launch_apply_pw<IDX, 4>(A, lda, m, n, b, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 2: launch_apply_pw<IDX, 2>(A, lda, m, n, b, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    default: launch_apply_pw<IDX, 1>(A, lda, m, n, b, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 16: launch_apply_pw<IDX, 16>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 8: launch_apply_pw<IDX, 8>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 4: launch_apply_pw<IDX, 4>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 2: launch_apply_pw<IDX, 2>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    default: launch_apply_pw<IDX, 1>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
   }
 }
 
@@ -191,10 +229,11 @@ hipError_t fs_launch_sketch_indices(int64_t m, int d, int zeta, uint64_t seed, i
   return hipGetLastError();
 }
 
-hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n, const double* b, const void* idx,
-                                  bool idx16, int d, int zeta, double* Y, int64_t ldy, double* colnorm2,
-                                  bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s) {
-  const int ncols = n + (b ? 1 : 0);
+hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb,
+                                  int nb, const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
+                                  double* colnorm2, bool scale_by_norm, bool write_bnorm, int lds_bytes,
+                                  hipStream_t s) {
+  const int ncols = n + (B ? nb : 0);
   const int lds_doubles = lds_bytes / 8;
   const int chunk = d < lds_doubles ? d : lds_doubles;
   int fit = lds_doubles / d;  // columns of Y that fit in LDS at once
@@ -202,10 +241,10 @@ hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n
   while (pw * 2 <= fit && pw * 2 <= 16 && pw < ncols) pw *= 2;
   const int nchunks = (d + chunk - 1) / chunk;
   if (idx16)
-    launch_apply<uint16_t>(A, lda, m, n, b, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2, scale_by_norm ? 1 : 0,
-                           write_bnorm ? 1 : 0, nchunks, s);
+    launch_apply<uint16_t>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
+                           scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
   else
-    launch_apply<uint32_t>(A, lda, m, n, b, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2, scale_by_norm ? 1 : 0,
-                           write_bnorm ? 1 : 0, nchunks, s);
+    launch_apply<uint32_t>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
+                           scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
   return hipGetLastError();
 }

@@ -17,8 +17,11 @@ constexpr double U_ROUND = 2.220446049250313e-16;
 // x may alias y.  x_out = xscale .* x (optional); y is read as yscale .* y (optional).
 __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int64_t ldr, int n, int transpose,
                                               const double* y, double* x, const double* __restrict__ yscale,
-                                              const double* __restrict__ xscale, const int* __restrict__ stop) {
+                                              const double* __restrict__ xscale, const int* __restrict__ stop,
+                                              int64_t ldy, int64_t ldx) {
   if (fs_stopped(stop)) return;
+  y += (int64_t)blockIdx.x * ldy;  // batched: right-hand side blockIdx.x
+  x += (int64_t)blockIdx.x * ldx;
   extern __shared__ double xs[];   // n
   __shared__ double dblk[64][65];  // current 64 x 64 diagonal block of R (padded)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -359,7 +362,18 @@ hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, c
     (void)hipFuncSetAttribute((const void*)k_trsv, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL(k_trsv, dim3(1), dim3(VNT), sh, s, R, ldr, n, transpose ? 1 : 0, y, x, yscale, xscale, stop);
+  hipLaunchKernelGGL(k_trsv, dim3(1), dim3(VNT), sh, s, R, ldr, n, transpose ? 1 : 0, y, x, yscale, xscale, stop,
+                     (int64_t)0, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t fs_launch_trsv_batched(const double* R, int64_t ldr, int n, bool transpose, const double* Yb, int64_t ldy,
+                                  double* Xb, int64_t ldx, int nrhs, hipStream_t s) {
+  const size_t sh = (size_t)n * sizeof(double);
+  if (sh > 120 * 1024 || nrhs < 1) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)k_trsv, hipFuncAttributeMaxDynamicSharedMemorySize, 120 * 1024);
+  hipLaunchKernelGGL(k_trsv, dim3((unsigned)nrhs), dim3(VNT), sh, s, R, ldr, n, transpose ? 1 : 0, Yb, Xb,
+                     (const double*)nullptr, (const double*)nullptr, (const int*)nullptr, ldy, ldx);
   return hipGetLastError();
 }
 

@@ -50,3 +50,45 @@ hipError_t fs_vec_set_int(int* p, int v, hipStream_t s);
 hipError_t fs_vec_set_double(double* p, double v, hipStream_t s);
 hipError_t fs_vec_state_init(DevState* st, double alpha, double beta, int max_inner, hipStream_t s);
 hipError_t fs_vec_trmv_t(const double* R, int64_t ldr, int n, const double* t, double* out, hipStream_t s);
+
+// Per-right-hand-side control block of a multi-RHS solve (k <= FS_MULTI_MAX columns).
+constexpr int FS_MULTI_MAX = 64;
+struct MultiState {
+  double thr[FS_MULTI_MAX];     // first-step thresholds
+  double be_sk[FS_MULTI_MAX];   // last sketched KW estimates
+  double r2[FS_MULTI_MAX];      // ||r_j||^2 of the last residual pass
+  double x2[FS_MULTI_MAX];      // ||x_hat_j||^2 at the last KW check
+  double b2[FS_MULTI_MAX];      // ||b_j||^2
+  double cnorm2[FS_MULTI_MAX];  // ||c_j||^2 at the start of the step
+  int active[FS_MULTI_MAX];     // column still iterating in the current step
+  int iters[FS_MULTI_MAX];      // inner iterations of the current step
+  int converged[FS_MULTI_MAX];  // stopped by its rule in the current step
+  int kw_evals[FS_MULTI_MAX];
+  int zero[FS_MULTI_MAX];       // b_j = 0: x_j = 0, never iterated
+  int stop;                     // no active column left
+  int pad[15];
+};
+
+hipError_t fs_m_step_init(int nr, int k, const double* C, double* DY, double* DY_old, MultiState* ms, hipStream_t s);
+hipError_t fs_m_polyak(int nr, int k, const double* C, const double* U, double* DY, double* DY_old, MultiState* ms,
+                       double alpha, double beta, bool first_step, hipStream_t s);
+hipError_t fs_m_update_stop(int k, MultiState* ms, hipStream_t s);
+hipError_t fs_m_first_threshold(int n, int k, const double* X0, MultiState* ms, double gamma, double rho,
+                                double normest, double condest, hipStream_t s);
+hipError_t fs_m_kw(int n, int k, const double* Wv, const double* sigma, MultiState* ms, double fro2, double fro_u,
+                   hipStream_t s);
+hipError_t fs_m_add_norm(int n, int k, const double* X, const double* Z, double* out, MultiState* ms, hipStream_t s);
+// Zs[c * kp + j] = scale[c] X[c + j ldxin] (zero for j >= k)
+hipError_t fs_m_to_panel(int n, int k, const double* X, int64_t ldxin, const double* scale, double* Zs,
+                         const int* stop, hipStream_t s);
+hipError_t fs_m_init_columns(int n, int k, const double* colnorm2, MultiState* ms, hipStream_t s);
+hipError_t fs_m_unscale(int n, int k, const double* X, const double* dinv, double* Xout, int64_t ldx, hipStream_t s);
+// out(c, j) = oscale[c] * (sum_{i < nr} V[c, i] Y[i, j] / sigma[i] + addX[c, j]);  Y: nr x k (ld nr),
+// addX: n x k (ld n, may be null), out: n x k (ld n) or, if panel, n x kp row-major.
+hipError_t fs_m_gemm_P(const double* V, int64_t ldv, int n, int nr, int k, const double* sigma, const double* Y,
+                       const double* addX, const double* oscale, double* out, bool panel, const int* stop,
+                       hipStream_t s);
+// U[i, j] = (sum_c V[c, i] G(c, j)) / sigma[i] (sigma may be null);  G: n x kp row-major panel;
+// U: nr x k (ld nr).
+hipError_t fs_m_gemm_PT(const double* V, int64_t ldv, int n, int nr, int k, const double* sigma, const double* G,
+                        double* U, const int* stop, hipStream_t s);

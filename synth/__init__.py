@@ -14,6 +14,7 @@ the sphere of the requested radius inside the orthogonal complement of ``range(A
 from .problems import (  # noqa: F401
     Problem,
     make_problem,
+    make_multi_problem,
     make_problem_torch,
     log_spaced_sigma,
     haar_cholqr2,

@@ -105,6 +105,30 @@ def make_problem(m: int, n: int, kappa: float, resid_norm: float, seed: int,
                    meta={"generator": "numpy", "r_perp": r if keep_U else None})
 
 
+def make_multi_problem(m: int, n: int, kappa: float, resid_norms, k: int, seed: int) -> Problem:
+    """CPU generator with k right-hand sides sharing A (same recipe as ``make_problem``):
+    column j of B is A x_j + r_j with x_j ~ N(0, I_n) and r_j perpendicular to range(A), of norm
+    resid_norms[j % len(resid_norms)] (0 gives b_j = A x_j exactly in exact arithmetic).
+    ``meta["B"]`` (m x k, Fortran order) and ``meta["X_true"]`` (n x k) hold them."""
+    rng = np.random.default_rng(seed)
+    U = _haar(rng, m, n)
+    V = _haar(rng, n, n)
+    sigma = log_spaced_sigma(n, kappa)
+    A = np.asfortranarray((U * sigma) @ V.T)
+    norms = list(resid_norms)
+    Xt = rng.standard_normal((n, k))
+    G = rng.standard_normal((m, k))
+    Rp = G - U @ (U.T @ G)
+    Rp = Rp - U @ (U.T @ Rp)
+    for j in range(k):
+        nr = np.linalg.norm(Rp[:, j])
+        Rp[:, j] *= norms[j % len(norms)] / nr if nr > 0 else 0.0
+    B = np.asfortranarray(A @ Xt + Rp)
+    return Problem(A=A, b=B[:, 0].copy(), x_true=Xt[:, 0].copy(), sigma=sigma, V=V, kappa=float(kappa),
+                   resid_norm=float(norms[0]), seed=int(seed), U=U if m * n <= 4_000_000 else None,
+                   meta={"generator": "numpy", "B": B, "X_true": Xt, "rhs_resid_norms": norms})
+
+
 def make_problem_torch(m: int, n: int, kappa: float, resid_norm: float, seed: int,
                        device: str = "cuda", nrhs: int = 0, rhs_resid_norms=None) -> Problem:
     """Device-side generator for the large (1e6 x 1e3) problems.

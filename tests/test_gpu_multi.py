@@ -1,0 +1,101 @@
+"""Multi-RHS FOSSILS on the GPU (k right-hand sides sharing A, passes on the FP64 matrix cores)
+against the per-column CPU oracle (same sketch seed: column j of the multi solve sees exactly the
+sketch [S A, S b_j] of the single-column method).
+
+Bar per column: relative backward error <= 1e-14 and forward error within 10x of Householder QR's
+(floored at kappa u, as for the single-RHS tests); iteration counts within a few of the oracle's.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import dev_colmajor, host
+from oracle import backward_error as be
+from oracle import householder as hh
+from oracle import solvers
+from synth import make_multi_problem
+
+pytestmark = pytest.mark.gpu
+U = 2.0**-52
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_03468_amd import binding
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _multi(ctx, A, B, **kw):
+    import torch
+    from paper_2406_03468_amd import binding
+    m, n = A.shape
+    k = B.shape[1]
+    o = binding.fs_options_default(m, n)
+    for key, v in kw.items():
+        setattr(o, key, v)
+    X = torch.zeros((k, n), dtype=torch.float64, device="cuda").t()  # (n, k) column-major
+    status, infos = binding.fossils_solve_multi(ctx, dev_colmajor(A), dev_colmajor(B), X, o)
+    return status, infos, host(X)
+
+
+def _fe(x, xt):
+    return np.linalg.norm(x - xt) / np.linalg.norm(xt)
+
+
+@pytest.mark.parametrize("m,n,k,kappa", [(4000, 50, 5, 1e10), (4000, 50, 64, 1e12), (10007, 130, 17, 1e8),
+                                         (3001, 37, 1, 1e6), (20000, 300, 33, 1e10)])
+def test_multi_rhs_vs_oracle(ctx, m, n, k, kappa):
+    P = make_multi_problem(m, n, kappa, [1e-10, 1e-4, 1.0, 1e-6], k, seed=4)
+    B, Xt = P.meta["B"], P.meta["X_true"]
+    status, infos, X = _multi(ctx, P.A, B)
+    assert status == 0, [f.to_dict() for f in infos]
+    cols = range(k) if k <= 8 else [0, 1, 2, 3, k // 2, k - 1]
+    for j in cols:
+        bg = be.relative_backward_error(P.A, B[:, j], X[:, j], P.sigma, P.V)
+        assert bg <= 1e-14, (j, bg, infos[j].to_dict())
+        xq = hh.qr_lstsq(P.A, B[:, j]) if m * n <= 2_000_000 else hh.qr_lstsq_lapack(P.A, B[:, j])
+        fref = max(_fe(xq, Xt[:, j]), kappa * U)
+        assert _fe(X[:, j], Xt[:, j]) <= 10 * fref, (j, _fe(X[:, j], Xt[:, j]), fref)
+    # iteration counts and sketch statistics against the oracle's single-column solves
+    for j in list(cols)[:3]:
+        ref = solvers.fossils(P.A, B[:, j], solvers.Options(precond="svd"))
+        assert abs(infos[j].iters[0] - ref.iters[0]) <= 3, (j, list(infos[j].iters), ref.iters)
+        assert abs(infos[j].iters[1] - ref.iters[1]) <= 6, (j, list(infos[j].iters), ref.iters)
+        assert abs(infos[j].normest - ref.normest) <= 1e-12 * ref.normest
+
+
+def test_multi_matches_single_gpu(ctx):
+    """Each column of the multi solve is as accurate as the single-RHS GPU solve of that column."""
+    import torch
+    from paper_2406_03468_amd import binding
+    P = make_multi_problem(6000, 80, 1e9, [1e-8, 1e-2], 6, seed=9)
+    B = P.meta["B"]
+    _, infos, X = _multi(ctx, P.A, B)
+    A = dev_colmajor(P.A)
+    for j in range(6):
+        x = torch.zeros(80, dtype=torch.float64, device="cuda")
+        binding.fossils_solve(ctx, A, torch.as_tensor(B[:, j].copy(), device="cuda"), x)
+        b_single = be.relative_backward_error(P.A, B[:, j], host(x), P.sigma, P.V)
+        b_multi = be.relative_backward_error(P.A, B[:, j], X[:, j], P.sigma, P.V)
+        assert b_multi <= max(10 * b_single, 1e-15), (j, b_multi, b_single)
+
+
+def test_multi_zero_column_and_edge_cases(ctx):
+    from paper_2406_03468_amd import binding
+    P = make_multi_problem(3000, 40, 1e6, [1e-3], 4, seed=2)
+    B = P.meta["B"].copy()
+    B[:, 2] = 0.0
+    status, infos, X = _multi(ctx, P.A, B)
+    assert status == 0
+    assert np.all(X[:, 2] == 0.0)
+    for j in (0, 1, 3):
+        assert be.relative_backward_error(P.A, B[:, j], X[:, j], P.sigma, P.V) <= 1e-14
+    with pytest.raises(binding.FossilsError) as e:  # k beyond the multi limit
+        _multi(ctx, P.A, np.zeros((3000, 65)))
+    assert e.value.status == binding.FS_ERR_SHAPE
+    B[5, 1] = np.nan
+    with pytest.raises(binding.FossilsError) as e:
+        _multi(ctx, P.A, B)
+    assert e.value.status == binding.FS_ERR_NONFINITE

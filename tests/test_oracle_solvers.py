@@ -197,3 +197,17 @@ def test_planted_mistakes_are_caught(monkeypatch):
     res = solvers.fossils(P.A, P.b)
     bad = be.relative_backward_error(P.A, P.b, res.x, P.sigma, P.V)
     assert res.flags & solvers.FLAG_NOT_CONVERGED or bad > 1e-14 or sum(res.iters) > 60
+
+
+def test_multi_rhs_generator_and_oracle():
+    """Multi-RHS inputs: every column of B = A X + R has R perpendicular to range(A) with the
+    requested norm, and the per-column oracle solves reach the backward-stable bar."""
+    from synth import make_multi_problem
+    P = make_multi_problem(3000, 30, 1e8, [1e-6, 1.0, 0.0], 4, seed=3)
+    B, Xt = P.meta["B"], P.meta["X_true"]
+    Rr = B - P.A @ Xt
+    assert np.allclose(np.linalg.norm(Rr, axis=0), [1e-6, 1.0, 0.0, 1e-6], rtol=1e-6, atol=1e-12)
+    assert np.max(np.abs(P.U.T @ Rr)) <= 1e-12
+    res = solvers.fossils_multi(P.A, B)
+    for j, r in enumerate(res):
+        assert be.relative_backward_error(P.A, B[:, j], r.x, P.sigma, P.V) <= 1e-14
