@@ -45,8 +45,9 @@ def parse():
     ap.add_argument("--precond", default="svd", choices=["qr", "svd"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=8)
+    ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--pass-repeats", type=int, default=20)
+    ap.add_argument("--multi", type=int, default=64, help="right-hand sides of the multi-RHS line (0: skip)")
     return ap.parse_args()
 
 
@@ -117,6 +118,34 @@ def main():
                 "kernel": "k_fused_pass (v = A^T(A z), H=16 rows x 1000 cols per tile)",
                 "ms_kernel": round(ms_kernel, 4), "ms_pass_with_reduction": round(ms_pass, 4)}
 
+    # ---- multi-RHS form: one solve for k right-hand sides sharing A (k = 64, C3 shapes)
+    multi = None
+    if args.multi > 0:
+        km = args.multi
+        PM = make_problem_torch(M, N, KAPPA, RESID[1], seed=1, nrhs=km, rhs_resid_norms=RESID)
+        Bm = PM.meta["B"]
+        Xm = torch.zeros((km, N), dtype=torch.float64, device=dev).t()
+        optm = binding.fs_options_default(M, N)
+        binding.fossils_solve_multi(ctx, PM.A, Bm, Xm, optm)  # warm-up
+        torch.cuda.synchronize()
+        tm = []
+        for _ in range(2):
+            t1 = time.perf_counter()
+            stm, infm = binding.fossils_solve_multi(ctx, PM.A, Bm, Xm, optm)
+            tm.append(time.perf_counter() - t1)
+        ms_multi = 1e3 * min(tm)
+        z64 = torch.randn((km, N), dtype=torch.float64, device=dev).t()
+        multi = {"k": km, "ms_per_solve": round(ms_multi, 2), "ms_per_rhs": round(ms_multi / km, 3),
+                 "status": int(stm), "iters": [list(f.iters) for f in infm[:4]],
+                 "max_iters": [max(f.iters[0] for f in infm), max(f.iters[1] for f in infm)],
+                 "phase_ms": [round(p, 2) for p in infm[0].phase_ms]}
+        print(f"# multi-RHS k={km}: {ms_multi:.1f} ms per solve ({ms_multi / km:.2f} ms per right-hand side), "
+              f"status {stm}, max iters {multi['max_iters']}", file=sys.stderr, flush=True)
+        multi_check = (PM, Bm, Xm)
+        del z64
+    else:
+        multi_check = None
+
     # ---- accuracy (CPU, long double; outside the timed region)
     accuracy = None
     Ah = None
@@ -139,6 +168,19 @@ def main():
             print(f"# accuracy problem {i}: BE {bek:.3e} FE {fe:.3e} (Wedin scale {wedin:.3e})", file=sys.stderr,
                   flush=True)
             del A_i
+        if multi_check is not None:  # two columns of the multi-RHS solve, known-SVD KW
+            PM, Bm, Xm = multi_check
+            A_m = PM.A.cpu().numpy()
+            fro = np.sqrt(np.sum(A_m * A_m))
+            bes = []
+            for j in (0, args.multi - 1):
+                b_j = Bm[:, j].cpu().numpy()
+                x_j = Xm[:, j].cpu().numpy()
+                theta = fro / np.linalg.norm(b_j)
+                bes.append(float(be.kw_known_svd(A_m, b_j, x_j, PM.sigma, PM.V, theta) / fro))
+            multi["be_checked_columns"] = bes
+            print(f"# multi-RHS accuracy (columns 0, k-1): BE {bes}", file=sys.stderr, flush=True)
+            del A_m
 
     # ---- CPU baseline: the oracle's heavy-ball iterations (Algorithm 5) on the same problem
     cpu = None
@@ -179,6 +221,7 @@ def main():
         "iters": iters, "kw_evals": [inf.kw_evals for _, _, inf in infos],
         "phase_ms_last": [round(p, 3) for p in infos[-1][2].phase_ms],
         "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy,
+        "multi_rhs": multi,
         "serving": None,
     }
     print(json.dumps(out), flush=True)

@@ -44,12 +44,13 @@ typedef enum fs_status {
   FS_ERR_DEVICE = -4,          /* a HIP call failed (see fs_last_error_detail) */
   FS_ERR_NONFINITE = -5,       /* A or b holds NaN or Inf */
   FS_ERR_TOO_LARGE = -6,       /* size beyond what this build supports (n > 15000, d > 65536) */
-  FS_ERR_UNKNOWN_TICKET = -7,
+  FS_ERR_UNKNOWN_TICKET = -7,  /* batched_poll / fs_server_ticket_times: no such ticket */
   FS_ERR_UNSUPPORTED = -8
 } fs_status;
 
 typedef struct fs_context_s* fs_context;
 typedef struct fs_sketch_s* fs_sketch;
+typedef struct fs_server_s* fs_server;
 
 enum { FS_PRECOND_QR = 0, FS_PRECOND_SVD = 1 };
 enum { FS_FP64 = 0, FS_MIXED = 1 };
@@ -179,6 +180,45 @@ fs_status fs_time_normal_pass(fs_context ctx, int64_t m, int32_t n, const double
  * substitution) for upper-triangular R (ldr >= n); x may equal y.  n <= 15000. */
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
                   double* x);
+
+/* ---------------- serving: many independent solves on one GPU ---------------- */
+
+/* A solve request.  A (m x n, lda >= m), b (m) and x (n) are device arrays owned by the caller;
+ * they must stay valid (and A, b unchanged) until batched_poll reports the ticket done.  method:
+ * FS_METHOD_FOSSILS or FS_METHOD_SPIR.  opts may be NULL (defaults); it is copied at submission. */
+enum { FS_METHOD_FOSSILS = 0, FS_METHOD_SPIR = 1 };
+typedef struct {
+  int32_t method;
+  int64_t m;
+  int32_t n;
+  const double* A;
+  int64_t lda;
+  const double* b;
+  double* x;
+  const fs_options* opts;
+} fs_request;
+
+/* A server on the device of ctx: max_slots worker slots (1..16), each with its own stream and
+ * workspace, take requests from one FIFO queue as they free up (continuous batching), so the
+ * passes of different solves overlap on the GPU; the cooperative QR/SVD kernels of different slots
+ * are serialized (a cooperative grid must be fully resident).  hbm_budget bounds the workspace:
+ * each slot may use hbm_budget / max_slots bytes, and a request whose workspace footprint exceeds
+ * that share is refused at submission with FS_ERR_TOO_LARGE. */
+fs_status fs_server_create(fs_context ctx, size_t hbm_budget, int32_t max_slots, fs_server* out);
+/* Finishes every queued request, then frees the slots. */
+fs_status fs_server_destroy(fs_server srv);
+/* Non-blocking: validate and enqueue; *ticket identifies the request. */
+fs_status batched_submit(fs_server srv, const fs_request* req, uint64_t* ticket);
+/* Non-blocking: *done = 1 once the solve has finished; then *result is its status (as returned by
+ * fossils_solve / spir_solve) and *info (if not NULL) its record. */
+fs_status batched_poll(fs_server srv, uint64_t ticket, int32_t* done, fs_status* result, fs_info* info);
+/* Blocks until the ticket is done. */
+fs_status fs_server_wait(fs_server srv, uint64_t ticket);
+/* Seconds on the server's steady clock at submission, start on a slot and completion (-1 if not
+ * yet reached). */
+fs_status fs_server_ticket_times(fs_server srv, uint64_t ticket, double* submit_s, double* start_s, double* finish_s);
+/* Workspace bytes one slot needs for an m x n solve with options opts (NULL: defaults). */
+size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts);
 
 #ifdef __cplusplus
 }

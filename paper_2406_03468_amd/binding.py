@@ -59,6 +59,15 @@ class FsInfo(ctypes.Structure):
         }
 
 
+class FsRequest(ctypes.Structure):
+    _fields_ = [("method", c_int32), ("m", c_int64), ("n", c_int32), ("A", c_vp), ("lda", c_int64), ("b", c_vp),
+                ("x", c_vp), ("opts", ctypes.POINTER(FsOptions))]
+
+
+FS_METHOD_FOSSILS = 0
+FS_METHOD_SPIR = 1
+
+
 class FossilsError(RuntimeError):
     def __init__(self, status, detail=""):
         self.status = status
@@ -80,6 +89,15 @@ _SIGS = [
                              ctypes.POINTER(FsInfo)]),
     ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
+    ("fs_server_create", c_int32, [c_vp, ctypes.c_size_t, c_int32, ctypes.POINTER(c_vp)]),
+    ("fs_server_destroy", c_int32, [c_vp]),
+    ("batched_submit", c_int32, [c_vp, ctypes.POINTER(FsRequest), ctypes.POINTER(c_uint64)]),
+    ("batched_poll", c_int32, [c_vp, c_uint64, ctypes.POINTER(c_int32), ctypes.POINTER(c_int32),
+                               ctypes.POINTER(FsInfo)]),
+    ("fs_server_wait", c_int32, [c_vp, c_uint64]),
+    ("fs_server_ticket_times", c_int32, [c_vp, c_uint64, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
+                                         ctypes.POINTER(c_double)]),
+    ("fs_solve_footprint", ctypes.c_size_t, [c_int64, c_int32, ctypes.POINTER(FsOptions)]),
     ("sketch_create", c_int32, [c_vp, c_int64, c_int32, c_int32, c_uint64, ctypes.POINTER(c_vp)]),
     ("sketch_destroy", c_int32, [c_vp]),
     ("sketch_indices", c_int32, [c_vp, c_int64, c_int64, c_vp, c_vp]),
@@ -212,6 +230,63 @@ def fossils_solve_multi(ctx: Context, A, B, X, opts: Optional[FsOptions] = None)
                                    ctypes.byref(opts) if opts is not None else None, infos)
     _check(s)
     return s, list(infos)
+
+
+class Server:
+    """fs_server: worker slots draining a FIFO of solve requests (continuous batching)."""
+
+    def __init__(self, ctx: Context, hbm_budget: int, max_slots: int = 4):
+        h = c_vp()
+        _check(load().fs_server_create(ctx.h, ctypes.c_size_t(int(hbm_budget)), int(max_slots), ctypes.byref(h)))
+        self.h = h
+        self._keep = {}  # ticket -> tensors that must outlive the solve
+
+    def close(self):
+        if self.h:
+            _check(load().fs_server_destroy(self.h))
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        try:
+            if not _finalizing():
+                self.close()
+        except Exception:
+            pass
+
+
+def batched_submit(srv: Server, A, b, x, method: int = FS_METHOD_FOSSILS, opts: Optional[FsOptions] = None) -> int:
+    m, n = A.shape
+    req = FsRequest(int(method), int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(x)),
+                    ctypes.pointer(opts) if opts is not None else None)
+    t = c_uint64(0)
+    _check(load().batched_submit(srv.h, ctypes.byref(req), ctypes.byref(t)))
+    srv._keep[t.value] = (A, b, x, opts)
+    return t.value
+
+
+def batched_poll(srv: Server, ticket: int):
+    """(done, status, FsInfo or None)."""
+    done, res, info = c_int32(0), c_int32(0), FsInfo()
+    _check(load().batched_poll(srv.h, c_uint64(ticket), ctypes.byref(done), ctypes.byref(res), ctypes.byref(info)))
+    if done.value:
+        srv._keep.pop(ticket, None)
+        return True, res.value, info
+    return False, None, None
+
+
+def fs_server_wait(srv: Server, ticket: int):
+    _check(load().fs_server_wait(srv.h, c_uint64(ticket)))
+
+
+def fs_server_ticket_times(srv: Server, ticket: int):
+    a, b_, c = c_double(), c_double(), c_double()
+    _check(load().fs_server_ticket_times(srv.h, c_uint64(ticket), ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c)))
+    return a.value, b_.value, c.value
+
+
+def fs_solve_footprint(m: int, n: int, opts: Optional[FsOptions] = None) -> int:
+    return int(load().fs_solve_footprint(int(m), int(n), ctypes.byref(opts) if opts is not None else None))
 
 
 class Sketch:

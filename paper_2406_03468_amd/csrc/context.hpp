@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "../../include/fossils.h"
 #include "common.hpp"
@@ -30,6 +31,21 @@ struct fs_context_s {
   Workspace ws;
   DevState* st_host = nullptr;  // pinned copy for read-back
   hipEvent_t ev[8] = {};
+  // Set by a server whose slots share the GPU: cooperative kernels (QR, SVD) of different
+  // contexts must not run concurrently (each grid has to be fully resident).
+  std::mutex* coop_lock = nullptr;
+};
+
+// Holds the cooperative-kernel lock of ctx (if any) until the context's stream has drained.
+struct CoopSection {
+  fs_context_s* ctx;
+  std::unique_lock<std::mutex> lk;
+  explicit CoopSection(fs_context_s* c) : ctx(c) {
+    if (c->coop_lock) lk = std::unique_lock<std::mutex>(*c->coop_lock);
+  }
+  ~CoopSection() {
+    if (lk.owns_lock()) (void)hipStreamSynchronize(ctx->stream);
+  }
 };
 
 struct fs_sketch_s {

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -365,6 +366,22 @@ fs_status fs_time_normal_pass(fs_context ctx, int64_t m, int32_t n, const double
   return FS_OK;
 }
 
+size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts) {
+  fs_options o;
+  if (opts) o = *opts;
+  else if (fs_options_default(m, n, &o) != FS_OK) return 0;
+  if (n < 1 || m < n || o.d < n) return 0;
+  const size_t d = (size_t)o.d, k = (size_t)n + 1, N = (size_t)n;
+  const PassConfig cfg = fs_pass_config(m, n, 256);
+  size_t b = (size_t)m * o.zeta * (fs_idx16_ok(o.d) ? 2 : 4);  // index stream
+  b += 8 * d * k;                                                // sketch Y
+  b += fs_qr_work_bytes(o.d, (int)k, 256) + fs_svd_work_bytes(n);
+  b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 16 * N);  // V, U_R, vectors
+  b += 8 * ((size_t)cfg.G * N + cfg.G + 64) + sizeof(DevState) + 64;
+  if (!cfg.H) b += 8 * (size_t)m;
+  return b;
+}
+
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
                   double* x) {
   if (!ctx || !R || !y || !x) return FS_ERR_INVALID_ARG;
@@ -447,7 +464,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
                               ctx->lds_bytes, s));
   FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
   FS_HIP(hipEventRecord(ev[1], s));
-  // ---- QR of the sketch
+  // ---- QR of the sketch (cooperative kernels: serialized against other slots of a server)
+  std::unique_ptr<CoopSection> coop(new CoopSection(ctx));
   FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
   FS_HIP(hipEventRecord(ev[2], s));
   // ---- SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate)
@@ -462,6 +480,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   int svd_sweeps = 0;
   FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
   FS_HIP(hipStreamSynchronize(s));
+  coop.reset();
   for (int j = 0; j <= n; ++j)
     if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
   const double b2 = cnh[n];
@@ -486,6 +505,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     use_svd = true;
     // the truncated start x_0 = V_r Sigma_r^{-1} U_r^T t needs U_R: redo the SVD accumulating it
     // (rank-deficient problems only)
+    CoopSection cs(ctx);
     FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev, s));
   }
   inf.rank = rk;

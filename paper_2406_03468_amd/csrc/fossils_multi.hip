@@ -11,6 +11,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
@@ -96,6 +97,7 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
                               true, ctx->lds_bytes, s));
   FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
   FS_HIP(hipEventRecord(ev[1], s));
+  std::unique_ptr<CoopSection> coop(new CoopSection(ctx));
   FS_K(fs_launch_qr(Y, d, d, kc, W.qrwork.p, ctx->num_cu, s));
   FS_HIP(hipEventRecord(ev[2], s));
   FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev,
@@ -108,6 +110,7 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
   int svd_sweeps = 0;
   FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
   FS_HIP(hipStreamSynchronize(s));
+  coop.reset();
   for (int j = 0; j < kc; ++j)
     if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
   const DevState hs = *ctx->st_host;
@@ -118,6 +121,7 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
   if (!(hs.condest <= 1.0 / (o.tau_factor * FS_U_ROUND))) {  // Alg 4: numerically rank deficient
     flags |= 1;
     nr = hs.rank_trunc > 0 ? hs.rank_trunc : 1;
+    CoopSection cs(ctx);
     FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev,
                             s));
     // x_0 = V_r Sigma_r^{-1} U_r^T t_j: U_r^T T (as P^T with sigma = 1), then V_r Sigma_r^{-1}

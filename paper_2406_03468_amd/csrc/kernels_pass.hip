@@ -66,13 +66,13 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
   __syncthreads();
 
   // Lane byte offsets inside a column slot (32-bit, so loads use a scalar base + vector offset);
-  // the host guarantees CPR * lda * 8 + H * 8 < 2^32 on this path.  Only the last slot can hold
-  // columns >= n; such lanes re-read the slot's first column (always < n): their z entry is zero
-  // and their sums are never written, so full tiles load with no per-lane predicate.
+  // the host guarantees CPR * lda * 8 + H * 8 < 2^32 on this path.  L is exactly ceil(n / CPR)
+  // (the launcher instantiates every value), so only the last slot holds columns >= n; its lanes
+  // beyond n re-read the slot's first column (< n): their z entry is zero and their sums are never
+  // written, so every load stays inside A and full tiles need no per-lane branch.
   const uint32_t voff = (uint32_t)(((int64_t)cb * lda + 2 * rp) * (int64_t)sizeof(double));
-  const uint32_t voffL =
-      (uint32_t)(((int64_t)((cb + (L - 1) * CPR) < n ? cb : 0) * lda + 2 * rp) * (int64_t)sizeof(double));
   const uint32_t boff = (uint32_t)(2 * rp * sizeof(double));
+  const uint32_t voffL = (cb + (L - 1) * CPR < n) ? voff : boff;
   auto ld2 = [&](const char* p) -> double2 {
     if (VEC) return *reinterpret_cast<const double2*>(p);
     const double* q = reinterpret_cast<const double*>(p);
@@ -276,16 +276,27 @@ hipError_t launch_one(const PassArgs& a, int G, bool vec, hipStream_t s) {
   return hipGetLastError();
 }
 
+// L must equal ceil(n / CPR) exactly (see the kernel): dispatch over [LO, HI].
+template <int H, int NT, bool RESID, int LO, int HI>
+hipError_t launch_exact(const PassArgs& a, int G, bool vec, int L, hipStream_t s) {
+  if constexpr (LO > HI) {
+    return hipErrorInvalidValue;
+  } else {
+    if (L == LO) return launch_one<H, NT, LO, RESID>(a, G, vec, s);
+    return launch_exact<H, NT, RESID, LO + 1, HI>(a, G, vec, L, s);
+  }
+}
+
 template <int H, int NT, bool RESID>
 hipError_t launch_L(const PassArgs& a, int G, bool vec, hipStream_t s) {
   constexpr int CPR = NT / (H / 2);
   const int L = (a.n + CPR - 1) / CPR;
-  if (L <= 1) return launch_one<H, NT, 1, RESID>(a, G, vec, s);
-  if (L <= 2) return launch_one<H, NT, 2, RESID>(a, G, vec, s);
-  if (L <= 4) return launch_one<H, NT, 4, RESID>(a, G, vec, s);
-  if (L <= 8) return launch_one<H, NT, 8, RESID>(a, G, vec, s);
-  if (L <= 12) return launch_one<H, NT, 12, RESID>(a, G, vec, s);
-  return launch_one<H, NT, 16, RESID>(a, G, vec, s);
+  // ranges of L each tile height serves (fs_pass_config): 64: n <= 64; 32: 64 < n <= 256;
+  // 16: 256 < n <= 1024; 8: 1024 < n <= 2048; 4: 2048 < n <= 4096 (direct calls may go lower)
+  if constexpr (H == 64) return launch_exact<H, NT, RESID, 1, 4>(a, G, vec, L, s);
+  if constexpr (H == 32) return launch_exact<H, NT, RESID, 1, 8>(a, G, vec, L, s);
+  if constexpr (H == 16) return launch_exact<H, NT, RESID, 1, 16>(a, G, vec, L, s);
+  return launch_exact<H, NT, RESID, 5, 16>(a, G, vec, L, s);
 }
 
 template <bool RESID>

@@ -73,3 +73,19 @@ def test_missing_library_fails_loudly(tmp_path):
     from paper_2406_03468_amd import binding
     with pytest.raises(FileNotFoundError):
         binding.load(str(tmp_path / "nope.so"))
+
+
+def test_solve_footprint_and_server_validation(clib):
+    """Workspace footprint used for serving admission: positive, growing with m and n; invalid
+    shapes give 0.  Server creation validates its arguments before touching the device."""
+    from paper_2406_03468_amd import binding
+    f1 = binding.fs_solve_footprint(100_000, 100)
+    f2 = binding.fs_solve_footprint(200_000, 100)
+    f3 = binding.fs_solve_footprint(100_000, 200)
+    assert 0 < f1 < f2 and f1 < f3
+    # the index stream (m zeta 2 bytes) and the sketch (12 n x (n+1) doubles) are both counted
+    assert f1 >= 100_000 * 8 * 2 + 8 * 1200 * 101
+    assert binding.fs_solve_footprint(10, 20) == 0
+    h = ctypes.c_void_p()
+    assert clib.fs_server_create(None, 1 << 30, 2, ctypes.byref(h)) == binding.FS_ERR_INVALID_ARG
+    assert clib.batched_submit(None, None, None) == binding.FS_ERR_INVALID_ARG

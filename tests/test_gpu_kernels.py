@@ -185,6 +185,43 @@ def test_residual_pass_matches_oracle(ctx, m, n):
     assert abs(r2 - r2r) <= 1e-10 * r2r + 1e-12 * np.linalg.norm(b) ** 2
 
 
+def _nan_fenced(A, ld, extra_cols):
+    """A inside a device buffer whose padding rows (m..ld-1) and trailing columns are NaN: any read
+    outside A shows up as NaN in the result instead of touching foreign memory."""
+    import torch
+    m, n = A.shape
+    buf = torch.full((n + extra_cols, ld), float("nan"), dtype=torch.float64, device="cuda")
+    buf[:n, :m] = torch.as_tensor(np.ascontiguousarray(A.T), device="cuda")
+    return buf[:n, :m].t()  # (m, n) view, column-major, leading dimension ld
+
+
+# n chosen so that ceil(n / columns-per-round) falls between the powers of two for every tile
+# height (65..97 -> 3 slots at H = 32, 130/150 -> 5, 300 -> 5 at H = 16, 700 -> 11, 1500 -> 12, 2100 -> 9)
+FENCE_SHAPES = [(6001, 20, 0), (6001, 65, 0), (6001, 97, 2), (5003, 130, 1), (5003, 150, 0), (4001, 300, 3),
+                (4001, 700, 0), (3001, 1500, 1), (2500, 2100, 0)]
+
+
+@pytest.mark.parametrize("m,n,pad", FENCE_SHAPES)
+def test_passes_stay_inside_A(ctx, m, n, pad):
+    from oracle.solvers import normal_pass, residual_pass
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((m, n))
+    z = rng.standard_normal(n)
+    b = A @ z + rng.standard_normal(m)
+    Ad = _nan_fenced(A, m + pad, extra_cols=300)
+    v = dev_vec(np.zeros(n))
+    binding.fs_normal_pass(ctx, Ad, dev_vec(z), v)
+    vh = host(v)
+    assert np.all(np.isfinite(vh))
+    assert np.all(np.abs(vh - normal_pass(A, z)) <= _pass_bound(A, z))
+    g = dev_vec(np.zeros(n))
+    r2 = binding.fs_residual_pass(ctx, Ad, dev_vec(b), dev_vec(z), g)
+    gr, r2r = residual_pass(A, b, z)
+    assert np.all(np.isfinite(host(g))) and np.isfinite(r2)
+    assert abs(r2 - r2r) <= 1e-10 * r2r
+
+
 def test_normal_pass_full_size(ctx):
     """The launch configuration of the 1e6 x 1000 solve, against numpy on the host."""
     import torch
