@@ -48,12 +48,105 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=100)
     ap.add_argument("--pass-repeats", type=int, default=20)
     ap.add_argument("--multi", type=int, default=64, help="right-hand sides of the multi-RHS line (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=2048, help="requests of the serving line (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
     return ap.parse_args()
 
 
 def passes_of(info) -> int:
     # sketch + residual pass per step + inner iterations + one residual pass per KW check
     return 1 + 2 + info.iters[0] + info.iters[1] + info.kw_evals
+
+
+def serve_bench(ctx, args, dev):
+    """Served stream (C5 shapes): requests with m ~ U[5000, 300000], n ~ U[20, 500] (m >= 20 n),
+    kappa = 10^U[2,12], ||r_perp|| log-uniform in [1e-12, 1], FOSSILS and SPIR alternating.  The
+    requests cycle through a pool of distinct device-resident problems (the whole stream, ~650 GB,
+    does not fit in HBM); every request has its own output vector.  Saturated throughput: all
+    requests submitted at once.  Latency: Poisson arrivals at 0.8 x the saturated rate, latency =
+    completion - submission on the server's clock; p50 / p99 over the requests."""
+    import numpy as np
+    import torch
+
+    from paper_2406_03468_amd import binding
+    from synth import make_problem_torch
+
+    rng = np.random.default_rng(2024)
+    pool = []
+    t0 = time.time()
+    for i in range(args.serve_pool):
+        while True:
+            m = int(rng.integers(5000, 300001))
+            n = int(rng.integers(20, 501))
+            if m >= 20 * n:
+                break
+        kappa = 10.0 ** rng.uniform(2, 12)
+        rn = 10.0 ** rng.uniform(-12, 0)
+        P = make_problem_torch(m, n, kappa, rn, seed=1000 + i)
+        pool.append(P)
+    torch.cuda.synchronize()
+    print(f"# serving pool: {len(pool)} problems in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    R = args.serve_requests
+    reqs = [(pool[i % len(pool)], i % 2) for i in range(R)]
+    outs = [torch.zeros(P.A.shape[1], dtype=torch.float64, device=dev) for P, _ in reqs]
+    torch.cuda.synchronize()
+    srv = binding.Server(ctx, hbm_budget=32 << 30, max_slots=args.serve_slots)
+    try:
+        # warm-up: one request per pool problem (workspace growth, first-launch costs)
+        wt = [binding.batched_submit(srv, P.A, P.b, torch.zeros(P.A.shape[1], dtype=torch.float64, device=dev))
+              for P in pool[: min(len(pool), 2 * args.serve_slots)]]
+        for t in wt:
+            binding.fs_server_wait(srv, t)
+        # saturated throughput
+        ts = time.perf_counter()
+        tickets = [binding.batched_submit(srv, P.A, P.b, x, method=meth) for (P, meth), x in zip(reqs, outs)]
+        for t in tickets:
+            binding.fs_server_wait(srv, t)
+        sat_s = time.perf_counter() - ts
+        thr = R / sat_s
+        bad = sum(1 for t in tickets if binding.batched_poll(srv, t)[1] < 0)
+        gbytes = sum(P.A.shape[0] * P.A.shape[1] * 8 for P, _ in reqs) / 1e9
+        print(f"# serving saturated: {R} requests in {sat_s:.2f}s = {thr:.1f} solves/s, errors {bad}",
+              file=sys.stderr, flush=True)
+        # Poisson arrivals at 0.8 x saturated rate
+        lam = 0.8 * thr
+        arr = np.cumsum(rng.exponential(1.0 / lam, size=R))
+        tickets2 = []
+        tstart = time.perf_counter()
+        for (P, meth), x, ta in zip(reqs, outs, arr):
+            now = time.perf_counter() - tstart
+            if ta > now:
+                time.sleep(ta - now)
+            tickets2.append(binding.batched_submit(srv, P.A, P.b, x, method=meth))
+        for t in tickets2:
+            binding.fs_server_wait(srv, t)
+        lat = []
+        for t in tickets2:
+            sub, st_, fin = binding.fs_server_ticket_times(srv, t)
+            lat.append(fin - sub)
+        lat = np.array(lat) * 1e3
+        p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+        print(f"# serving Poisson at {lam:.1f}/s: p50 {p50:.2f} ms, p99 {p99:.2f} ms", file=sys.stderr, flush=True)
+        # accuracy of a sample of served requests (known-SVD KW, CPU)
+        bes = []
+        if not args.no_check:
+            from oracle import backward_error as be
+            for i in sorted({0, R // 4 + 1, R // 2 + 2, 3 * R // 4 + 3} & set(range(R))):
+                P, _ = reqs[i]
+                A_h = P.A.cpu().numpy()
+                b_h = P.b.cpu().numpy()
+                x_h = outs[i].cpu().numpy()
+                fro = np.sqrt(np.sum(A_h * A_h))
+                bes.append(float(be.kw_known_svd(A_h, b_h, x_h, P.sigma, P.V, fro / np.linalg.norm(b_h)) / fro))
+            print(f"# serving accuracy sample: BE {bes}", file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+    return {"requests": R, "slots": args.serve_slots, "pool": len(pool), "saturated_solves_per_s": round(thr, 1),
+            "saturated_GBps_of_A": round(gbytes / sat_s, 1), "poisson_rate_per_s": round(lam, 1),
+            "p50_ms": round(p50, 2), "p99_ms": round(p99, 2), "errors": bad, "be_sample": bes,
+            "workload": "C5: m~U[5e3,3e5], n~U[20,500], m>=20n, kappa=10^U[2,12], ||r|| log-U[1e-12,1], "
+                        "FOSSILS/SPIR alternating, FP64; requests cycle through the pool"}
 
 
 def main():
@@ -146,6 +239,8 @@ def main():
     else:
         multi_check = None
 
+    serving = serve_bench(ctx, args, dev) if args.serve_requests > 0 else None
+
     # ---- accuracy (CPU, long double; outside the timed region)
     accuracy = None
     Ah = None
@@ -154,7 +249,10 @@ def main():
     if not args.no_check:
         from oracle import backward_error as be
         accuracy = []
+        solved = sorted({i for i, _, _ in infos})
         for i, P in enumerate(probs):
+            if i not in solved:
+                continue
             A_i = Ah if i == 0 else P.A.cpu().numpy()
             b_i = P.b.cpu().numpy()
             x_i = xs[i].cpu().numpy()
@@ -222,7 +320,7 @@ def main():
         "phase_ms_last": [round(p, 3) for p in infos[-1][2].phase_ms],
         "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy,
         "multi_rhs": multi,
-        "serving": None,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
