@@ -34,6 +34,11 @@ sys.path.insert(0, ROOT)
 M, N, KAPPA = 1_000_000, 1000, 1e10
 RESID = [1e-10, 1e-4, 1.0]
 HBM_PEAK_GBPS = 8000.0
+# HBM bytes per launch of the fused pass at 1e6 x 1000 from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
+# by a 1 GiB copy (profiles/fused_pass_1e6x1000_hbm_traffic.md); valid only for the kernel source
+# with this hash (reported as null otherwise).
+PASS_TRAFFIC_BYTES = 8.0020e9
+PASS_TRAFFIC_SHA256 = "1234717bd0b6d2c65a3add37aa8696614cb0381f67f1a380903c5f4518f303d6"
 
 
 def parse():
@@ -49,6 +54,9 @@ def parse():
     ap.add_argument("--pass-repeats", type=int, default=20)
     ap.add_argument("--multi", type=int, default=64, help="right-hand sides of the multi-RHS line (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2048, help="requests of the serving line (0: skip)")
+    ap.add_argument("--pass-only", action="store_true",
+                    help="profiling mode: a 1 GiB device copy (counter calibration) then the fused pass "
+                         "A^T(A z) at m=1e6, n=1000, --pass-repeats times; prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
     return ap.parse_args()
@@ -149,8 +157,36 @@ def serve_bench(ctx, args, dev):
                         "FOSSILS/SPIR alternating, FP64; requests cycle through the pool"}
 
 
+def pass_only(args):
+    """Counter-calibration workload: one plain copy of a known size (1 GiB read + 1 GiB written by
+    torch's copy kernel), then the fused normal pass on a random 1e6 x 1000 matrix."""
+    import torch
+
+    from paper_2406_03468_amd import binding
+
+    dev = torch.device("cuda:0")
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    At = torch.randn((N, M), generator=gen, dtype=torch.float64, device=dev)
+    z = torch.randn((N,), generator=gen, dtype=torch.float64, device=dev)
+    v = torch.empty(N, dtype=torch.float64, device=dev)
+    ctx = binding.Context(0)
+    ms_pass, ms_kernel = binding.fs_time_normal_pass(ctx, At.t(), z, v, repeats=args.pass_repeats)
+    alg = M * N * 8 + 2 * N * 8
+    print(json.dumps({"mode": "pass-only", "copy_bytes": 2 * (1 << 30), "pass_algorithmic_bytes": alg,
+                      "ms_kernel": ms_kernel, "ms_pass": ms_pass, "GBps": alg / (ms_kernel / 1e3) / 1e9}), flush=True)
+    ctx.close()
+
+
 def main():
     args = parse()
+    if args.pass_only:
+        return pass_only(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU row sharding is design only "
                                    "(see DESIGN.md)", "n_gpus": args.gpus}))
@@ -206,8 +242,12 @@ def main():
     ms_pass, ms_kernel = binding.fs_time_normal_pass(ctx, probs[0].A, z, v, repeats=args.pass_repeats)
     alg_bytes = bytes_per_pass + 2 * N * 8
     achieved = alg_bytes / (ms_kernel / 1e3) / 1e9
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2406_03468_amd", "csrc", "kernels_pass.hip"), "rb") as fh:
+        same_kernel = hashlib.sha256(fh.read()).hexdigest() == PASS_TRAFFIC_SHA256
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": PASS_TRAFFIC_BYTES if same_kernel else None, "algorithmic_bytes": alg_bytes,
                 "kernel": "k_fused_pass (v = A^T(A z), H=16 rows x 1000 cols per tile)",
                 "ms_kernel": round(ms_kernel, 4), "ms_pass_with_reduction": round(ms_pass, 4)}
 
