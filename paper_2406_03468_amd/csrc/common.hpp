@@ -204,5 +204,23 @@ __device__ __forceinline__ void grid_barrier_co(const GridBarrier& b, unsigned n
   __syncthreads();
 }
 
+// Launch a kernel that synchronizes its whole grid with the barriers above as an ordinary dispatch,
+// after checking that every work-group can be resident at once (grid <= occupancy x CUs).  The
+// HIP cooperative-launch path is not used: on this GPU it serializes against the work of every
+// other stream, which would stop the solves of a server's slots from overlapping.  When several
+// streams launch such grids, their owners reserve work-groups first (CoopBudget) so that the grids
+// running together always fit; ordinary kernels on other streams only delay residency (they finish
+// on their own), and the bounded spin of the barriers turns any failure into an error flag.
+inline hipError_t fs_launch_resident(const void* fn, dim3 grid, dim3 block, void** args, size_t shmem,
+                                     hipStream_t s) {
+  int dev = 0, ncu = 0, per = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, (int)(block.x * block.y * block.z), shmem);
+  if (e != hipSuccess) return e;
+  if (per < 1 || (int64_t)grid.x * grid.y * grid.z > (int64_t)per * ncu) return hipErrorCooperativeLaunchTooLarge;
+  return hipLaunchKernel(fn, grid, block, args, shmem, s);
+}
+
 // Zero the barrier words before a cooperative launch (a kernel, so it is also graph-safe).
 __global__ void k_barrier_reset(unsigned* words, int n);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <mutex>
 
 #include "../../include/fossils.h"
@@ -31,20 +32,43 @@ struct fs_context_s {
   Workspace ws;
   DevState* st_host = nullptr;  // pinned copy for read-back
   hipEvent_t ev[8] = {};
-  // Set by a server whose slots share the GPU: cooperative kernels (QR, SVD) of different
-  // contexts must not run concurrently (each grid has to be fully resident).
-  std::mutex* coop_lock = nullptr;
+  // Set by a server whose slots share the GPU (see CoopBudget).
+  struct CoopBudget* coop_budget = nullptr;
 };
 
-// Holds the cooperative-kernel lock of ctx (if any) until the context's stream has drained.
+// Cooperative kernels (QR, SVD) need every work-group of their grid resident at once.  Slots of a
+// server reserve their grid's work-groups (at most one per CU for these kernels: their LDS use
+// leaves room for one) from a budget of num_cu before launching, and give them back once the
+// stream has drained; grids that fit together run concurrently, and two grids can never hold parts
+// of the GPU while waiting for each other.  Other kernels need no reservation: they finish on
+// their own and free their CUs.
+struct CoopBudget {
+  std::mutex mu;
+  std::condition_variable cv;
+  int total = 0, avail = 0;
+};
+
+// Holds a reservation of `need` work-groups (if the context has a budget) until the stream drains.
 struct CoopSection {
   fs_context_s* ctx;
-  std::unique_lock<std::mutex> lk;
-  explicit CoopSection(fs_context_s* c) : ctx(c) {
-    if (c->coop_lock) lk = std::unique_lock<std::mutex>(*c->coop_lock);
+  int need = 0;
+  CoopSection(fs_context_s* c, int need_wgs) : ctx(c) {
+    CoopBudget* b = c->coop_budget;
+    if (!b) return;
+    need = std::max(1, std::min(need_wgs, b->total));
+    std::unique_lock<std::mutex> lk(b->mu);
+    b->cv.wait(lk, [&] { return b->avail >= need; });
+    b->avail -= need;
   }
   ~CoopSection() {
-    if (lk.owns_lock()) (void)hipStreamSynchronize(ctx->stream);
+    if (!need) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    CoopBudget* b = ctx->coop_budget;
+    {
+      std::lock_guard<std::mutex> lk(b->mu);
+      b->avail += need;
+    }
+    b->cv.notify_all();
   }
 };
 

@@ -465,7 +465,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
   FS_HIP(hipEventRecord(ev[1], s));
   // ---- QR of the sketch (cooperative kernels: serialized against other slots of a server)
-  std::unique_ptr<CoopSection> coop(new CoopSection(ctx));
+  std::unique_ptr<CoopSection> coop(new CoopSection(
+      ctx, std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false))));
   FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
   FS_HIP(hipEventRecord(ev[2], s));
   // ---- SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate)
@@ -477,10 +478,18 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   std::vector<double> cnh(n + 1);
   FS_HIP(hipMemcpyAsync(cnh.data(), cn2, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, s));
-  int svd_sweeps = 0;
+  int svd_sweeps = 0, bar_err[2] = {0, 0};
   FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  FS_HIP(hipMemcpyAsync(&bar_err[0], fs_qr_err_word(W.qrwork.p, d, k, ctx->num_cu), sizeof(int),
+                        hipMemcpyDeviceToHost, s));
+  FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
   FS_HIP(hipStreamSynchronize(s));
   coop.reset();
+  if (bar_err[0] || bar_err[1]) {
+    fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the QR/SVD kernels gave up waiting", __FILE__,
+                          __LINE__);
+    return FS_ERR_DEVICE;
+  }
   for (int j = 0; j <= n; ++j)
     if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
   const double b2 = cnh[n];
@@ -505,7 +514,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     use_svd = true;
     // the truncated start x_0 = V_r Sigma_r^{-1} U_r^T t needs U_R: redo the SVD accumulating it
     // (rank-deficient problems only)
-    CoopSection cs(ctx);
+    CoopSection cs(ctx, fs_svd_grid_size(n, ctx->num_cu, true));
     FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev, s));
   }
   inf.rank = rk;

@@ -97,7 +97,8 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
                               true, ctx->lds_bytes, s));
   FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
   FS_HIP(hipEventRecord(ev[1], s));
-  std::unique_ptr<CoopSection> coop(new CoopSection(ctx));
+  std::unique_ptr<CoopSection> coop(new CoopSection(
+      ctx, std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false))));
   FS_K(fs_launch_qr(Y, d, d, kc, W.qrwork.p, ctx->num_cu, s));
   FS_HIP(hipEventRecord(ev[2], s));
   FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev,
@@ -107,10 +108,18 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
   FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   std::vector<double> cnh(kc);
   FS_HIP(hipMemcpyAsync(cnh.data(), cn2, sizeof(double) * kc, hipMemcpyDeviceToHost, s));
-  int svd_sweeps = 0;
+  int svd_sweeps = 0, bar_err[2] = {0, 0};
   FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  FS_HIP(hipMemcpyAsync(&bar_err[0], fs_qr_err_word(W.qrwork.p, d, kc, ctx->num_cu), sizeof(int),
+                        hipMemcpyDeviceToHost, s));
+  FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
   FS_HIP(hipStreamSynchronize(s));
   coop.reset();
+  if (bar_err[0] || bar_err[1]) {
+    fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the QR/SVD kernels gave up waiting", __FILE__,
+                          __LINE__);
+    return FS_ERR_DEVICE;
+  }
   for (int j = 0; j < kc; ++j)
     if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
   const DevState hs = *ctx->st_host;
@@ -121,7 +130,7 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
   if (!(hs.condest <= 1.0 / (o.tau_factor * FS_U_ROUND))) {  // Alg 4: numerically rank deficient
     flags |= 1;
     nr = hs.rank_trunc > 0 ? hs.rank_trunc : 1;
-    CoopSection cs(ctx);
+    CoopSection cs(ctx, fs_svd_grid_size(n, ctx->num_cu, true));
     FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev,
                             s));
     // x_0 = V_r Sigma_r^{-1} U_r^T t_j: U_r^T T (as P^T with sigma = 1), then V_r Sigma_r^{-1}

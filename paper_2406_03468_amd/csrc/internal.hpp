@@ -86,3 +86,11 @@ struct MultiPassArgs {
 int fs_multi_blocks(int k);
 size_t fs_multi_work_doubles(int64_t m, int n, int k, int64_t* rc_out);
 hipError_t fs_launch_multi_pass(const MultiPassArgs& a, hipStream_t s);
+
+// Work-groups of the cooperative grids (for reservations when several streams share the GPU).
+int fs_qr_grid_size(int d, int num_cu);
+int fs_svd_grid_size(int n, int num_cu, bool with_u);
+// Device address of the barrier-timeout flag of the last QR / SVD launch on this workspace
+// (nonzero: a grid barrier gave up waiting; the results are not valid).
+int* fs_qr_err_word(void* work, int d, int k, int num_cu);
+int* fs_svd_err_word(void* work, int n);

@@ -255,6 +255,21 @@ void qr_grid(int d, int num_cu, int* G, int* RB) {
 
 }  // namespace
 
+int* fs_qr_err_word(void* work, int d, int k, int num_cu) {
+  int G, RB;
+  qr_grid(d, num_cu, &G, &RB);
+  double* part = (double*)work;
+  double* wred = part + (size_t)2 * G * 2 * NB + (size_t)G * NB * k;
+  unsigned* words = (unsigned*)(wred + (size_t)NB * k);
+  return (int*)(words + FS_BAR_WORDS - 1);
+}
+
+int fs_qr_grid_size(int d, int num_cu) {
+  int G, RB;
+  qr_grid(d, num_cu, &G, &RB);
+  return G;
+}
+
 size_t fs_qr_work_bytes(int d, int k, int num_cu) {
   int G, RB;
   qr_grid(d, num_cu, &G, &RB);
@@ -275,5 +290,5 @@ hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int nu
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   void* args[] = {&Y, &ldy, &d, &k, &RB, &part, &wpart, &wred, &bar};
-  return hipLaunchCooperativeKernel((const void*)k_qr_coop, dim3(G), dim3(QR_NT), args, 0, s);
+  return fs_launch_resident((const void*)k_qr_coop, dim3(G), dim3(QR_NT), args, 0, s);
 }

@@ -359,6 +359,21 @@ int svd_block_width(int n) {
 }
 }  // namespace
 
+int* fs_svd_err_word(void* work, int n) {
+  double* norms = (double*)work + (size_t)2 * n * n;
+  return (int*)(norms + n) + 66;
+}
+
+int fs_svd_grid_size(int n, int num_cu, bool with_u) {
+  const int bw = svd_block_width(n);
+  if (!with_u && bw > 0) {
+    const int nblk = (n + bw - 1) / bw;
+    return (nblk + (nblk & 1)) / 2;
+  }
+  const int G = (n + 1) / 2;
+  return G < num_cu ? (G < 1 ? 1 : G) : num_cu;
+}
+
 size_t fs_svd_work_bytes(int n) {
   // Gm | Uacc | norms | counters | mailboxes [P][2][2][b*n] | flags [P][2]
   const int b = svd_block_width(n);
@@ -410,14 +425,14 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     int NB2 = NBLK;
     int bw2 = bw;
     void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co};
-    e = hipLaunchCooperativeKernel((const void*)k_jacobi_block, dim3(P), dim3(1024), args, shmem, s);
+    e = fs_launch_resident((const void*)k_jacobi_block, dim3(P), dim3(1024), args, shmem, s);
     if (e != hipSuccess) return e;
   } else {
     int G = (n + 1) / 2;
     if (G > num_cu) G = num_cu;
     if (G < 1) G = 1;
     void* args[] = {&Gm, &Uarg, &n, &max_sweeps, &tol, &rot, &sweeps_out_dev, &bar};
-    e = hipLaunchCooperativeKernel((const void*)k_jacobi_coop, dim3(G), dim3(SVD_NT), args, 0, s);
+    e = fs_launch_resident((const void*)k_jacobi_coop, dim3(G), dim3(SVD_NT), args, 0, s);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_svd_norms, dim3(n), dim3(256), 0, s, Gm, n, norms);

@@ -2,10 +2,11 @@
 //
 // Each slot is a host thread with its own fs_context (own HIP stream, grow-only workspace), so the
 // passes over A of different requests overlap on the GPU (a request with small n does not fill the
-// GPU on its own).  The cooperative QR/SVD kernels are serialized across slots through the shared
-// coop_lock (a cooperative grid must be fully resident; two of them partially resident at once could
-// wait on each other).  Admission is by workspace footprint: each slot owns hbm_budget / max_slots
-// bytes and a request needing more is refused at submission.
+// GPU on its own).  The cooperative QR/SVD kernels of different slots run concurrently when their
+// grids fit on the GPU together: each reserves its work-groups from a device-wide budget of num_cu
+// (CoopBudget), so two grids never hold parts of the GPU while waiting for each other.  Admission is
+// by workspace footprint: each slot owns hbm_budget / max_slots bytes and a request needing more is
+// refused at submission.
 #include <math.h>
 
 #include <chrono>
@@ -46,7 +47,7 @@ struct fs_server_s {
   std::unordered_map<uint64_t, Ticket> tickets;
   uint64_t next_ticket = 1;
   bool shutdown = false;
-  std::mutex coop;               // cooperative kernels, device-wide
+  CoopBudget coop;               // work-groups of cooperative grids, device-wide
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
   double now() const {
@@ -102,6 +103,7 @@ fs_status fs_server_create(fs_context ctx, size_t hbm_budget, int32_t max_slots,
   fs_server srv = new fs_server_s();
   srv->device = ctx->device;
   srv->slot_budget = hbm_budget / (size_t)max_slots;
+  srv->coop.total = srv->coop.avail = ctx->num_cu;
   for (int i = 0; i < max_slots; ++i) {
     hipStream_t st = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);  // default priority
@@ -116,7 +118,7 @@ fs_status fs_server_create(fs_context ctx, size_t hbm_budget, int32_t max_slots,
       delete srv;
       return s;
     }
-    c->coop_lock = &srv->coop;
+    c->coop_budget = &srv->coop;
     srv->slots.push_back(c);
     srv->streams.push_back(st);
   }
