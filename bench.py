@@ -58,6 +58,7 @@ def parse():
                     help="profiling mode: a 1 GiB device copy (counter calibration) then the fused pass "
                          "A^T(A z) at m=1e6, n=1000, --pass-repeats times; prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-precision line")
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
     return ap.parse_args()
 
@@ -96,8 +97,14 @@ def serve_bench(ctx, args, dev):
     torch.cuda.synchronize()
     print(f"# serving pool: {len(pool)} problems in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     R = args.serve_requests
-    reqs = [(pool[i % len(pool)], i % 2) for i in range(R)]
-    outs = [torch.zeros(P.A.shape[1], dtype=torch.float64, device=dev) for P, _ in reqs]
+    # FOSSILS / SPIR alternate; every other pair runs in the mixed-precision form (FP32 sketch)
+    opt_mixed = {}
+    for P in pool:
+        o = binding.fs_options_default(*P.A.shape)
+        o.precision = binding.FS_MIXED
+        opt_mixed[id(P)] = o
+    reqs = [(pool[i % len(pool)], i % 2, (i // 2) % 2 == 1) for i in range(R)]
+    outs = [torch.zeros(P.A.shape[1], dtype=torch.float64, device=dev) for P, _, _ in reqs]
     torch.cuda.synchronize()
     srv = binding.Server(ctx, hbm_budget=32 << 30, max_slots=args.serve_slots)
     try:
@@ -108,7 +115,8 @@ def serve_bench(ctx, args, dev):
             binding.fs_server_wait(srv, t)
         # saturated throughput
         ts = time.perf_counter()
-        tickets = [binding.batched_submit(srv, P.A, P.b, x, method=meth) for (P, meth), x in zip(reqs, outs)]
+        tickets = [binding.batched_submit(srv, P.A, P.b, x, method=meth, opts=opt_mixed[id(P)] if mx else None)
+                   for (P, meth, mx), x in zip(reqs, outs)]
         for t in tickets:
             binding.fs_server_wait(srv, t)
         sat_s = time.perf_counter() - ts
@@ -116,7 +124,9 @@ def serve_bench(ctx, args, dev):
         bad = sum(1 for t in tickets if binding.batched_poll(srv, t)[1] < 0)
         svc = [binding.fs_server_ticket_times(srv, t) for t in tickets]
         service_ms = 1e3 * float(np.mean([f - st_ for _, st_, f in svc]))
-        gbytes = sum(P.A.shape[0] * P.A.shape[1] * 8 for P, _ in reqs) / 1e9
+        gbytes = sum(P.A.shape[0] * P.A.shape[1] * 8 for P, _, _ in reqs) / 1e9
+        n_fb = sum(1 for t, (_, _, mx) in zip(tickets, reqs)
+                   if mx and binding.batched_poll(srv, t)[2].flags & binding.FS_FLAG_FP64_SKETCH)
         print(f"# serving saturated: {R} requests in {sat_s:.2f}s = {thr:.1f} solves/s, errors {bad}, "
               f"mean service {service_ms:.2f} ms", file=sys.stderr, flush=True)
         # Poisson arrivals at 0.8 x saturated rate
@@ -124,11 +134,12 @@ def serve_bench(ctx, args, dev):
         arr = np.cumsum(rng.exponential(1.0 / lam, size=R))
         tickets2 = []
         tstart = time.perf_counter()
-        for (P, meth), x, ta in zip(reqs, outs, arr):
+        for (P, meth, mx), x, ta in zip(reqs, outs, arr):
             now = time.perf_counter() - tstart
             if ta > now:
                 time.sleep(ta - now)
-            tickets2.append(binding.batched_submit(srv, P.A, P.b, x, method=meth))
+            tickets2.append(binding.batched_submit(srv, P.A, P.b, x, method=meth,
+                                                   opts=opt_mixed[id(P)] if mx else None))
         for t in tickets2:
             binding.fs_server_wait(srv, t)
         lat = []
@@ -143,7 +154,7 @@ def serve_bench(ctx, args, dev):
         if not args.no_check:
             from oracle import backward_error as be
             for i in sorted({0, R // 4 + 1, R // 2 + 2, 3 * R // 4 + 3} & set(range(R))):
-                P, _ = reqs[i]
+                P, _, _ = reqs[i]
                 A_h = P.A.cpu().numpy()
                 b_h = P.b.cpu().numpy()
                 x_h = outs[i].cpu().numpy()
@@ -156,8 +167,72 @@ def serve_bench(ctx, args, dev):
             "saturated_GBps_of_A": round(gbytes / sat_s, 1), "mean_service_ms": round(service_ms, 2),
             "poisson_rate_per_s": round(lam, 1),
             "p50_ms": round(p50, 2), "p99_ms": round(p99, 2), "errors": bad, "be_sample": bes,
+            "mixed_requests": sum(1 for _, _, mx in reqs if mx), "mixed_fp64_sketch_fallbacks": n_fb,
             "workload": "C5: m~U[5e3,3e5], n~U[20,500], m>=20n, kappa=10^U[2,12], ||r|| log-U[1e-12,1], "
-                        "FOSSILS/SPIR alternating, FP64; requests cycle through the pool"}
+                        "FOSSILS/SPIR alternating, half of the requests in the mixed-precision form; "
+                        "requests cycle through the pool"}
+
+
+def mixed_bench(ctx, args, dev, P10):
+    """Mixed-precision form at 1e6 x 1000 (C4): the kappa = 1e10 problem of the timed steps, a
+    kappa = 1e14 variant, and a kappa = 1e6 one (where the FP32 sketch is kept).  Per problem: the
+    FP64 solve, the mixed solve with A32 = fl32(A) created inside the timed region (fs_to_fp32 +
+    solve), and the mixed solve with A32 already resident; each the best of two.  Backward error
+    (known-SVD KW) and forward error of the mixed and FP64 solutions, CPU, outside the timing."""
+    import numpy as np
+    import torch
+
+    from paper_2406_03468_amd import binding
+    from synth import make_problem_torch
+
+    cases = [("kappa=1e10", P10), ("kappa=1e14", make_problem_torch(M, N, 1e14, RESID[1], seed=3)),
+             ("kappa=1e6", make_problem_torch(M, N, 1e6, RESID[1], seed=4))]
+    A32 = torch.empty((N, M), dtype=torch.float32, device=dev).t()
+    opts = binding.fs_options_default(M, N)
+    x64 = torch.zeros(N, dtype=torch.float64, device=dev)
+    xm = torch.zeros(N, dtype=torch.float64, device=dev)
+
+    def best(fn):
+        ts = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t1)
+        return 1e3 * min(ts), r
+
+    out = []
+    for name, P in cases:
+        binding.fossils_solve(ctx, P.A, P.b, x64, opts)  # warm-up
+        ms64, (_, i64) = best(lambda: binding.fossils_solve(ctx, P.A, P.b, x64, opts))
+
+        def created():
+            binding.fs_to_fp32(ctx, P.A, A32)
+            return binding.fossils_solve_mixed(ctx, P.A, P.b, xm, A32)
+        ms_c, _ = best(created)
+        ms_r, (_, im) = best(lambda: binding.fossils_solve_mixed(ctx, P.A, P.b, xm, A32))
+        ms_conv, _ = best(lambda: binding.fs_to_fp32(ctx, P.A, A32))
+        rec = {"problem": name, "ms_fp64": round(ms64, 2), "ms_mixed_a32_created": round(ms_c, 2),
+               "ms_mixed_a32_resident": round(ms_r, 2), "ms_to_fp32": round(ms_conv, 2),
+               "fp64_sketch_fallback": bool(im.flags & binding.FS_FLAG_FP64_SKETCH),
+               "condest": im.condest, "iters_mixed": list(im.iters), "iters_fp64": list(i64.iters),
+               "sketch_ms_mixed": round(im.phase_ms[0], 2), "sketch_ms_fp64": round(i64.phase_ms[0], 2)}
+        if not args.no_check:
+            from oracle import backward_error as be
+            A_h = P.A.cpu().numpy()
+            b_h = P.b.cpu().numpy()
+            fro = np.sqrt(np.sum(A_h * A_h))
+            for key, xx in (("mixed", xm), ("fp64", x64)):
+                x_h = xx.cpu().numpy()
+                rec[f"be_{key}"] = float(be.kw_known_svd(A_h, b_h, x_h, P.sigma, P.V, fro / np.linalg.norm(b_h)) / fro)
+                rec[f"fe_{key}"] = float(np.linalg.norm(x_h - P.x_true) / np.linalg.norm(P.x_true))
+            del A_h
+        print(f"# mixed {name}: {rec}", file=sys.stderr, flush=True)
+        out.append(rec)
+    del A32
+    return {"cases": out, "workload": "C4: 1e6 x 1000, ||r_perp|| = 1e-4, kappa in {1e10, 1e14, 1e6}; the FP32 "
+                                      "sketch is kept while u32 condest <= 0.5, else redone in FP64"}
 
 
 def pass_only(args):
@@ -283,6 +358,8 @@ def main():
     else:
         multi_check = None
 
+    mixed = mixed_bench(ctx, args, dev, probs[1]) if args.mixed else None
+
     serving = serve_bench(ctx, args, dev) if args.serve_requests > 0 else None
 
     # ---- accuracy (CPU, long double; outside the timed region)
@@ -364,6 +441,7 @@ def main():
         "phase_ms_last": [round(p, 3) for p in infos[-1][2].phase_ms],
         "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy,
         "multi_rhs": multi,
+        "mixed": mixed,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

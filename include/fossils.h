@@ -54,6 +54,8 @@ typedef struct fs_server_s* fs_server;
 
 enum { FS_PRECOND_QR = 0, FS_PRECOND_SVD = 1 };
 enum { FS_FP64 = 0, FS_MIXED = 1 };
+/* bits of fs_info.flags */
+enum { FS_FLAG_RANK_DEFICIENT = 1, FS_FLAG_NOT_CONVERGED = 2, FS_FLAG_FP64_SKETCH = 4 };
 
 /* Solver options (Section 4.2 and Algorithm 4).  Fill with fs_options_default. */
 typedef struct fs_options {
@@ -71,7 +73,7 @@ typedef struct fs_options {
   int32_t fixed_q;        /* 0: adaptive stopping; q > 0: Algorithm 2 with q heavy-ball steps;
                              -1: q_0 of Theorem 7.1 (eq:iterations) with kappa = condest */
   int32_t steps;          /* refinement steps: 2 (the method) or 1 ("one step" variant) */
-  int32_t precision;      /* FS_FP64 (reserved: FS_MIXED) */
+  int32_t precision;      /* FS_FP64, or FS_MIXED: FP32 sketch (see fossils_solve_mixed) */
   int32_t max_sweeps;     /* Jacobi sweep cap of the SVD of R */
 } fs_options;
 
@@ -126,6 +128,17 @@ fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int6
 fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, int32_t k,
                               const double* B, int64_t ldb, double* X, int64_t ldx, const fs_options* opts,
                               fs_info* info);
+
+/* Mixed-precision form: the sketch S [A_s b] is accumulated in FP32 (from A32 = fl32(A), column-major
+ * lda32 >= m, when A32 is not NULL, else from A converted on the fly); QR, SVD and the whole
+ * refinement (every pass over A, Alg 1 lines 5-7) stay FP64 on A.  An FP32 sketch perturbs S A by
+ * about u32 ||A||, which keeps A_s R^{-1} well conditioned only while condest * u32 is small; above
+ * the threshold (u32 condest > 0.5, condest > ~8.4e6) the sketch is redone in FP64 and info->flags gets
+ * FS_FLAG_FP64_SKETCH.  The result meets the same backward-error bar as fossils_solve. */
+fs_status fossils_solve_mixed(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const float* A32,
+                              int64_t lda32, const double* b, double* x, const fs_options* opts, fs_info* info);
+/* A32 = fl32(A) on the context's stream (for callers that keep an FP32 copy resident). */
+fs_status fs_to_fp32(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, float* A32, int64_t lda32);
 
 /* ---------------- sparse sign embedding (Section 4.2, "Choice of embedding") ---------------- */
 

@@ -36,12 +36,20 @@ import numpy as np
 
 from .backward_error import kw_from_svd
 from .householder import back_substitution, forward_substitution_transposed, householder_qr
-from .sketch import sketch_Ab
+from .sketch import sketch_Ab, sketch_fp32
 
 U_ROUND = 2.0**-52
 
 FLAG_RANK_DEFICIENT = 1
 FLAG_NOT_CONVERGED = 2
+FLAG_FP64_SKETCH = 4
+
+U32 = 2.0**-24
+# mixed precision: the FP32 sketch is kept while u32 condest <= 0.5 (see solve()); measured with this
+# oracle on the 4000 x 50 problems, the FP32-sketch preconditioner needs the FP64 iteration counts up
+# to u32 condest ~ 0.5 and degrades beyond u32 condest ~ 1 (it fails to converge at kappa = 1e10)
+MIXED_COND_FACTOR = U32
+MIXED_DISTORTION = 0.5
 
 
 @dataclass
@@ -60,6 +68,8 @@ class Options:
     precond: str = "qr"              # "qr" (P = R^{-1}) or "svd" (P = V Sigma^{-1})
     fixed_q: int = 0                 # 0 adaptive; q > 0 Algorithm 2 with q steps; -1 q_0 of Thm 7.1
     steps: int = 2                   # refinement steps (2 = the method; 1 = "FOSSILS (1 step)")
+    precision: str = "fp64"          # "fp64", or "mixed": FP32 sketch, FP64 everything else
+    mixed_fallback: bool = True      # mixed: redo the sketch in FP64 when condest u32 is too large
 
 
 @dataclass
@@ -168,8 +178,20 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
     # Alg 4: embedding parameters and Polyak coefficients.
     eta = (opts.eta if opts.eta is not None else math.sqrt(n / dsk)) * opts.eta_factor
     alpha, beta = polyak_coefficients(eta)
-    # Alg 1 / Alg 4: sketch [A b] with one embedding.
-    Y = sketch_Ab(As, b, dsk, opts.zeta, opts.seed)
+    # Alg 1 / Alg 4: sketch [A b] with one embedding (single precision in the mixed form).
+    flags = 0
+    if opts.precision == "mixed":
+        Y = sketch_fp32(np.column_stack([As, b]), dsk, opts.zeta, opts.seed)
+        # An FP32 sketch is S A perturbed by ~u32 ||A||: R from it preconditions A_s well only while
+        # condest u32 is small (Lemma 6.3 with u32 in place of u); beyond that, redo it in FP64.
+        cond32 = np.linalg.cond(np.linalg.qr(Y[:, :n], mode="r"))
+        if opts.mixed_fallback and not (cond32 * MIXED_COND_FACTOR <= MIXED_DISTORTION):
+            flags |= FLAG_FP64_SKETCH
+            Y = sketch_Ab(As, b, dsk, opts.zeta, opts.seed)
+    elif opts.precision == "fp64":
+        Y = sketch_Ab(As, b, dsk, opts.zeta, opts.seed)
+    else:
+        raise ValueError("precision must be 'fp64' or 'mixed'")
     SA, Sb = Y[:, :n], Y[:, n]
 
     # Factor the sketch.
@@ -188,7 +210,6 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
     normest = float(sig_full[0])
     condest = float(sig_full[0] / sig_full[-1]) if sig_full[-1] > 0 else math.inf
 
-    flags = 0
     rank = n
     kind = opts.precond
     if condest > 1.0 / (opts.tau_factor * u):

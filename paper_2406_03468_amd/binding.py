@@ -30,6 +30,11 @@ FS_ERR_UNSUPPORTED = -8
 
 FS_PRECOND_QR = 0
 FS_PRECOND_SVD = 1
+FS_FP64 = 0
+FS_MIXED = 1
+FS_FLAG_RANK_DEFICIENT = 1
+FS_FLAG_NOT_CONVERGED = 2
+FS_FLAG_FP64_SKETCH = 4
 
 c_int32, c_int64, c_uint64, c_double, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
 
@@ -89,6 +94,9 @@ _SIGS = [
                              ctypes.POINTER(FsInfo)]),
     ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
+    ("fossils_solve_mixed", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64, c_vp, c_vp,
+                                      ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
+    ("fs_to_fp32", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64]),
     ("fs_server_create", c_int32, [c_vp, ctypes.c_size_t, c_int32, ctypes.POINTER(c_vp)]),
     ("fs_server_destroy", c_int32, [c_vp]),
     ("batched_submit", c_int32, [c_vp, ctypes.POINTER(FsRequest), ctypes.POINTER(c_uint64)]),
@@ -216,6 +224,24 @@ def spir_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
     s, info = _solve(load().spir_solve, ctx, A, b, x, opts)
     _check(s)
     return s, info
+
+
+def fossils_solve_mixed(ctx: Context, A, b, x, A32=None, opts: Optional[FsOptions] = None):
+    """Mixed-precision form: FP32 sketch (from A32 if given, a float32 column-major copy of A)."""
+    m, n = A.shape
+    info = FsInfo()
+    ld32 = int(_colmajor(A32)) if A32 is not None else 0
+    s = load().fossils_solve_mixed(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(A32)), ld32,
+                                   c_vp(_ptr(b)), c_vp(_ptr(x)), ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(info))
+    _check(s)
+    return s, info
+
+
+def fs_to_fp32(ctx: Context, A, A32):
+    m, n = A.shape
+    _check(load().fs_to_fp32(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(A32)),
+                             int(_colmajor(A32))))
 
 
 def fossils_solve_multi(ctx: Context, A, B, X, opts: Optional[FsOptions] = None):

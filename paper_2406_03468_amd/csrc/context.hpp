@@ -13,6 +13,9 @@
 #include "state.hpp"
 
 constexpr double FS_U_ROUND = 2.220446049250313e-16;
+// Mixed precision: the FP32 sketch is accepted while u32 condest <= 0.5 (condest <= ~8.4e6).
+constexpr double FS_MIXED_COND_FACTOR = 5.9604644775390625e-08;
+constexpr double FS_MIXED_DISTORTION = 0.5;
 
 struct DevBuf {
   void* p = nullptr;

@@ -80,7 +80,7 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (o.kw_every < 1 || o.max_inner < 1 || o.steps < 1 || o.steps > 2) return FS_ERR_INVALID_ARG;
   if (!(o.gamma >= 0) || !(o.rho >= 0) || !(o.tau_factor > 0) || !(o.eta_factor > 0)) return FS_ERR_INVALID_ARG;
   if (o.precond != FS_PRECOND_QR && o.precond != FS_PRECOND_SVD) return FS_ERR_INVALID_ARG;
-  if (o.precision != FS_FP64) return FS_ERR_UNSUPPORTED;
+  if (o.precision != FS_FP64 && o.precision != FS_MIXED) return FS_ERR_INVALID_ARG;
   if (o.fixed_q < -1) return FS_ERR_INVALID_ARG;
   if (n > 15000) return FS_ERR_TOO_LARGE;       // TRSV keeps x in LDS
   if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
@@ -405,7 +405,8 @@ struct Vecs {
 };
 
 fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
-                double* x_out, const fs_options* opts_in, fs_info* info) {
+                double* x_out, const fs_options* opts_in, fs_info* info, const float* A32 = nullptr,
+                int64_t lda32 = 0) {
   if (!ctx) return FS_ERR_INVALID_ARG;
   FS_TRY(validate_problem(m, n, A, lda, b, x_out));
   fs_options o;
@@ -458,40 +459,56 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
 
   hipEvent_t* ev = ctx->ev;
   FS_HIP(hipEventRecord(ev[0], s));
-  // ---- sketch (Alg 1 first statement; Alg 4 column scaling in the same read of A)
   FS_K(fs_launch_sketch_indices(m, d, zeta, o.seed, 0, m, W.idx.p, i16, s));
-  FS_K(fs_launch_sketch_apply(A, lda, m, n, b, m, 1, W.idx.p, i16, d, zeta, Y, d, cn2, o.column_scaling != 0, true,
-                              ctx->lds_bytes, s));
-  FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
-  FS_HIP(hipEventRecord(ev[1], s));
-  // ---- QR of the sketch (cooperative kernels: serialized against other slots of a server)
-  std::unique_ptr<CoopSection> coop(new CoopSection(
-      ctx, std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false))));
-  FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
-  FS_HIP(hipEventRecord(ev[2], s));
-  // ---- SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate)
-  FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
-                          svd_sweeps_dev, s));
-  FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
-  FS_HIP(hipEventRecord(ev[3], s));
-  // read back: colnorms (finiteness, ||b||), sigma stats
-  FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   std::vector<double> cnh(n + 1);
-  FS_HIP(hipMemcpyAsync(cnh.data(), cn2, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, s));
-  int svd_sweeps = 0, bar_err[2] = {0, 0};
-  FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-  FS_HIP(hipMemcpyAsync(&bar_err[0], fs_qr_err_word(W.qrwork.p, d, k, ctx->num_cu), sizeof(int),
-                        hipMemcpyDeviceToHost, s));
-  FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
-  FS_HIP(hipStreamSynchronize(s));
-  coop.reset();
-  if (bar_err[0] || bar_err[1]) {
-    fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the QR/SVD kernels gave up waiting", __FILE__,
-                          __LINE__);
-    return FS_ERR_DEVICE;
+  int svd_sweeps = 0;
+  // Sketch (Alg 1 first statement; Alg 4 column scaling in the same read of A), QR of the sketch,
+  // SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate), then a read-back
+  // of the statistics.  fp32: the mixed-precision form's sketch (FP32 accumulation, from A32 if given).
+  auto factor = [&](bool fp32) -> fs_status {
+    if (fp32)
+      FS_K(fs_launch_sketch_apply_fp32(A, lda, A32, lda32, m, n, b, m, 1, W.idx.p, i16, d, zeta, Y, d, cn2,
+                                       o.column_scaling != 0, true, ctx->lds_bytes, s));
+    else
+      FS_K(fs_launch_sketch_apply(A, lda, m, n, b, m, 1, W.idx.p, i16, d, zeta, Y, d, cn2, o.column_scaling != 0,
+                                  true, ctx->lds_bytes, s));
+    FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
+    FS_HIP(hipEventRecord(ev[1], s));
+    // grid-synchronizing kernels: work-groups reserved against other slots of a server
+    CoopSection coop(ctx, std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false)));
+    FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
+    FS_HIP(hipEventRecord(ev[2], s));
+    FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+                            svd_sweeps_dev, s));
+    FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
+    FS_HIP(hipEventRecord(ev[3], s));
+    FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(cnh.data(), cn2, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, s));
+    int bar_err[2] = {0, 0};
+    FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(&bar_err[0], fs_qr_err_word(W.qrwork.p, d, k, ctx->num_cu), sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    if (bar_err[0] || bar_err[1]) {
+      fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the QR/SVD kernels gave up waiting", __FILE__,
+                            __LINE__);
+      return FS_ERR_DEVICE;
+    }
+    for (int j = 0; j <= n; ++j)
+      if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
+    return FS_OK;
+  };
+  const bool mixed = (o.precision == FS_MIXED);
+  int flags = 0;
+  FS_TRY(factor(mixed));
+  if (mixed && !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
+    // The FP32 sketch perturbs S A by about u32 ||A||: as a preconditioner its R keeps A_s R^{-1}
+    // well conditioned only while condest u32 is small (the hazard of Lemma 6.3 at single precision).
+    // Otherwise the sketch is redone in FP64 (the FP64 correction of R) and the solve continues in FP64.
+    flags |= FS_FLAG_FP64_SKETCH;
+    FS_TRY(factor(false));
   }
-  for (int j = 0; j <= n; ++j)
-    if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
   const double b2 = cnh[n];
   DevState hs = *ctx->st_host;
   fs_info inf{};
@@ -505,7 +522,6 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     if (info) *info = inf;
     return FS_OK;
   }
-  int flags = 0;
   bool use_svd = (o.precond == FS_PRECOND_SVD);
   int rk = n;
   if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {  // Alg 4: numerically rank deficient
@@ -665,6 +681,25 @@ fs_status fossils_solve(fs_context ctx, int64_t m, int32_t n, const double* A, i
 fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b, double* x,
                      const fs_options* opts, fs_info* info) {
   return solve(ctx, M_SPIR, m, n, A, lda, b, x, opts, info);
+}
+
+fs_status fossils_solve_mixed(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const float* A32,
+                              int64_t lda32, const double* b, double* x, const fs_options* opts, fs_info* info) {
+  if (A32 && lda32 < m) return FS_ERR_SHAPE;
+  fs_options o;
+  if (opts) o = *opts;
+  else FS_TRY(fs_options_default(m, n, &o));
+  o.precision = FS_MIXED;
+  return solve(ctx, M_FOSSILS, m, n, A, lda, b, x, &o, info, A32, lda32);
+}
+
+fs_status fs_to_fp32(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, float* A32, int64_t lda32) {
+  if (!ctx || !A || !A32) return FS_ERR_INVALID_ARG;
+  if (m < 1 || n < 1 || lda < m || lda32 < m) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_K(fs_launch_to_fp32(A, lda, m, n, A32, lda32, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return FS_OK;
 }
 
 }  // extern "C"

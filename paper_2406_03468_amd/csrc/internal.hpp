@@ -39,6 +39,14 @@ hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n
                                   int nb, const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
                                   double* colnorm2, bool scale_by_norm, bool write_bnorm, int lds_bytes,
                                   hipStream_t s);
+// The same with FP32 accumulation in LDS (mixed-precision form), reading A32 (FP32 copy, lda32) if
+// non-null, else A converted on the fly.  Y and the column norms are FP64.
+hipError_t fs_launch_sketch_apply_fp32(const double* A, int64_t lda, const float* A32, int64_t lda32, int64_t m,
+                                       int n, const double* B, int64_t ldb, int nb, const void* idx, bool idx16,
+                                       int d, int zeta, double* Y, int64_t ldy, double* colnorm2,
+                                       bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s);
+// A32 = fl32(A) (column-major, lda32 >= m).
+hipError_t fs_launch_to_fp32(const double* A, int64_t lda, int64_t m, int n, float* A32, int64_t lda32, hipStream_t s);
 
 // ---------------------------------------------------------------- QR of the sketch
 // In-place Householder QR of the d x k matrix Y (ldy), d >= k.  On exit the upper triangle of

@@ -86,9 +86,11 @@ __global__ __launch_bounds__(256) void k_sketch_indices(int64_t col0, int64_t nc
 // n <= c < ncols from B (ldb).  PW is the compile-time panel width (columns held in LDS at once);
 // np <= PW columns are active.  Each thread walks RU rows per step with all their loads issued
 // before the LDS atomics (memory-level parallelism); for zeta = 8 with 16-bit entries the eight
-// entries of a row come in one 16-byte load.
-template <typename IDX, int NT, int PW, bool Z8>
-__global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+// entries of a row come in one 16-byte load.  TA is the element type of A (double, or float for the
+// mixed-precision form's FP32 copy), TACC the LDS accumulator (float halves the LDS per column, so
+// twice the columns share one read of the index stream); column norms always accumulate in FP64.
+template <typename IDX, int NT, int PW, bool Z8, typename TA, typename TACC>
+__global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, int64_t lda, int64_t m, int n,
                                                      const double* __restrict__ B, int64_t ldb,
                                                      const IDX* __restrict__ idx, int d, int zeta, int chunk,
                                                      int ncols, double* __restrict__ Y, int64_t ldy,
@@ -96,7 +98,8 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
                                                      int write_bnorm) {
   static_assert(!Z8 || sizeof(IDX) == 2, "the 16-byte index load packs eight 16-bit entries");
   constexpr int RU = PW >= 16 ? 1 : (PW >= 8 ? 2 : 4);  // rows in flight per thread (register budget)
-  extern __shared__ double ysh[];  // [PW][chunk]
+  extern __shared__ __align__(16) unsigned char ysh_raw[];
+  TACC* ysh = reinterpret_cast<TACC*>(ysh_raw);  // [PW][chunk]
   __shared__ double sred[NT / 64];
   const int npanels = (ncols + PW - 1) / PW;
   const int pnl = blockIdx.x % npanels;
@@ -107,15 +110,17 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
   const int hc = min(chunk, d - h0);
   const int tid = threadIdx.x;
 
-  for (int i = tid; i < PW * chunk; i += NT) ysh[i] = 0.0;
+  for (int i = tid; i < PW * chunk; i += NT) ysh[i] = (TACC)0;
   __syncthreads();
 
-  const double* colp[PW];
+  const TA* colA[PW];
+  const double* colB[PW];
   double ss[PW];
 #pragma unroll
   for (int p = 0; p < PW; ++p) {
     const int col = c0 + p;
-    colp[p] = (p < np) ? ((col < n) ? A + (int64_t)col * lda : B + (int64_t)(col - n) * ldb) : nullptr;
+    colA[p] = (p < np && col < n) ? A + (int64_t)col * lda : nullptr;
+    colB[p] = (p < np && col >= n) ? B + (int64_t)(col - n) * ldb : nullptr;
     ss[p] = 0.0;
   }
   auto scatter = [&](uint32_t ev, const double (&a)[PW]) {
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
       const bool neg = (ev & 1u) != 0;
 #pragma unroll
       for (int p = 0; p < PW; ++p)
-        if (p < np) atomicAdd(&ysh[p * chunk + pos], neg ? -a[p] : a[p]);
+        if (p < np) atomicAdd(&ysh[p * chunk + pos], (TACC)(neg ? -a[p] : a[p]));
     }
   };
 
@@ -136,7 +141,8 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
       const int64_t i = i0 + (int64_t)u * NT;
       const bool ok = i < m;
 #pragma unroll
-      for (int p = 0; p < PW; ++p) a[u][p] = (ok && p < np) ? colp[p][i] : 0.0;
+      for (int p = 0; p < PW; ++p)
+        a[u][p] = (ok && p < np) ? (colA[p] ? (double)colA[p][i] : colB[p][i]) : 0.0;
       if (Z8) e8[u] = ok ? *reinterpret_cast<const uint4*>(idx + i * 8) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
@@ -170,46 +176,71 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const double* __restrict__ 
     if (col < n) {
       if (scale_by_norm && nrm2 > 0.0) f = inv_sqrt_zeta / sqrt(nrm2);
     }
-    for (int h = tid; h < hc; h += NT) Y[(int64_t)col * ldy + h0 + h] = ysh[p * chunk + h] * f;
+    for (int h = tid; h < hc; h += NT) Y[(int64_t)col * ldy + h0 + h] = (double)ysh[p * chunk + h] * f;
   }
 }
 
-template <typename IDX, int PW>
-void launch_apply_pw(const double* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx,
-                     int d, int zeta, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
+template <typename IDX, int PW, typename TA, typename TACC>
+void launch_apply_pw(const TA* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx, int d,
+                     int zeta, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
                      int nchunks, hipStream_t s) {
   constexpr int NT = 1024;
   const int npanels = (ncols + PW - 1) / PW;
-  const size_t shmem = (size_t)PW * chunk * sizeof(double);
+  const size_t shmem = (size_t)PW * chunk * sizeof(TACC);
   const dim3 grid((unsigned)(npanels * nchunks));
   if constexpr (sizeof(IDX) == 2) {
     if (zeta == 8) {
-      (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, true>,
+      (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, true, TA, TACC>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, true>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
-                         (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
+      hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, true, TA, TACC>), grid, dim3(NT), shmem, s, A, lda, m, n, B,
+                         ldb, (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
       return;
     }
   }
-  {
-    (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, false>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
-                       (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
-  }
+  (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, false, TA, TACC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, false, TA, TACC>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
+                     (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
 }
 
-template <typename IDX>
-void launch_apply(const double* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx, int d,
+template <typename IDX, typename TA, typename TACC>
+void launch_apply(const TA* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx, int d,
                   int zeta, int pw, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
                   int nchunks, hipStream_t s) {
   switch (pw) {
-    case 16: launch_apply_pw<IDX, 16>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 8: launch_apply_pw<IDX, 8>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 4: launch_apply_pw<IDX, 4>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 2: launch_apply_pw<IDX, 2>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    default: launch_apply_pw<IDX, 1>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 16: launch_apply_pw<IDX, 16, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 8: launch_apply_pw<IDX, 8, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 4: launch_apply_pw<IDX, 4, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 2: launch_apply_pw<IDX, 2, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    default: launch_apply_pw<IDX, 1, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
   }
+}
+
+template <typename TA, typename TACC>
+hipError_t sketch_apply_t(const TA* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, int nb,
+                          const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy, double* colnorm2,
+                          bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s) {
+  const int ncols = n + (B ? nb : 0);
+  const int lds_elems = lds_bytes / (int)sizeof(TACC);
+  const int chunk = d < lds_elems ? d : lds_elems;
+  int fit = lds_elems / d;  // columns of Y that fit in LDS at once
+  int pw = 1;
+  while (pw * 2 <= fit && pw * 2 <= 16 && pw < ncols) pw *= 2;
+  const int nchunks = (d + chunk - 1) / chunk;
+  if (idx16)
+    launch_apply<uint16_t, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
+                                     scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
+  else
+    launch_apply<uint32_t, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
+                                     scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
+  return hipGetLastError();
+}
+
+__global__ void k_to_fp32(const double* __restrict__ A, int64_t lda, int64_t m, int n, float* __restrict__ A32,
+                          int64_t lda32) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  for (int64_t r = q; r < m; r += (int64_t)gridDim.x * blockDim.x) A32[(int64_t)c * lda32 + r] = (float)A[(int64_t)c * lda + r];
 }
 
 }  // namespace
@@ -233,18 +264,25 @@ hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n
                                   int nb, const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
                                   double* colnorm2, bool scale_by_norm, bool write_bnorm, int lds_bytes,
                                   hipStream_t s) {
-  const int ncols = n + (B ? nb : 0);
-  const int lds_doubles = lds_bytes / 8;
-  const int chunk = d < lds_doubles ? d : lds_doubles;
-  int fit = lds_doubles / d;  // columns of Y that fit in LDS at once
-  int pw = 1;
-  while (pw * 2 <= fit && pw * 2 <= 16 && pw < ncols) pw *= 2;
-  const int nchunks = (d + chunk - 1) / chunk;
-  if (idx16)
-    launch_apply<uint16_t>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
-                           scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
-  else
-    launch_apply<uint32_t>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
-                           scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
+  return sketch_apply_t<double, double>(A, lda, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
+                                        scale_by_norm, write_bnorm, lds_bytes, s);
+}
+
+hipError_t fs_launch_sketch_apply_fp32(const double* A, int64_t lda, const float* A32, int64_t lda32, int64_t m,
+                                       int n, const double* B, int64_t ldb, int nb, const void* idx, bool idx16,
+                                       int d, int zeta, double* Y, int64_t ldy, double* colnorm2,
+                                       bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s) {
+  if (A32)
+    return sketch_apply_t<float, float>(A32, lda32, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
+                                        scale_by_norm, write_bnorm, lds_bytes, s);
+  return sketch_apply_t<double, float>(A, lda, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
+                                       scale_by_norm, write_bnorm, lds_bytes, s);
+}
+
+hipError_t fs_launch_to_fp32(const double* A, int64_t lda, int64_t m, int n, float* A32, int64_t lda32, hipStream_t s) {
+  if (n < 1 || m < 1) return hipSuccess;
+  const int64_t bx = (m + 255) / 256;
+  const unsigned gx = (unsigned)(bx < 1024 ? bx : 1024);
+  hipLaunchKernelGGL(k_to_fp32, dim3(gx, (unsigned)n), dim3(256), 0, s, A, lda, m, n, A32, lda32);
   return hipGetLastError();
 }

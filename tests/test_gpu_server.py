@@ -43,12 +43,26 @@ def test_mixed_stream_all_backward_stable(ctx):
         dev = [(dev_colmajor(P.A), dev_vec(P.b), torch.zeros(P.A.shape[1], dtype=torch.float64, device="cuda"))
                for P, _ in probs]
         torch.cuda.synchronize()
-        tickets = [binding.batched_submit(srv, A, b, x, method=meth) for (A, b, x), (_, meth) in zip(dev, probs)]
+        # every other pair of requests runs the mixed-precision form (FP32 sketch, FP64 fallback)
+        om = [None] * len(probs)
+        for i, (P, _) in enumerate(probs):
+            if (i // 2) % 2:
+                om[i] = binding.fs_options_default(*P.A.shape)
+                om[i].precision = binding.FS_MIXED
+        tickets = [binding.batched_submit(srv, A, b, x, method=meth, opts=o)
+                   for (A, b, x), (_, meth), o in zip(dev, probs, om)]
         for t in tickets:
             binding.fs_server_wait(srv, t)
-        for t, (P, meth), (_, _, x) in zip(tickets, probs, dev):
+        for t, (P, meth), (_, _, x), o in zip(tickets, probs, dev, om):
             done, status, info = binding.batched_poll(srv, t)
             assert done and status in (0, binding.FS_WARN_NOT_CONVERGED), (status, info.to_dict())
+            fb = bool(info.flags & binding.FS_FLAG_FP64_SKETCH)
+            # the fallback is taken exactly when the FP32 sketch's condest passes u32 condest > 0.5
+            # (info.condest is then the FP64 sketch's, equal to it up to u32 condest relative)
+            if o is None:
+                assert not fb
+            else:
+                assert (info.condest * 2.0**-24 > 0.4) if fb else (info.condest * 2.0**-24 <= 0.5), info.to_dict()
             xh = host(x)
             bg = be.relative_backward_error(P.A, P.b, xh, P.sigma, P.V)
             assert bg <= 1e-14, (P.A.shape, P.kappa, meth, bg, info.to_dict())
