@@ -345,6 +345,109 @@ __global__ void k_svd_sort_write(const double* __restrict__ Gm, const double* __
     for (int q = threadIdx.x; q < n; q += 256) Uout[(int64_t)rk * ldu + q] = U[(int64_t)i * n + q];
 }
 
+// ---------------------------------------------------------------- orthogonality correction of V
+// The Jacobi sweeps stop once every pair satisfies |v_i^T v_j| <= tol (tol = n u), so the normalized
+// columns are orthogonal only to n u.  The preconditioner V Sigma^{-1} turns that into
+// R V Sigma^{-1} = J Sigma (V^T V) Sigma^{-1}, whose (i, j) entry carries sigma_i / sigma_j times the
+// cosine: up to condest * n u, far above 1 at condest ~ 1e13 and n ~ 1000.  One first-order Cholesky
+// step restores orthogonality to working precision: with C = V^T V - I and T = triu(C, 1) + diag(C) / 2
+// (V^T V = (I + T)^T (I + T) + O(C^2)), V <- V (I + T)^{-1} ~= V - V T.  Columns are sorted by
+// decreasing sigma, so the remaining lower-triangular coupling is damped (sigma_i / sigma_j <= 1).
+//
+// Both products run on the FP64 matrix cores: a 256-thread work-group owns a 64 x 64 output tile,
+// each wave a 32 x 32 block (2 x 2 v_mfma_f64_16x16x4f64 accumulators); operands come straight from
+// global memory (V is 8 MB at n = 1000 and stays in L2 / MALL).
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int OC_T = 64;
+
+// Tc[i, j] (ld n) = v_i^T v_j for i < j, (v_i^T v_i - 1) / 2 on the diagonal, 0 below (tiles on or
+// above the diagonal only; tiles wholly below it are never read).
+__global__ __launch_bounds__(256) void k_v_gram_upper(const double* __restrict__ V, int64_t ldv, int n,
+                                                      double* __restrict__ Tc) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  if (I > J) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = I * OC_T + (w >> 1) * 32, j0 = J * OC_T + (w & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int ia[2] = {i0 + lr, i0 + 16 + lr};
+  const int jb[2] = {j0 + lr, j0 + 16 + lr};
+  for (int k = 0; k < n; k += 16) {
+    double av[4][2], bv[4][2];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = k + 4 * s + lk;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[s][q] = (kk < n && ia[q] < n) ? V[(int64_t)ia[q] * ldv + kk] : 0.0;
+        bv[s][q] = (kk < n && jb[q] < n) ? V[(int64_t)jb[q] * ldv + kk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + a * 16 + 4 * r + lk, j = j0 + b * 16 + lr;
+        if (i >= n || j >= n) continue;
+        const double c = acc[a][b][r];
+        Tc[(int64_t)j * n + i] = (i < j) ? c : ((i == j) ? 0.5 * (c - 1.0) : 0.0);
+      }
+}
+
+// Vout[:, j] (ld n) = V[:, j] - sum_{i <= j} V[:, i] Tc[i, j].
+__global__ __launch_bounds__(256) void k_v_correct(const double* __restrict__ V, int64_t ldv, int n,
+                                                   const double* __restrict__ Tc, double* __restrict__ Vout) {
+  const int I = blockIdx.y, J = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = I * OC_T + (w >> 1) * 32, j0 = J * OC_T + (w & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int kend = min(n, (J + 1) * OC_T);  // Tc is upper triangular
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  const int ra[2] = {r0 + lr, r0 + 16 + lr};
+  const int jb[2] = {j0 + lr, j0 + 16 + lr};
+  for (int k = 0; k < kend; k += 16) {
+    double av[4][2], bv[4][2];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = k + 4 * s + lk;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[s][q] = (kk < kend && ra[q] < n) ? V[(int64_t)kk * ldv + ra[q]] : 0.0;
+        bv[s][q] = (kk < kend && jb[q] < n) ? Tc[(int64_t)jb[q] * n + kk] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][a], bv[s][b], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + a * 16 + 4 * r + lk, j = j0 + b * 16 + lr;
+        if (row >= n || j >= n) continue;
+        Vout[(int64_t)j * n + row] = V[(int64_t)j * ldv + row] - acc[a][b][r];
+      }
+}
+
 }  // namespace
 
 namespace {
@@ -437,7 +540,15 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   }
   hipLaunchKernelGGL(k_svd_norms, dim3(n), dim3(256), 0, s, Gm, n, norms);
   hipLaunchKernelGGL(k_svd_sort_write, dim3(n), dim3(256), 0, s, Gm, Uarg, n, norms, sigma, V, ldv, Uout, ldu);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // orthogonality correction of V (Gm and Uacc are free once sorted and written): Tc in Gm, the
+  // corrected V in Uacc, copied back to V
+  const unsigned T = (unsigned)((n + OC_T - 1) / OC_T);
+  hipLaunchKernelGGL(k_v_gram_upper, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm);
+  hipLaunchKernelGGL(k_v_correct, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm, Uacc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipMemcpy2DAsync(V, sizeof(double) * ldv, Uacc, sizeof(double) * n, sizeof(double) * n, n,
+                          hipMemcpyDeviceToDevice, s);
 }
 
 hipError_t fs_launch_svd(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, void* work,

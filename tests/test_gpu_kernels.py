@@ -114,7 +114,8 @@ def test_qr_backward_property_ill_conditioned(ctx, d, k, kappa):
 
 
 # ---------------------------------------------------------------- SVD of R
-@pytest.mark.parametrize("n,kappa", [(50, 1e10), (301, 1e12), (7, 1.0), (1000, 1e10), (1999, 1e6), (130, 1e14)])
+@pytest.mark.parametrize("n,kappa", [(50, 1e10), (301, 1e12), (7, 1.0), (1000, 1e10), (1999, 1e6), (130, 1e14),
+                                     (1000, 1e14), (300, 1e13)])
 def test_svd_of_triangular(ctx, n, kappa):
     from paper_2406_03468_amd import binding
     rng = np.random.default_rng(n)
@@ -134,6 +135,11 @@ def test_svd_of_triangular(ctx, n, kappa):
     assert np.linalg.norm(Vg.T @ Vg - np.eye(n)) <= 1e-12 * n
     assert np.linalg.norm(R.T @ R - (Vg * sg**2) @ Vg.T) <= 1e-13 * n * sr[0] ** 2
     assert 1 <= sweeps <= 40
+    # V is orthogonal to working precision (not only to the Jacobi tolerance n u), so the
+    # preconditioner V Sigma^{-1} keeps R V Sigma^{-1} orthogonal up to O(1) even at condest 1e14
+    # (the normalized Jacobi columns alone give cond up to ~condest n u: ~20 at n = 1000, 1e14)
+    assert np.abs(Vg.T @ Vg - np.eye(n)).max() <= 4 * U * np.sqrt(n)
+    assert np.linalg.cond(R @ (Vg / sg)) <= 1.2
 
 
 # ---------------------------------------------------------------- fused passes

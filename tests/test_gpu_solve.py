@@ -77,6 +77,18 @@ def test_c1_backward_stable_vs_oracle(ctx, kappa, rnorm, method, precond):
     assert abs(info.normest - ref.normest) <= 1e-12 * ref.normest
 
 
+@pytest.mark.parametrize("m,n,kappa", [(30000, 300, 1e13), (30000, 300, 1e14), (60000, 1000, 1e14)])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_high_kappa_larger_n(ctx, m, n, kappa, precond):
+    """Condition numbers near the rank-truncation edge at n in the hundreds to a thousand: both
+    preconditioners (R^{-1} and V Sigma^{-1}) must stay backward stable and converge."""
+    P = make_problem(m, n, kappa, 1e-4, seed=3)
+    status, info, x = _solve(ctx, P, "fossils", precond=precond)
+    assert status == 0 and not (info.flags & 2), info.to_dict()
+    assert be.relative_backward_error(P.A, P.b, x, P.sigma, P.V) <= 1e-14
+    assert max(info.iters) <= 20, info.to_dict()
+
+
 def test_table2_norm_of_c_gpu(ctx):
     """Table 2 magnitudes on the GPU: ||c_0|| ~ 3e-7, ||c_1|| ~ 1.9e-11 (within 10x)."""
     P = make_problem(4000, 50, 1e12, 1e-6, seed=1)
