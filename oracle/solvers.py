@@ -123,6 +123,43 @@ def polyak_coefficients(eta):
     return (1.0 - beta) ** 2, beta
 
 
+def lsqr_iterate(apply_B, apply_BT, r, c, q):
+    """Paige and Saunders' LSQR for min || r - B y || from y = 0, given c = B^T r: Golub-Kahan
+    bidiagonalization (beta_1 u_1 = r, alpha_1 v_1 = B^T u_1 = c / beta_1, then
+    beta u' = B v - alpha u, alpha v' = B^T u' - beta v) with a Givens rotation per step.  Yields
+    (Delta, y, done) after each of at most q steps; Delta is the step's update of y, done is set when
+    the bidiagonalization terminates (alpha or beta = 0: y is the exact minimizer)."""
+    bet = float(np.linalg.norm(r))
+    cn = float(np.linalg.norm(c))
+    y = np.zeros_like(c)
+    if bet == 0.0 or cn == 0.0:
+        return
+    uvec = r / bet
+    alf = cn / bet
+    vvec = c / cn
+    w = vvec.copy()
+    phibar, rhobar = bet, alf
+    for _ in range(q):
+        t = apply_B(vvec) - alf * uvec
+        bet = float(np.linalg.norm(t))
+        if bet > 0.0:
+            uvec = t / bet
+        s_v = apply_BT(uvec) - bet * vvec
+        alf = float(np.linalg.norm(s_v))
+        if alf > 0.0:
+            vvec = s_v / alf
+        rho = math.hypot(rhobar, bet)
+        cs, sn = rhobar / rho, bet / rho
+        theta = sn * alf
+        rhobar = -cs * alf
+        phi = cs * phibar
+        phibar = sn * phibar
+        Delta = (phi / rho) * w
+        y = y + Delta
+        w = vvec - (theta / rho) * w
+        yield Delta, y, (bet == 0.0 or alf == 0.0)
+
+
 def q0_theorem71(kappa, eta):
     """eq:iterations: q_0 = max(1 + 2 log(1/(kappa u)) / log(1/(1.01 eta)), 11), rounded up."""
     ku = kappa * U_ROUND
@@ -155,7 +192,8 @@ def _stop_first(Delta, thr):
 
 
 def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
-    """FOSSILS (Algorithm 4 / Algorithm 2) or SPIR (Algorithm 3 with CG) for min ||b - A x||."""
+    """FOSSILS (Algorithm 4 / Algorithm 2), SPIR (Algorithm 3 with CG) or SPIR with LSQR
+    (method "spir_lsqr") for min ||b - A x||."""
     opts = opts or Options()
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -308,8 +346,31 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
                     if be_sk < fro * u:
                         converged = True
                         break
+        elif method == "spir_lsqr":
+            # LSQR on min || r_i - (A_s P) dy || (the LSQR form of SPIR, Section 4.3); the stopping
+            # rules are SPIR's with Delta = the update of dy.
+            dy = np.zeros_like(c)
+            steps = lsqr_iterate(lambda y: As @ pre.P(y), lambda v: pre.PT(As.T @ v), b - As @ x, c,
+                                 opts.max_inner)
+            for j, (Delta, dy, done) in enumerate(steps):
+                it += 1
+                if done:
+                    converged = True
+                    break
+                if i == 0 and _stop_first(Delta, thr_first):
+                    converged = True
+                    break
+                if i == 1 and j % opts.kw_every == 0:
+                    xh = x + pre.P(dy)
+                    rh = b - As @ xh
+                    be_sk = kw_from_svd(sig_full, V_full, As.T @ rh, theta, np.linalg.norm(rh), np.linalg.norm(xh))
+                    if be_sk < fro * u:
+                        converged = True
+                        break
+            else:
+                converged = converged or it == 0
         else:
-            raise ValueError("method must be 'fossils' or 'spir'")
+            raise ValueError("method must be 'fossils', 'spir' or 'spir_lsqr'")
         x = x + pre.P(dy)                                     # Alg 1: x_{i+1} = x_i + P dy_i
         iters.append(it)
         xs.append(x / dcol)
@@ -337,6 +398,11 @@ def fossils_multi(A, B, opts: Optional[Options] = None):
 
 def spir(A, b, opts: Optional[Options] = None) -> Result:
     return solve(A, b, "spir", opts)
+
+
+def spir_lsqr(A, b, opts: Optional[Options] = None) -> Result:
+    """SPIR with LSQR as the Krylov method of each refinement step (Section 4.3)."""
+    return solve(A, b, "spir_lsqr", opts)
 
 
 def sketch_and_solve(A, b, d, zeta=8, seed=12345):

@@ -238,3 +238,49 @@ def test_mixed_precision_sketch_and_fallback():
     P = make_problem(4000, 50, 1e10, 1e-6, seed=3)
     r = solvers.fossils(P.A, P.b, solvers.Options(precision="mixed", mixed_fallback=False))
     assert r.flags & solvers.FLAG_NOT_CONVERGED or be.relative_backward_error(P.A, P.b, r.x, P.sigma, P.V) > 1e-14
+
+
+def test_lsqr_iterate_matches_scipy_lsqr_and_cg():
+    """The oracle's LSQR steps against scipy's LSQR (same algorithm, exactly q iterations) and, in
+    exact arithmetic, against CG on the normal equations (Section 4.3: CG and LSQR are equivalent)."""
+    from scipy.sparse.linalg import lsqr
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((300, 20)) @ np.diag(np.logspace(0, 1, 20))  # a preconditioned-like kappa
+    r = rng.standard_normal(300)
+    c = B.T @ r
+    # (beyond ~q = 10 the three recurrences drift apart by their own rounding: Lanczos without
+    # reorthogonalization; every one of them still converges, checked at q = 60 below)
+    for q in (1, 3, 6, 8):
+        ys = [y for _, y, _ in solvers.lsqr_iterate(lambda v: B @ v, lambda v: B.T @ v, r, c, q)]
+        ref = lsqr(B, r, atol=0, btol=0, conlim=0, iter_lim=q)[0]
+        assert np.linalg.norm(ys[-1] - ref) <= 1e-12 * np.linalg.norm(ref)
+        # CG on B^T B y = c from 0, q steps
+        y = np.zeros(20)
+        res = c.copy()
+        p = c.copy()
+        for _ in range(q):
+            qv = B.T @ (B @ p)
+            a = (res @ res) / (p @ qv)
+            y = y + a * p
+            rn = res - a * qv
+            p = rn + (rn @ rn) / (res @ res) * p
+            res = rn
+        assert np.linalg.norm(ys[-1] - y) <= 1e-12 * np.linalg.norm(y)
+    # q = n steps solve the problem exactly (up to rounding)
+    ys = [y for _, y, _ in solvers.lsqr_iterate(lambda v: B @ v, lambda v: B.T @ v, r, c, 60)]
+    assert np.linalg.norm(ys[-1] - np.linalg.lstsq(B, r, rcond=None)[0]) <= 1e-10 * np.linalg.norm(ys[-1])
+
+
+@pytest.mark.parametrize("kappa,rnorm", [(1e10, 1e-6), (1e4, 1.0), (1e2, 1e-10), (1e13, 1e-8)])
+@pytest.mark.parametrize("precond", ["qr", "svd"])
+def test_spir_lsqr_backward_stable(kappa, rnorm, precond):
+    """LSQR-based SPIR meets the same bar as the CG form (Section 4.3: similarly stable)."""
+    P = make_problem(4000, 50, kappa, rnorm, seed=0)
+    r = solvers.spir_lsqr(P.A, P.b, solvers.Options(precond=precond))
+    assert be.relative_backward_error(P.A, P.b, r.x, P.sigma, P.V) <= 1e-14
+    xq = hh.qr_lstsq(P.A, P.b)
+    fe = np.linalg.norm(r.x - P.x_true) / np.linalg.norm(P.x_true)
+    fq = max(np.linalg.norm(xq - P.x_true) / np.linalg.norm(P.x_true), kappa * 2.0**-52)
+    assert fe <= 10 * fq
+    cg = solvers.spir(P.A, P.b, solvers.Options(precond=precond))
+    assert abs(r.iters[0] - cg.iters[0]) <= 2
