@@ -75,6 +75,9 @@ typedef struct fs_options {
   int32_t steps;          /* refinement steps: 2 (the method) or 1 ("one step" variant) */
   int32_t precision;      /* FS_FP64, or FS_MIXED: FP32 sketch (see fossils_solve_mixed) */
   int32_t max_sweeps;     /* Jacobi sweep cap of the SVD of R */
+  int32_t graph_sweeps;   /* 1: the inner iterations run as a captured HIP graph of kw_every iterations,
+                             replayed until the device-side stop flag is set (one launch and one
+                             host poll per kw_every iterations); 0: kernel-by-kernel launches */
 } fs_options;
 
 /* Per-solve report. */
@@ -117,6 +120,15 @@ fs_status fossils_solve(fs_context ctx, int64_t m, int32_t n, const double* A, i
 fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                      double* x, const fs_options* opts, fs_info* info);
 
+/* SPIR with LSQR as the Krylov method (Section 4.3: LSQR on the preconditioned least-squares
+ * problem of each refinement step instead of CG on its normal equations; the paper reports the two
+ * similarly stable).  Each step runs Paige and Saunders' bidiagonalization on A_s P from
+ * beta_1 u_1 = b - A_s x_i; one read of A per iteration (the residual pass that also stores the
+ * m-vector alpha u - A_s P v), plus 16 m bytes of workspace.  Same sketch, preconditioner, start
+ * and stopping rules as spir_solve (Delta = the update of the correction). */
+fs_status spir_lsqr_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                          double* x, const fs_options* opts, fs_info* info);
+
 /* FOSSILS for k (1..64) right-hand sides sharing A: column j of X (n x k, ldx >= n) solves the
  * least-squares problem with column j of B (m x k, ldb >= m), both column-major device arrays.
  * One sketch S [A B], one QR and one SVD serve every column (x_0 = R^{-1} t_j); the inner
@@ -129,12 +141,13 @@ fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, const double
                               const double* B, int64_t ldb, double* X, int64_t ldx, const fs_options* opts,
                               fs_info* info);
 
-/* Mixed-precision form: the sketch S [A_s b] is accumulated in FP32 (from A32 = fl32(A), column-major
- * lda32 >= m, when A32 is not NULL, else from A converted on the fly); QR, SVD and the whole
- * refinement (every pass over A, Alg 1 lines 5-7) stay FP64 on A.  An FP32 sketch perturbs S A by
- * about u32 ||A||, which keeps A_s R^{-1} well conditioned only while condest * u32 is small; above
- * the threshold (u32 condest > 0.5, condest > ~8.4e6) the sketch is redone in FP64 and info->flags gets
- * FS_FLAG_FP64_SKETCH.  The result meets the same backward-error bar as fossils_solve. */
+/* Mixed-precision form: the sketch S [A_s b] is taken of the single-precision copy of A (A32 =
+ * fl32(A), column-major lda32 >= m, when A32 is not NULL, else A rounded to FP32 as it is read), with
+ * FP64 sums; QR, SVD and the whole refinement (every pass over A) stay FP64 on A.  The FP32 copy
+ * perturbs S A by about u32 ||A||, which keeps A_s R^{-1} well conditioned only while condest * u32
+ * is small; above the threshold (u32 condest > 2, condest > ~3.4e7) the sketch is redone in FP64 and
+ * info->flags gets FS_FLAG_FP64_SKETCH.  The result meets the same backward-error bar as
+ * fossils_solve. */
 fs_status fossils_solve_mixed(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const float* A32,
                               int64_t lda32, const double* b, double* x, const fs_options* opts, fs_info* info);
 /* A32 = fl32(A) on the context's stream (for callers that keep an FP32 copy resident). */
@@ -198,8 +211,9 @@ fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32
 
 /* A solve request.  A (m x n, lda >= m), b (m) and x (n) are device arrays owned by the caller;
  * they must stay valid (and A, b unchanged) until batched_poll reports the ticket done.  method:
- * FS_METHOD_FOSSILS or FS_METHOD_SPIR.  opts may be NULL (defaults); it is copied at submission. */
-enum { FS_METHOD_FOSSILS = 0, FS_METHOD_SPIR = 1 };
+ * FS_METHOD_FOSSILS, FS_METHOD_SPIR or FS_METHOD_SPIR_LSQR.  opts may be NULL (defaults); it is
+ * copied at submission. */
+enum { FS_METHOD_FOSSILS = 0, FS_METHOD_SPIR = 1, FS_METHOD_SPIR_LSQR = 2 };
 typedef struct {
   int32_t method;
   int64_t m;

@@ -54,12 +54,8 @@ def sketch_Ab(A: np.ndarray, b: np.ndarray, d: int, zeta: int, seed: int) -> np.
 
 
 def sketch_fp32(M: np.ndarray, d: int, zeta: int, seed: int) -> np.ndarray:
-    """The mixed-precision form's sketch: S fl32(M) with float32 accumulation (any summation order),
-    times fl32(zeta^{-1/2}); returned in float64.  Each entry is within (k + 2) u32 (|S| |M|) of the
-    exact one, k the entry's count of nonzero terms, instead of (k + 2) u64."""
-    M2 = M.reshape(M.shape[0], -1)
-    S = sparse_sign_matrix(M2.shape[0], d, zeta, seed).astype(np.float32)
-    Y = np.asarray(S @ np.asarray(M2, dtype=np.float32), dtype=np.float32)
-    Y = Y * np.float32(1.0 / np.sqrt(zeta))
-    Y = np.asfortranarray(Y.astype(np.float64))
-    return Y if M.ndim == 2 else Y[:, 0]
+    """The mixed-precision form's sketch: S fl32(M), the sketch of the single-precision copy, with
+    double-precision sums.  Each entry is within (u32 + (k + 2) u) (|S| |M|) of S M, k the entry's
+    count of nonzero terms."""
+    M32 = np.asarray(M, dtype=np.float32).astype(np.float64)
+    return sketch(M32, d, zeta, seed)

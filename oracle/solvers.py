@@ -45,11 +45,12 @@ FLAG_NOT_CONVERGED = 2
 FLAG_FP64_SKETCH = 4
 
 U32 = 2.0**-24
-# mixed precision: the FP32 sketch is kept while u32 condest <= 0.5 (see solve()); measured with this
-# oracle on the 4000 x 50 problems, the FP32-sketch preconditioner needs the FP64 iteration counts up
-# to u32 condest ~ 0.5 and degrades beyond u32 condest ~ 1 (it fails to converge at kappa = 1e10)
+# mixed precision: the sketch of the FP32 copy is kept while u32 condest <= 2 (see solve()); measured
+# with this oracle on 4000 x 50 problems (fallback disabled), that preconditioner needs the FP64
+# iteration counts up to u32 condest ~ 6 (kappa = 1e8), three times as many at ~ 10 and fails to
+# converge beyond ~ 11 (kappa >= 1e9)
 MIXED_COND_FACTOR = U32
-MIXED_DISTORTION = 0.5
+MIXED_DISTORTION = 2.0
 
 
 @dataclass
@@ -216,16 +217,22 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
     # Alg 4: embedding parameters and Polyak coefficients.
     eta = (opts.eta if opts.eta is not None else math.sqrt(n / dsk)) * opts.eta_factor
     alpha, beta = polyak_coefficients(eta)
-    # Alg 1 / Alg 4: sketch [A b] with one embedding (single precision in the mixed form).
+    # Alg 1 / Alg 4: sketch [A b] with one embedding (of the single-precision copy of A in the mixed
+    # form, whose column norms then give the scaling).
     flags = 0
     if opts.precision == "mixed":
-        Y = sketch_fp32(np.column_stack([As, b]), dsk, opts.zeta, opts.seed)
-        # An FP32 sketch is S A perturbed by ~u32 ||A||: R from it preconditions A_s well only while
-        # condest u32 is small (Lemma 6.3 with u32 in place of u); beyond that, redo it in FP64.
+        A32 = A.astype(np.float32).astype(np.float64)
+        dcol32 = column_norms(A32) if opts.column_scaling else np.ones(n)
+        Y = sketch_Ab(A32 / dcol32, b, dsk, opts.zeta, opts.seed)
+        # The sketch of fl32(A) is S A perturbed by ~u32 ||A||: R from it preconditions A_s well only
+        # while condest u32 is small (Lemma 6.3 with u32 in place of u); beyond that, redo it in FP64.
         cond32 = np.linalg.cond(np.linalg.qr(Y[:, :n], mode="r"))
         if opts.mixed_fallback and not (cond32 * MIXED_COND_FACTOR <= MIXED_DISTORTION):
             flags |= FLAG_FP64_SKETCH
             Y = sketch_Ab(As, b, dsk, opts.zeta, opts.seed)
+        else:
+            dcol = dcol32
+            As = A / dcol
     elif opts.precision == "fp64":
         Y = sketch_Ab(As, b, dsk, opts.zeta, opts.seed)
     else:

@@ -44,7 +44,7 @@ class FsOptions(ctypes.Structure):
         ("d", c_int32), ("zeta", c_int32), ("seed", c_uint64), ("eta", c_double), ("eta_factor", c_double),
         ("gamma", c_double), ("rho", c_double), ("kw_every", c_int32), ("max_inner", c_int32),
         ("tau_factor", c_double), ("column_scaling", c_int32), ("precond", c_int32), ("fixed_q", c_int32),
-        ("steps", c_int32), ("precision", c_int32), ("max_sweeps", c_int32),
+        ("steps", c_int32), ("precision", c_int32), ("max_sweeps", c_int32), ("graph_sweeps", c_int32),
     ]
 
 
@@ -71,6 +71,7 @@ class FsRequest(ctypes.Structure):
 
 FS_METHOD_FOSSILS = 0
 FS_METHOD_SPIR = 1
+FS_METHOD_SPIR_LSQR = 2
 
 
 class FossilsError(RuntimeError):
@@ -92,6 +93,8 @@ _SIGS = [
                                 ctypes.POINTER(FsInfo)]),
     ("spir_solve", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
                              ctypes.POINTER(FsInfo)]),
+    ("spir_lsqr_solve", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
+                                  ctypes.POINTER(FsInfo)]),
     ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
     ("fossils_solve_mixed", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64, c_vp, c_vp,
@@ -222,6 +225,12 @@ def fossils_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
 
 def spir_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
     s, info = _solve(load().spir_solve, ctx, A, b, x, opts)
+    _check(s)
+    return s, info
+
+
+def spir_lsqr_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
+    s, info = _solve(load().spir_lsqr_solve, ctx, A, b, x, opts)
     _check(s)
     return s, info
 

@@ -13,9 +13,9 @@
 #include "state.hpp"
 
 constexpr double FS_U_ROUND = 2.220446049250313e-16;
-// Mixed precision: the FP32 sketch is accepted while u32 condest <= 0.5 (condest <= ~8.4e6).
+// Mixed precision: the sketch of the FP32 copy is accepted while u32 condest <= 2 (condest <= ~3.4e7).
 constexpr double FS_MIXED_COND_FACTOR = 5.9604644775390625e-08;
-constexpr double FS_MIXED_DISTORTION = 0.5;
+constexpr double FS_MIXED_DISTORTION = 2.0;
 
 struct DevBuf {
   void* p = nullptr;
@@ -25,6 +25,7 @@ struct DevBuf {
 struct Workspace {
   DevBuf idx, Y, colnorm2, dinv, qrwork, svdwork, sigma, V, UR, partial, pr2, wscratch, gemvpart, vecs, state;
   DevBuf mwork, mvecs, mstate;  // multi-RHS solves
+  DevBuf lsqr;                  // LSQR form of SPIR: the residual r and ubar = alpha u (2 m-vectors)
 };
 
 struct fs_context_s {
@@ -37,6 +38,7 @@ struct fs_context_s {
   hipEvent_t ev[8] = {};
   // Set by a server whose slots share the GPU (see CoopBudget).
   struct CoopBudget* coop_budget = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture (created on first use)
 };
 
 // Cooperative kernels (QR, SVD) need every work-group of their grid resident at once.  Slots of a

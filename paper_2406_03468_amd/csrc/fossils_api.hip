@@ -85,6 +85,7 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (n > 15000) return FS_ERR_TOO_LARGE;       // TRSV keeps x in LDS
   if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
   if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
+  if (o.graph_sweeps != 0 && o.graph_sweeps != 1) return FS_ERR_INVALID_ARG;
   (void)m;
   return FS_OK;
 }
@@ -132,6 +133,7 @@ fs_status fs_options_default(int64_t m, int32_t n, fs_options* o) {
   o->steps = 2;
   o->precision = FS_FP64;
   o->max_sweeps = 40;
+  o->graph_sweeps = 1;
   return FS_OK;
 }
 
@@ -167,8 +169,9 @@ fs_status fs_context_destroy(fs_context c) {
   (void)hipStreamSynchronize(c->stream);
   Workspace& w = c->ws;
   for (DevBuf* b : {&w.idx, &w.Y, &w.colnorm2, &w.dinv, &w.qrwork, &w.svdwork, &w.sigma, &w.V, &w.UR, &w.partial,
-                    &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state})
+                    &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate, &w.lsqr})
     free_buf(*b);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -302,10 +305,11 @@ static fs_status ensure_pass_ws(fs_context ctx, int64_t m, int32_t n, int64_t ld
 // Enqueue one fused pass; the workspace must already be sized (ensure_pass_ws), so no buffer
 // is reallocated while earlier work on the stream may still use it.
 static fs_status run_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* zs,
-                          const double* b, double* out, const double* out_scale, double* r2_dev, const int* stop) {
+                          const double* b, double* out, const double* out_scale, double* r2_dev, const int* stop,
+                          double* rout = nullptr) {
   const PassConfig cfg = pass_config(ctx, m, n, lda);
   if (ctx->ws.partial.bytes < sizeof(double) * (size_t)cfg.G * n) return FS_ERR_INVALID_ARG;
-  PassArgs a{A, lda, m, n, zs, b, (double*)ctx->ws.partial.p, (double*)ctx->ws.pr2.p, stop};
+  PassArgs a{A, lda, m, n, zs, b, (double*)ctx->ws.partial.p, (double*)ctx->ws.pr2.p, stop, rout};
   FS_K(fs_launch_pass(a, cfg, out, out_scale, r2_dev, (double*)ctx->ws.wscratch.p, ctx->stream));
   return FS_OK;
 }
@@ -379,6 +383,7 @@ size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts) {
   b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 16 * N);  // V, U_R, vectors
   b += 8 * ((size_t)cfg.G * N + cfg.G + 64) + sizeof(DevState) + 64;
   if (!cfg.H) b += 8 * (size_t)m;
+  b += 16 * (size_t)m;  // the LSQR form's two m-vectors (counted for every method)
   return b;
 }
 
@@ -398,11 +403,55 @@ fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32
 // ---------------------------------------------------------------- the solver
 namespace {
 
-enum Method { M_FOSSILS = 0, M_SPIR = 1 };
+enum Method { M_FOSSILS = 0, M_SPIR = 1, M_SPIR_LSQR = 2 };
 
 struct Vecs {
   double *x, *x0, *c, *dy, *dy_old, *zs, *v, *u, *g, *xh, *w, *res, *p, *t, *tmp, *z;
 };
+
+// Captures `len` calls of iteration(j) (j = 0 .. len-1) on stream s into a graph and replays it up to
+// `reps` times, polling after each replay (poll sets `stopped`).  Capture is thread-local, so other
+// threads' HIP calls (the server's other slots) are unaffected; a failure inside the capture ends it
+// before returning.  The captured work is kernels only (no memset nodes).
+// The capture runs on the context's private capture stream (the caller's stream may be the null
+// stream, which cannot be captured): while capturing, `s` (the solve's launch stream, captured by
+// reference in the iteration) and ctx->stream point at it; the graph is then launched on the
+// caller's stream.
+template <typename Iter, typename Poll>
+static fs_status sweep_graph_run(fs_context ctx, hipStream_t& s, int len, int reps, Iter&& iteration, Poll&& poll,
+                                 bool& stopped) {
+  if (!ctx->cap_stream) FS_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  const hipStream_t launch = s;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  FS_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  s = ctx->cap_stream;
+  ctx->stream = ctx->cap_stream;
+  fs_status st = FS_OK;
+  for (int j = 0; j < len && st == FS_OK; ++j) st = iteration(j);
+  s = launch;
+  ctx->stream = launch;
+  const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+  if (st != FS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  FS_HIP(ec);
+  const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  FS_HIP(ei);
+  for (int r = 0; r < reps && !stopped && st == FS_OK; ++r) {
+    const hipError_t el = hipGraphLaunch(ge, launch);
+    if (el != hipSuccess) {
+      fs_set_last_hip_error(el, "hipGraphLaunch", __FILE__, __LINE__);
+      st = FS_ERR_DEVICE;
+      break;
+    }
+    st = poll();
+  }
+  (void)hipGraphExecDestroy(ge);
+  return st;
+}
 
 fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                 double* x_out, const fs_options* opts_in, fs_info* info, const float* A32 = nullptr,
@@ -435,6 +484,10 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_TRY(grow(W.vecs, sizeof(double) * (size_t)NV * n));
   FS_TRY(grow(W.state, sizeof(DevState) + 64));
   FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  const bool lsqr = (method == M_SPIR_LSQR);
+  if (lsqr) FS_TRY(grow(W.lsqr, sizeof(double) * 2 * (size_t)m));
+  double* rbuf = lsqr ? (double*)W.lsqr.p : nullptr;  // r of the last LSQR pass (m)
+  double* ubar = lsqr ? rbuf + m : nullptr;          // alpha u (m)
   double* vb = (double*)W.vecs.p;
   Vecs v{vb, vb + n, vb + 2 * n, vb + 3 * n, vb + 4 * n, vb + 5 * n, vb + 6 * n, vb + 7 * n,
          vb + 8 * n, vb + 9 * n, vb + 10 * n, vb + 11 * n, vb + 12 * n, vb + 13 * n, vb + 14 * n, vb + 15 * n};
@@ -593,27 +646,40 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   for (int step = 0; step < o.steps; ++step) {
     // residual pass at x (scaled coordinates): g = D^{-1} A^T (b - A D^{-1} x), r2
     FS_K(fs_vec_mul(n, v.x, dinv, v.zs, nullptr, s));
-    FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, nullptr));
+    FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, nullptr, rbuf));
     if (step == 0) {
       FS_K(fs_vec_first_threshold(n, v.x0, o.gamma, o.rho, st, s));
       FS_HIP(hipEventRecord(ev[5], s));
     }
     FS_TRY(applyPT(v.g, v.c, nullptr));
     // FOSSILS: dy = dy_old = c.  SPIR: dy = 0, res = p = c.
+    // LSQR: v = c / ||c||, w = v, dy = 0, ubar = alpha_1 u_1 = (alpha_1 / beta_1) r.
     if (method == M_FOSSILS) FS_K(fs_vec_step_init(nr, v.c, v.dy, v.dy_old, v.dy, false, st, s));
-    else FS_K(fs_vec_step_init(nr, v.c, v.res, v.p, v.dy, true, st, s));
+    else if (lsqr) {
+      FS_K(fs_vec_lsqr_init(nr, v.c, v.p, v.res, v.dy, st, s));
+      FS_K(fs_vec_lsqr_ubar(m, rbuf, ubar, 1.0, st, s));
+    } else FS_K(fs_vec_step_init(nr, v.c, v.res, v.p, v.dy, true, st, s));
     const bool fixed = (method == M_FOSSILS && q_fixed > 0);
     const int cap = fixed ? q_fixed - 1 : o.max_inner;
     if (fixed) FS_K(fs_vec_set_int(&st->max_inner, cap, s));
     const bool first = (step == 0) && !fixed;
     bool stopped = false;
-    for (int j = 0; j < cap && !stopped; ++j) {
+    // one inner iteration (every kernel returns at once after the device-side stop flag is set)
+    auto iteration = [&](int j) -> fs_status {
       const double* dir = (method == M_FOSSILS) ? v.dy : v.p;
       FS_TRY(applyP(dir, v.zs, dinv, nullptr, stop));                   // z' = D^{-1} P dir
-      FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, nullptr, v.v, dinv, nullptr, stop));  // v = D^{-1} A^T A z'
-      FS_TRY(applyPT(v.v, v.u, stop));                                 // u = P^T v
-      if (method == M_FOSSILS) FS_K(fs_vec_polyak(nr, v.c, v.u, v.dy, v.dy_old, st, first, s));
-      else FS_K(fs_vec_cg(nr, v.p, v.u, v.res, v.dy, st, first, s));
+      if (lsqr) {
+        // r = alpha u - A_s P v (stored), h = P^T A_s^T r, beta^2 = ||r||^2: one residual pass
+        FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, ubar, v.v, dinv, &st->r2, stop, rbuf));
+        FS_TRY(applyPT(v.v, v.u, stop));
+        FS_K(fs_vec_lsqr_step(nr, v.u, v.p, v.res, v.dy, st, first, s));
+        FS_K(fs_vec_lsqr_ubar(m, rbuf, ubar, -1.0, st, s));
+      } else {
+        FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, nullptr, v.v, dinv, nullptr, stop));  // v = D^{-1} A^T A z'
+        FS_TRY(applyPT(v.v, v.u, stop));                                 // u = P^T v
+        if (method == M_FOSSILS) FS_K(fs_vec_polyak(nr, v.c, v.u, v.dy, v.dy_old, st, first, s));
+        else FS_K(fs_vec_cg(nr, v.p, v.u, v.res, v.dy, st, first, s));
+      }
       const bool kw_now = (!fixed) && (step == 1) && (j % o.kw_every == 0);
       if (kw_now) {  // second-step rule (Alg 4): sketched KW at x_hat = x + P dy
         FS_TRY(applyP(v.dy, v.xh, nullptr, v.x, stop));
@@ -623,11 +689,24 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
         FS_K(fs_vec_gemv_vt(V, n, n, n, v.g, nullptr, v.w, stop, s));
         FS_K(fs_vec_kw(n, v.w, sigma, st, s));
       }
-      const bool poll = fixed ? (j == cap - 1) : (((j + 1) % o.kw_every) == 0 || j == cap - 1);
-      if (poll && !fixed) {
-        FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-        FS_HIP(hipStreamSynchronize(s));
-        if (ctx->st_host->stop) stopped = true;
+      return FS_OK;
+    };
+    auto poll_stop = [&]() -> fs_status {
+      FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+      FS_HIP(hipStreamSynchronize(s));
+      if (ctx->st_host->stop) stopped = true;
+      return FS_OK;
+    };
+    const int sweep = o.kw_every;
+    if (o.graph_sweeps && !fixed && cap % sweep == 0) {
+      // kw_every iterations (the KW check, when due, is the first of them) captured once as a graph
+      // and replayed; the host polls the stop flag after each replay, as the launch-by-launch loop does
+      FS_TRY(sweep_graph_run(ctx, s, sweep, cap / sweep, iteration, poll_stop, stopped));
+    } else {
+      for (int j = 0; j < cap && !stopped; ++j) {
+        FS_TRY(iteration(j));
+        const bool poll = ((j + 1) % sweep) == 0 || j == cap - 1;
+        if (poll && !fixed) FS_TRY(poll_stop());
       }
     }
     // x <- x + P dy
@@ -681,6 +760,11 @@ fs_status fossils_solve(fs_context ctx, int64_t m, int32_t n, const double* A, i
 fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b, double* x,
                      const fs_options* opts, fs_info* info) {
   return solve(ctx, M_SPIR, m, n, A, lda, b, x, opts, info);
+}
+
+fs_status spir_lsqr_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                          double* x, const fs_options* opts, fs_info* info) {
+  return solve(ctx, M_SPIR_LSQR, m, n, A, lda, b, x, opts, info);
 }
 
 fs_status fossils_solve_mixed(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const float* A32,

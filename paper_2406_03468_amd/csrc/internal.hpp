@@ -15,6 +15,7 @@ struct PassArgs {
   double* partial;       // [G][n] work-group partials
   double* partial_r2;    // [G]
   const int* stop;       // device stop flag (may be null)
+  double* rout = nullptr;  // m, residual mode only: receives r = b - A zs (may be null)
 };
 struct PassConfig {
   int H;  // tile rows (0 = unfused fallback)

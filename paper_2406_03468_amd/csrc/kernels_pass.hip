@@ -27,7 +27,7 @@ template <int H, int NT, int L, bool RESID, bool VEC>
 __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A, int64_t lda, int64_t m, int n,
                                                    const double* __restrict__ zs, const double* __restrict__ b,
                                                    double* __restrict__ partial, double* __restrict__ partial_r2,
-                                                   const int* __restrict__ stop) {
+                                                   const int* __restrict__ stop, double* __restrict__ rout) {
   static_assert(H >= 2 && (H & (H - 1)) == 0 && H <= 128, "H must be a power of two in [2,128]");
   constexpr int RP = H / 2;           // row pairs per tile == lanes per column segment
   constexpr int CPR = NT / RP;        // columns per round
@@ -129,7 +129,13 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
       const int64_t r0 = t * H + 2 * rp;  // rows past m carry zeros in a[L] and A
       w0 = (r0 < m) ? a[L].x - w0 : 0.0;
       w1 = (r0 + 1 < m) ? a[L].y - w1 : 0.0;
-      if (cb == 0) r2 = fma(w0, w0, fma(w1, w1, r2));
+      if (cb == 0) {
+        r2 = fma(w0, w0, fma(w1, w1, r2));
+        if (rout) {  // the residual itself (LSQR keeps it as its left Lanczos vector)
+          if (r0 < m) rout[r0] = w0;
+          if (r0 + 1 < m) rout[r0 + 1] = w1;
+        }
+      }
     }
     if (RESID) {
 #pragma unroll
@@ -269,10 +275,10 @@ template <int H, int NT, int L, bool RESID>
 hipError_t launch_one(const PassArgs& a, int G, bool vec, hipStream_t s) {
   if (vec)
     hipLaunchKernelGGL((k_fused_pass<H, NT, L, RESID, true>), dim3(G), dim3(NT), 0, s, a.A, a.lda, a.m, a.n, a.zs,
-                       a.b, a.partial, a.partial_r2, a.stop);
+                       a.b, a.partial, a.partial_r2, a.stop, a.rout);
   else
     hipLaunchKernelGGL((k_fused_pass<H, NT, L, RESID, false>), dim3(G), dim3(NT), 0, s, a.A, a.lda, a.m, a.n,
-                       a.zs, a.b, a.partial, a.partial_r2, a.stop);
+                       a.zs, a.b, a.partial, a.partial_r2, a.stop, a.rout);
   return hipGetLastError();
 }
 
@@ -345,11 +351,12 @@ hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out,
   } else {
     // unfused: two reads of A
     const int gb = (int)((a.m + 255) / 256);
-    hipLaunchKernelGGL(k_gemv_n, dim3(gb), dim3(256), 0, s, a.A, a.lda, a.m, a.n, a.zs, a.b, w_scratch, a.stop);
-    hipLaunchKernelGGL(k_gemv_t, dim3(a.n, cfg.G), dim3(256), 0, s, a.A, a.lda, a.m, a.n, w_scratch, a.partial,
+    double* w = (resid && a.rout) ? a.rout : w_scratch;  // the residual goes straight to rout when asked
+    hipLaunchKernelGGL(k_gemv_n, dim3(gb), dim3(256), 0, s, a.A, a.lda, a.m, a.n, a.zs, a.b, w, a.stop);
+    hipLaunchKernelGGL(k_gemv_t, dim3(a.n, cfg.G), dim3(256), 0, s, a.A, a.lda, a.m, a.n, w, a.partial,
                        cfg.G, a.stop);
     if (resid)
-      hipLaunchKernelGGL(k_sumsq_partials, dim3(cfg.G), dim3(256), 0, s, w_scratch, a.m, cfg.G, a.partial_r2, a.stop);
+      hipLaunchKernelGGL(k_sumsq_partials, dim3(cfg.G), dim3(256), 0, s, w, a.m, cfg.G, a.partial_r2, a.stop);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_reduce_partials, dim3((a.n + 63) / 64), dim3(1024), 0, s, a.partial, cfg.G, a.n, out_scale,

@@ -87,9 +87,11 @@ __global__ __launch_bounds__(256) void k_sketch_indices(int64_t col0, int64_t nc
 // np <= PW columns are active.  Each thread walks RU rows per step with all their loads issued
 // before the LDS atomics (memory-level parallelism); for zeta = 8 with 16-bit entries the eight
 // entries of a row come in one 16-byte load.  TA is the element type of A (double, or float for the
-// mixed-precision form's FP32 copy), TACC the LDS accumulator (float halves the LDS per column, so
-// twice the columns share one read of the index stream); column norms always accumulate in FP64.
-template <typename IDX, int NT, int PW, bool Z8, typename TA, typename TACC>
+// mixed-precision form's FP32 copy); R32 rounds double inputs to FP32 first (the mixed form without
+// a resident copy).  The LDS accumulator is FP64 in every form: on gfx950 an FP32 LDS atomic add
+// measured 7x slower than an FP64 one (1e6 x 8 scatters into one 12000-entry column: 10.0 ms
+// against 1.36 ms), so FP32 sums would make the sketch slower, not faster.
+template <typename IDX, int NT, int PW, bool Z8, typename TA, bool R32>
 __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, int64_t lda, int64_t m, int n,
                                                      const double* __restrict__ B, int64_t ldb,
                                                      const IDX* __restrict__ idx, int d, int zeta, int chunk,
@@ -99,7 +101,7 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
   static_assert(!Z8 || sizeof(IDX) == 2, "the 16-byte index load packs eight 16-bit entries");
   constexpr int RU = PW >= 16 ? 1 : (PW >= 8 ? 2 : 4);  // rows in flight per thread (register budget)
   extern __shared__ __align__(16) unsigned char ysh_raw[];
-  TACC* ysh = reinterpret_cast<TACC*>(ysh_raw);  // [PW][chunk]
+  double* ysh = reinterpret_cast<double*>(ysh_raw);  // [PW][chunk]
   __shared__ double sred[NT / 64];
   const int npanels = (ncols + PW - 1) / PW;
   const int pnl = blockIdx.x % npanels;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
   const int hc = min(chunk, d - h0);
   const int tid = threadIdx.x;
 
-  for (int i = tid; i < PW * chunk; i += NT) ysh[i] = (TACC)0;
+  for (int i = tid; i < PW * chunk; i += NT) ysh[i] = 0.0;
   __syncthreads();
 
   const TA* colA[PW];
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
       const bool neg = (ev & 1u) != 0;
 #pragma unroll
       for (int p = 0; p < PW; ++p)
-        if (p < np) atomicAdd(&ysh[p * chunk + pos], (TACC)(neg ? -a[p] : a[p]));
+        if (p < np) atomicAdd(&ysh[p * chunk + pos], neg ? -a[p] : a[p]);
     }
   };
 
@@ -142,7 +144,8 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
       const bool ok = i < m;
 #pragma unroll
       for (int p = 0; p < PW; ++p)
-        a[u][p] = (ok && p < np) ? (colA[p] ? (double)colA[p][i] : colB[p][i]) : 0.0;
+        a[u][p] = (ok && p < np) ? (colA[p] ? (R32 ? (double)(float)colA[p][i] : (double)colA[p][i]) : colB[p][i])
+                                 : 0.0;
       if (Z8) e8[u] = ok ? *reinterpret_cast<const uint4*>(idx + i * 8) : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
@@ -176,62 +179,62 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
     if (col < n) {
       if (scale_by_norm && nrm2 > 0.0) f = inv_sqrt_zeta / sqrt(nrm2);
     }
-    for (int h = tid; h < hc; h += NT) Y[(int64_t)col * ldy + h0 + h] = (double)ysh[p * chunk + h] * f;
+    for (int h = tid; h < hc; h += NT) Y[(int64_t)col * ldy + h0 + h] = ysh[p * chunk + h] * f;
   }
 }
 
-template <typename IDX, int PW, typename TA, typename TACC>
+template <typename IDX, int PW, typename TA, bool R32>
 void launch_apply_pw(const TA* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx, int d,
                      int zeta, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
                      int nchunks, hipStream_t s) {
   constexpr int NT = 1024;
   const int npanels = (ncols + PW - 1) / PW;
-  const size_t shmem = (size_t)PW * chunk * sizeof(TACC);
+  const size_t shmem = (size_t)PW * chunk * sizeof(double);
   const dim3 grid((unsigned)(npanels * nchunks));
   if constexpr (sizeof(IDX) == 2) {
     if (zeta == 8) {
-      (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, true, TA, TACC>,
+      (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, true, TA, R32>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-      hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, true, TA, TACC>), grid, dim3(NT), shmem, s, A, lda, m, n, B,
+      hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, true, TA, R32>), grid, dim3(NT), shmem, s, A, lda, m, n, B,
                          ldb, (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
       return;
     }
   }
-  (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, false, TA, TACC>,
+  (void)hipFuncSetAttribute((const void*)k_sketch_apply<IDX, NT, PW, false, TA, R32>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, false, TA, TACC>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
+  hipLaunchKernelGGL((k_sketch_apply<IDX, NT, PW, false, TA, R32>), grid, dim3(NT), shmem, s, A, lda, m, n, B, ldb,
                      (const IDX*)idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn);
 }
 
-template <typename IDX, typename TA, typename TACC>
+template <typename IDX, typename TA, bool R32>
 void launch_apply(const TA* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, const void* idx, int d,
                   int zeta, int pw, int chunk, int ncols, double* Y, int64_t ldy, double* colnorm2, int sbn, int wbn,
                   int nchunks, hipStream_t s) {
   switch (pw) {
-    case 16: launch_apply_pw<IDX, 16, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 8: launch_apply_pw<IDX, 8, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 4: launch_apply_pw<IDX, 4, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    case 2: launch_apply_pw<IDX, 2, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
-    default: launch_apply_pw<IDX, 1, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 16: launch_apply_pw<IDX, 16, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 8: launch_apply_pw<IDX, 8, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 4: launch_apply_pw<IDX, 4, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    case 2: launch_apply_pw<IDX, 2, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
+    default: launch_apply_pw<IDX, 1, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, chunk, ncols, Y, ldy, colnorm2, sbn, wbn, nchunks, s); break;
   }
 }
 
-template <typename TA, typename TACC>
+template <typename TA, bool R32>
 hipError_t sketch_apply_t(const TA* A, int64_t lda, int64_t m, int n, const double* B, int64_t ldb, int nb,
                           const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy, double* colnorm2,
                           bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s) {
   const int ncols = n + (B ? nb : 0);
-  const int lds_elems = lds_bytes / (int)sizeof(TACC);
+  const int lds_elems = lds_bytes / (int)sizeof(double);
   const int chunk = d < lds_elems ? d : lds_elems;
   int fit = lds_elems / d;  // columns of Y that fit in LDS at once
   int pw = 1;
   while (pw * 2 <= fit && pw * 2 <= 16 && pw < ncols) pw *= 2;
   const int nchunks = (d + chunk - 1) / chunk;
   if (idx16)
-    launch_apply<uint16_t, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
+    launch_apply<uint16_t, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
                                      scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
   else
-    launch_apply<uint32_t, TA, TACC>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
+    launch_apply<uint32_t, TA, R32>(A, lda, m, n, B, ldb, idx, d, zeta, pw, chunk, ncols, Y, ldy, colnorm2,
                                      scale_by_norm ? 1 : 0, write_bnorm ? 1 : 0, nchunks, s);
   return hipGetLastError();
 }
@@ -264,8 +267,8 @@ hipError_t fs_launch_sketch_apply(const double* A, int64_t lda, int64_t m, int n
                                   int nb, const void* idx, bool idx16, int d, int zeta, double* Y, int64_t ldy,
                                   double* colnorm2, bool scale_by_norm, bool write_bnorm, int lds_bytes,
                                   hipStream_t s) {
-  return sketch_apply_t<double, double>(A, lda, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
-                                        scale_by_norm, write_bnorm, lds_bytes, s);
+  return sketch_apply_t<double, false>(A, lda, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
+                                       scale_by_norm, write_bnorm, lds_bytes, s);
 }
 
 hipError_t fs_launch_sketch_apply_fp32(const double* A, int64_t lda, const float* A32, int64_t lda32, int64_t m,
@@ -273,10 +276,10 @@ hipError_t fs_launch_sketch_apply_fp32(const double* A, int64_t lda, const float
                                        int d, int zeta, double* Y, int64_t ldy, double* colnorm2,
                                        bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s) {
   if (A32)
-    return sketch_apply_t<float, float>(A32, lda32, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
+    return sketch_apply_t<float, false>(A32, lda32, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
                                         scale_by_norm, write_bnorm, lds_bytes, s);
-  return sketch_apply_t<double, float>(A, lda, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
-                                       scale_by_norm, write_bnorm, lds_bytes, s);
+  return sketch_apply_t<double, true>(A, lda, m, n, B, ldb, nb, idx, idx16, d, zeta, Y, ldy, colnorm2,
+                                      scale_by_norm, write_bnorm, lds_bytes, s);
 }
 
 hipError_t fs_launch_to_fp32(const double* A, int64_t lda, int64_t m, int n, float* A32, int64_t lda32, hipStream_t s) {

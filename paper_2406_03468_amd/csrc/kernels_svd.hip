@@ -105,6 +105,9 @@ __global__ __launch_bounds__(SVD_NT) void k_jacobi_coop(double* __restrict__ Gm,
 }
 
 // ---------------------------------------------------------------- block (systolic) variant
+// 8 waves: a round has at most b = 8 disjoint pairs at a time, and 512 threads leave each wave 256
+// VGPRs for a register-resident column pair.
+constexpr int SVD_BLOCK_NT = 512;
 // Columns are grouped in NBLK blocks of b columns (padded to an even count with an empty block).
 // Work-group p holds two blocks in LDS, at circle positions p ("top") and NBLK-1-p ("bottom").
 // In a round it orthogonalizes every column of its top block against every column of its bottom
@@ -141,6 +144,64 @@ __device__ __forceinline__ void jac_rotate_pair(double* __restrict__ x, double* 
   }
 }
 
+// The same rotation with the column pair held in registers (NQ = ceil(n / 64) elements per lane):
+// every LDS load is issued before the first use, so the dot products wait once for the whole column
+// instead of once per 64-element step.  Same arithmetic in the same order as jac_rotate_pair.
+template <int NQ>
+__device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double* __restrict__ y, int n, double tol,
+                                                  int lane, int& nrot) {
+  double xr[NQ], yr[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = lane + 64 * k;
+    xr[k] = (q < n) ? x[q] : 0.0;
+    yr[k] = (q < n) ? y[q] : 0.0;
+  }
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    sa = fma(xr[k], xr[k], sa);
+    sb = fma(yr[k], yr[k], sb);
+    sc = fma(xr[k], yr[k], sc);
+  }
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  sc = wave_sum(sc);
+  if (sa > 0.0 && sb > 0.0 && fabs(sc) > tol * sqrt(sa) * sqrt(sb)) {
+    const double zeta = (sb - sa) / (2.0 * sc);
+    double t;
+    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+    else t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = lane + 64 * k;
+      if (q < n) {
+        x[q] = cs * xr[k] - sn * yr[k];
+        y[q] = sn * xr[k] + cs * yr[k];
+      }
+    }
+    ++nrot;
+  }
+}
+
+template <int NQ>
+__device__ __forceinline__ void jac_rotate(double* __restrict__ x, double* __restrict__ y, int n, double tol,
+                                           int lane, int& nrot) {
+  if constexpr (NQ > 0) jac_rotate_pair_r<NQ>(x, y, n, tol, lane, nrot);
+  else jac_rotate_pair(x, y, n, tol, lane, nrot);
+}
+
+// 16-byte coherent mailbox traffic (two doubles per access; offsets are 16-byte aligned).
+typedef unsigned int fs_u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned int))));
+typedef double fs_f64x2 __attribute__((__vector_size__(2 * sizeof(double))));
+__device__ __forceinline__ fs_f64x2 ld_cob2(__amdgpu_buffer_rsrc_t r, size_t byte_off) {
+  return __builtin_bit_cast(fs_f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)(uint32_t)byte_off, 0, FS_CPOL_SC1));
+}
+__device__ __forceinline__ void st_cob2(__amdgpu_buffer_rsrc_t r, size_t byte_off, fs_f64x2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(fs_u32x4, v), r, (int)(uint32_t)byte_off, 0, FS_CPOL_SC1);
+}
+
 __device__ __forceinline__ int circle_player(int pos, int r, int nb) {
   return (pos == 0) ? 0 : 1 + (pos - 1 + r) % (nb - 1);
 }
@@ -156,7 +217,8 @@ __device__ __forceinline__ void wait_flag(unsigned* f, unsigned target, int* err
   }
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
+template <int NQ>
+__global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
                                                       double tol, double* __restrict__ mbox, unsigned* __restrict__ flags,
                                                       int* __restrict__ rotcount, int* __restrict__ sweeps_out,
                                                       GridBarrier bar) {
@@ -195,7 +257,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
             const int s2 = pp / (be / 2), k = pp % (be / 2);
             int a = circle_player(k, sr, be), c2 = circle_player(be - 1 - k, sr, be);
             const int nc = s2 ? nc1 : nc0;
-            if (a < nc && c2 < nc) jac_rotate_pair(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, lane, nrot);
+            if (a < nc && c2 < nc) jac_rotate<NQ>(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, lane, nrot);
           }
           __syncthreads();
         }
@@ -204,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
       for (int sr = 0; sr < b; ++sr) {
         for (int t = wv; t < b; t += nw) {
           const int c2 = (t + sr) % b;
-          if (t < nc0 && c2 < nc1) jac_rotate_pair(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, lane, nrot);
+          if (t < nc0 && c2 < nc1) jac_rotate<NQ>(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, lane, nrot);
         }
         __syncthreads();
       }
@@ -220,14 +282,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
       if (p <= P - 2) dst_bot = p + 1;
       // mailboxes are written and read with coherent accesses; the flag is raised once every
       // thread's stores have completed (no cache flush needed, see grid_barrier_co)
-      if (dst_top >= 0) {
-        const size_t o = mb(dst_top, dst_top_slot, par);
-        for (size_t q = tid; q < blk; q += blockDim.x) st_cob(rmbox, 8 * (o + q), slot[0][q]);
-      }
-      if (dst_bot >= 0) {
-        const size_t o = mb(dst_bot, 1, par);
-        for (size_t q = tid; q < blk; q += blockDim.x) st_cob(rmbox, 8 * (o + q), slot[1][q]);
-      }
+      auto send = [&](const double* src, size_t o) {
+        if ((blk & 1) == 0) {  // pairs of doubles (the mailboxes and b n are even, so 16-byte aligned)
+          for (size_t q = 2 * tid; q < blk; q += 2 * (size_t)blockDim.x)
+            st_cob2(rmbox, 8 * (o + q), (fs_f64x2){src[q], src[q + 1]});
+        } else {
+          for (size_t q = tid; q < blk; q += blockDim.x) st_cob(rmbox, 8 * (o + q), src[q]);
+        }
+      };
+      if (dst_top >= 0) send(slot[0], mb(dst_top, dst_top_slot, par));
+      if (dst_bot >= 0) send(slot[1], mb(dst_bot, 1, par));
       stores_complete();
       __syncthreads();
       if (tid == 0) {
@@ -250,6 +314,25 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double* __restrict__ Gm, 
       __syncthreads();
       // batches of 8 independent coherent loads per thread (offsets past the block read 0)
       auto recv = [&](double* dst, size_t src) {
+        if ((blk & 1) == 0) {
+          for (size_t q0 = 2 * tid; q0 < blk; q0 += 16 * (size_t)blockDim.x) {
+            fs_f64x2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const size_t q = q0 + (size_t)u * 2 * blockDim.x;
+              v[u] = ld_cob2(rmbox, q < blk ? 8 * (src + q) : (size_t)0xFFFFFFF0u);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const size_t q = q0 + (size_t)u * 2 * blockDim.x;
+              if (q < blk) {
+                dst[q] = v[u][0];
+                dst[q + 1] = v[u][1];
+              }
+            }
+          }
+          return;
+        }
         for (size_t q0 = tid; q0 < blk; q0 += 8 * (size_t)blockDim.x) {
           double v[8];
 #pragma unroll
@@ -519,16 +602,23 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     const int NBLK = nblk + (nblk & 1);
     const int P = NBLK / 2;
     if (P > num_cu) return hipErrorInvalidValue;
-    double* mbox = norms + n + SVD_CTR_DOUBLES;  // after the counters
+    // after the counters, 16-byte aligned (the workspace has 1 KB of slack)
+    double* mbox = (double*)(((uintptr_t)(norms + n + SVD_CTR_DOUBLES) + 15) & ~(uintptr_t)15);
     unsigned* flg = (unsigned*)(mbox + (size_t)P * 4 * bw * n);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, s, (int*)flg, 2 * P, 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t shmem = (size_t)2 * bw * n * sizeof(double);
-    (void)hipFuncSetAttribute((const void*)k_jacobi_block, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    // columns of up to 2048 rows are rotated from registers (NQ = elements per lane)
+    const void* kfn = (n <= 256)    ? (const void*)k_jacobi_block<4>
+                      : (n <= 512)  ? (const void*)k_jacobi_block<8>
+                      : (n <= 1024) ? (const void*)k_jacobi_block<16>
+                      : (n <= 2048) ? (const void*)k_jacobi_block<32>
+                                    : (const void*)k_jacobi_block<0>;
+    (void)hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     int NB2 = NBLK;
     int bw2 = bw;
     void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co};
-    e = fs_launch_resident((const void*)k_jacobi_block, dim3(P), dim3(1024), args, shmem, s);
+    e = fs_launch_resident(kfn, dim3(P), dim3(SVD_BLOCK_NT), args, shmem, s);
     if (e != hipSuccess) return e;
   } else {
     int G = (n + 1) / 2;

@@ -216,6 +216,103 @@ __global__ __launch_bounds__(VNT) void k_cg(int n, double* __restrict__ p, const
   }
 }
 
+// LSQR (Paige and Saunders) on min || r - (A_s P) dy ||, the LSQR form of SPIR (Section 4.3).
+// Start: beta_1 u_1 = r (st->r2 = ||r||^2), alpha_1 v_1 = (A_s P)^T u_1 = c / beta_1, w = v_1,
+// phibar = beta_1, rhobar = alpha_1, dy = 0.  A zero r or c ends the step at once (dy = 0 is exact).
+__global__ __launch_bounds__(VNT) void k_lsqr_init(int n, const double* __restrict__ c, double* __restrict__ v,
+                                                   double* __restrict__ w, double* __restrict__ dy,
+                                                   DevState* __restrict__ st) {
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) s = fma(c[i], c[i], s);
+  const double cn2 = bsum(s, sh);
+  const double cn = sqrt(cn2), bet = sqrt(st->r2);
+  const bool zero = !(cn > 0.0) || !(bet > 0.0);
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double vi = zero ? 0.0 : c[i] / cn;
+    v[i] = vi;
+    w[i] = vi;
+    dy[i] = 0.0;
+  }
+  if (threadIdx.x == 0) {
+    st->cnorm2 = cn2;
+    st->iters = 0;
+    st->l_beta = bet;
+    st->l_alpha = zero ? 0.0 : cn / bet;
+    st->l_phibar = bet;
+    st->l_rhobar = st->l_alpha;
+    st->stop = zero ? 1 : 0;
+    st->converged = zero ? 1 : 0;
+  }
+}
+
+// One step.  Input h = P^T A_s^T (alpha u - A_s P v) = -beta P^T A_s^T u' (the pass ran on
+// ubar = alpha u), st->r2 = beta^2.  Then
+//   alpha' v' = -h / beta - beta v;  rho = hypot(rhobar, beta), c = rhobar / rho, s = beta / rho,
+//   theta = s alpha', rhobar' = -c alpha', phi = c phibar, phibar' = s phibar,
+//   Delta = (phi / rho) w, dy += Delta, w' = v' - (theta / rho) w,
+// with SPIR's first-step rule on ||Delta||, the cap, and termination at beta = 0 or alpha' = 0.
+__global__ __launch_bounds__(VNT) void k_lsqr_step(int n, const double* __restrict__ h, double* __restrict__ v,
+                                                   double* __restrict__ w, double* __restrict__ dy,
+                                                   DevState* __restrict__ st, int first_step) {
+  if (st->stop) return;
+  __shared__ double sh[VNT / 64];
+  const double bet = sqrt(st->r2);
+  const double ib = (bet > 0.0) ? 1.0 / bet : 0.0;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double si = -h[i] * ib - bet * v[i];
+    v[i] = si;  // unnormalized until alpha' is known
+    s = fma(si, si, s);
+  }
+  const double alf = sqrt(bsum(s, sh));
+  const double ia = (alf > 0.0) ? 1.0 / alf : 0.0;
+  const double rhobar = st->l_rhobar, phibar = st->l_phibar;
+  const double rho = hypot(rhobar, bet);
+  const double cs = rhobar / rho, sn = bet / rho;
+  const double theta = sn * alf, phi = cs * phibar;
+  const double fd = phi / rho, fw = theta / rho;
+  double sd = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double vi = v[i] * ia;
+    v[i] = vi;
+    const double wi = w[i];
+    const double D = fd * wi;
+    dy[i] += D;
+    w[i] = vi - fw * wi;
+    sd = fma(D, D, sd);
+  }
+  const double dn2 = bsum(sd, sh);
+  if (threadIdx.x == 0) {
+    st->l_alpha = alf;
+    st->l_beta = bet;
+    st->l_rhobar = -cs * alf;
+    st->l_phibar = sn * phibar;
+    st->dnorm2 = dn2;
+    st->iters += 1;
+    if (!(bet > 0.0) || !(alf > 0.0)) {
+      st->stop = 1;
+      st->converged = 1;
+    }
+    if (first_step && sqrt(dn2) <= st->thr_first) {
+      st->stop = 1;
+      st->converged = 1;
+    }
+    if (st->iters >= st->max_inner) st->stop = 1;
+  }
+}
+
+// ubar = sign (alpha / beta) r: alpha_1 u_1 = (alpha_1 / beta_1) r at the start of a step (sign +1);
+// alpha' u' = -(alpha' / beta) r_out inside the iteration (sign -1, r_out = alpha u - A_s P v).
+__global__ __launch_bounds__(256) void k_lsqr_ubar(int64_t m, const double* __restrict__ r, double* __restrict__ ubar,
+                                                   double sign, const DevState* __restrict__ st) {
+  if (st->stop) return;
+  const double bet = st->l_beta;
+  const double f = (bet > 0.0) ? sign * st->l_alpha / bet : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    ubar[i] = f * r[i];
+}
+
 // Start of a refinement step: dy = dy_old = c (FOSSILS) or dy = 0, res = p = c (SPIR); rho = c^T c.
 __global__ __launch_bounds__(VNT) void k_step_init(int n, const double* __restrict__ c, double* __restrict__ a,
                                                    double* __restrict__ b, double* __restrict__ dy, int spir,
@@ -397,6 +494,22 @@ hipError_t fs_vec_gemv_vt(const double* V, int64_t ldv, int n, int k, const doub
 hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, double* dy_old, DevState* st,
                          bool first_step, hipStream_t s) {
   hipLaunchKernelGGL(k_polyak, dim3(1), dim3(VNT), 0, s, n, c, u, dy, dy_old, st, first_step ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t fs_vec_lsqr_init(int n, const double* c, double* v, double* w, double* dy, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_init, dim3(1), dim3(VNT), 0, s, n, c, v, w, dy, st);
+  return hipGetLastError();
+}
+hipError_t fs_vec_lsqr_step(int n, const double* h, double* v, double* w, double* dy, DevState* st, bool first_step,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_lsqr_step, dim3(1), dim3(VNT), 0, s, n, h, v, w, dy, st, first_step ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t fs_vec_lsqr_ubar(int64_t m, const double* r, double* ubar, double sign, const DevState* st,
+                            hipStream_t s) {
+  const int64_t nb = (m + 255) / 256;
+  hipLaunchKernelGGL(k_lsqr_ubar, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, s, m, r, ubar, sign, st);
   return hipGetLastError();
 }
 

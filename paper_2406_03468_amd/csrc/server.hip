@@ -79,7 +79,9 @@ struct fs_server_s {
       const fs_options* op = has_opts ? &opts : nullptr;
       fs_status r = (req.method == FS_METHOD_SPIR)
                         ? spir_solve(ctx, req.m, req.n, req.A, req.lda, req.b, req.x, op, &info)
-                        : fossils_solve(ctx, req.m, req.n, req.A, req.lda, req.b, req.x, op, &info);
+                        : (req.method == FS_METHOD_SPIR_LSQR)
+                              ? spir_lsqr_solve(ctx, req.m, req.n, req.A, req.lda, req.b, req.x, op, &info)
+                              : fossils_solve(ctx, req.m, req.n, req.A, req.lda, req.b, req.x, op, &info);
       {
         std::lock_guard<std::mutex> lk(mu);
         Ticket& t = tickets[id];
@@ -145,7 +147,8 @@ fs_status fs_server_destroy(fs_server srv) {
 
 fs_status batched_submit(fs_server srv, const fs_request* req, uint64_t* ticket) {
   if (!srv || !req || !ticket) return FS_ERR_INVALID_ARG;
-  if (req->method != FS_METHOD_FOSSILS && req->method != FS_METHOD_SPIR) return FS_ERR_INVALID_ARG;
+  if (req->method != FS_METHOD_FOSSILS && req->method != FS_METHOD_SPIR && req->method != FS_METHOD_SPIR_LSQR)
+    return FS_ERR_INVALID_ARG;
   FS_TRY(fs_validate_problem(req->m, req->n, req->A, req->lda, req->b, req->x));
   fs_options o;
   if (req->opts) o = *req->opts;

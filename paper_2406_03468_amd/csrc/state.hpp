@@ -19,6 +19,8 @@ struct DevState {
   double normest, condest;
   double x0norm, r0norm;
   double b2;             // ||b||^2
+  double l_alpha, l_beta;       // LSQR: alpha_i, beta_i of the Golub-Kahan bidiagonalization
+  double l_phibar, l_rhobar;    // LSQR: the rotated right-hand side and diagonal
   int stop;              // inner-loop stop flag
   int iters;             // inner iterations in the current step
   int converged;         // the current step stopped by its rule (not by the cap)
@@ -35,6 +37,14 @@ hipError_t fs_vec_gemv_vt(const double* V, int64_t ldv, int n, int k, const doub
                           const int* stop, hipStream_t s);
 hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, double* dy_old, DevState* st,
                          bool first_step, hipStream_t s);
+// LSQR form of SPIR: start of a step (needs st->r2 = ||r||^2 and c = P^T A_s^T r), one bidiagonalization
+// and rotation step (h = P^T A_s^T (alpha u - A_s P v), st->r2 its squared residual), and the
+// m-vector ubar = alpha u from the stored residual r (sign -1 inside the iteration).
+hipError_t fs_vec_lsqr_init(int n, const double* c, double* v, double* w, double* dy, DevState* st, hipStream_t s);
+hipError_t fs_vec_lsqr_step(int n, const double* h, double* v, double* w, double* dy, DevState* st, bool first_step,
+                            hipStream_t s);
+hipError_t fs_vec_lsqr_ubar(int64_t m, const double* r, double* ubar, double sign, const DevState* st,
+                            hipStream_t s);
 hipError_t fs_vec_cg(int n, double* p, const double* q, double* res, double* dy, DevState* st, bool first_step,
                      hipStream_t s);
 hipError_t fs_vec_step_init(int n, const double* c, double* a, double* b, double* dy, bool spir, DevState* st,

@@ -214,7 +214,7 @@ def test_multi_rhs_generator_and_oracle():
 
 
 def test_mixed_precision_sketch_and_fallback():
-    """Mixed form (FP32 sketch, FP64 refinement): single-precision sketch error bound; backward
+    """Mixed form (sketch of the FP32 copy, FP64 refinement): sketch error bound; backward
     stable with the FP32 preconditioner while u32 condest is small; past the threshold the FP64
     sketch is used (flag); and without that fallback the FP32 preconditioner fails at kappa = 1e10
     (the single-precision reading of Lemma 6.3's hazard)."""
@@ -225,11 +225,12 @@ def test_mixed_precision_sketch_and_fallback():
     y32 = sketch_fp32(M, 300, 8, 5)
     from oracle.sketch import sparse_sign_matrix
     S = sparse_sign_matrix(3000, 300, 8, 5)
-    k = (S != 0).sum(axis=1).max()          # the longest single-precision sum (standard gamma_k bound)
-    bound = 1.01 * (k + 2) * 2.0**-24 * (abs(S) @ np.abs(M)) / np.sqrt(8)   # S carries zeta^{-1/2}
+    k = (S != 0).sum(axis=1).max()          # the longest sum (standard gamma_k bound)
+    # input rounding u32 plus double-precision sums; S carries zeta^{-1/2}
+    bound = 1.01 * (2.0**-24 + (k + 2) * 2.0**-53) * (abs(S) @ np.abs(M)) / np.sqrt(8)
     err = np.abs(y32 - y64)
     assert np.all(err <= bound)
-    assert err.max() > 1e3 * 2.0**-53 * np.abs(y64).max()   # it is single precision, not double
+    assert err.max() > 1e3 * 2.0**-53 * np.abs(y64).max()   # the input is single precision
     for kappa, flagged in [(1e3, False), (1e5, False), (1e8, True)]:
         P = make_problem(4000, 50, kappa, 1e-6, seed=3)
         r = solvers.fossils(P.A, P.b, solvers.Options(precision="mixed"))
