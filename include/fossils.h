@@ -54,6 +54,7 @@ typedef struct fs_server_s* fs_server;
 
 enum { FS_PRECOND_QR = 0, FS_PRECOND_SVD = 1 };
 enum { FS_FP64 = 0, FS_MIXED = 1 };
+enum { FS_INIT_SKETCH = 0, FS_INIT_ZERO = 1 };
 /* bits of fs_info.flags */
 enum { FS_FLAG_RANK_DEFICIENT = 1, FS_FLAG_NOT_CONVERGED = 2, FS_FLAG_FP64_SKETCH = 4 };
 
@@ -75,6 +76,8 @@ typedef struct fs_options {
   int32_t steps;          /* refinement steps: 2 (the method) or 1 ("one step" variant) */
   int32_t precision;      /* FS_FP64, or FS_MIXED: FP32 sketch (see fossils_solve_mixed) */
   int32_t max_sweeps;     /* Jacobi sweep cap of the SVD of R */
+  int32_t init;           /* FS_INIT_SKETCH: x_0 = sketch-and-solve (Alg 4); FS_INIT_ZERO: x_0 = 0 (the
+                             zero start of plain sketch-and-precondition, for the Section 5.1 comparisons) */
   int32_t graph_sweeps;   /* 1: the inner iterations run as a captured HIP graph of kw_every iterations,
                              replayed until the device-side stop flag is set (one launch and one
                              host poll per kw_every iterations); 0: kernel-by-kernel launches */
@@ -134,7 +137,8 @@ fs_status spir_lsqr_solve(fs_context ctx, int64_t m, int32_t n, const double* A,
  * One sketch S [A B], one QR and one SVD serve every column (x_0 = R^{-1} t_j); the inner
  * heavy-ball iterations of all columns run together, each pass A^T (A Z) over the k columns on the
  * FP64 matrix cores, and every column keeps Algorithm 4's stopping rules of its own (a column
- * that has stopped is frozen).  Adaptive mode only (opts->fixed_q must be 0); P = V Sigma^{-1}.
+ * that has stopped is frozen).  Adaptive mode from the sketch-and-solve start only (opts->fixed_q 0,
+ * FP64, FS_INIT_SKETCH; otherwise FS_ERR_UNSUPPORTED); P = V Sigma^{-1}.
  * info, if not NULL, points to k fs_info records (per right-hand side).  Returns
  * FS_WARN_NOT_CONVERGED if any column hit the iteration cap in the second step. */
 fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, int32_t k,

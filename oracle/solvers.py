@@ -70,6 +70,7 @@ class Options:
     fixed_q: int = 0                 # 0 adaptive; q > 0 Algorithm 2 with q steps; -1 q_0 of Thm 7.1
     steps: int = 2                   # refinement steps (2 = the method; 1 = "FOSSILS (1 step)")
     precision: str = "fp64"          # "fp64", or "mixed": FP32 sketch, FP64 everything else
+    init: str = "sketch"             # "sketch": x_0 = sketch-and-solve (Alg 4); "zero": x_0 = 0
     mixed_fallback: bool = True      # mixed: redo the sketch in FP64 when condest u32 is too large
 
 
@@ -276,6 +277,10 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
         pre = _Precond("qr", R=R)
         x0 = back_substitution(R, t)                           # eq:sketch-and-solve-2.3
 
+    if opts.init == "zero":      # sketch-and-precondition's zero start (Section 5.1 comparison)
+        x0 = np.zeros(n)
+    elif opts.init != "sketch":
+        raise ValueError("init must be 'sketch' or 'zero'")
     # Alg 4: r = b - A x, kept for the first-step rule.
     r0 = b - As @ x0
     thr_first = (opts.gamma * normest * np.linalg.norm(x0) + opts.rho * condest * np.linalg.norm(r0)) * u

@@ -32,6 +32,8 @@ FS_PRECOND_QR = 0
 FS_PRECOND_SVD = 1
 FS_FP64 = 0
 FS_MIXED = 1
+FS_INIT_SKETCH = 0
+FS_INIT_ZERO = 1
 FS_FLAG_RANK_DEFICIENT = 1
 FS_FLAG_NOT_CONVERGED = 2
 FS_FLAG_FP64_SKETCH = 4
@@ -44,7 +46,8 @@ class FsOptions(ctypes.Structure):
         ("d", c_int32), ("zeta", c_int32), ("seed", c_uint64), ("eta", c_double), ("eta_factor", c_double),
         ("gamma", c_double), ("rho", c_double), ("kw_every", c_int32), ("max_inner", c_int32),
         ("tau_factor", c_double), ("column_scaling", c_int32), ("precond", c_int32), ("fixed_q", c_int32),
-        ("steps", c_int32), ("precision", c_int32), ("max_sweeps", c_int32), ("graph_sweeps", c_int32),
+        ("steps", c_int32), ("precision", c_int32), ("max_sweeps", c_int32), ("init", c_int32),
+        ("graph_sweeps", c_int32),
     ]
 
 

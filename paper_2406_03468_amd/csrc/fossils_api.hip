@@ -86,6 +86,7 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
   if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
   if (o.graph_sweeps != 0 && o.graph_sweeps != 1) return FS_ERR_INVALID_ARG;
+  if (o.init != FS_INIT_SKETCH && o.init != FS_INIT_ZERO) return FS_ERR_INVALID_ARG;
   (void)m;
   return FS_OK;
 }
@@ -133,7 +134,8 @@ fs_status fs_options_default(int64_t m, int32_t n, fs_options* o) {
   o->steps = 2;
   o->precision = FS_FP64;
   o->max_sweeps = 40;
-  o->graph_sweeps = 1;
+  o->init = FS_INIT_SKETCH;
+  o->graph_sweeps = 0;  // measured no faster than kernel-by-kernel launches (the host enqueues ahead)
   return FS_OK;
 }
 
@@ -616,6 +618,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
     FS_K(fs_launch_trsv(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, s));
   }
+  if (o.init == FS_INIT_ZERO) FS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));  // (not captured)
   FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));
 
   // theta^2 and the first-step threshold need ||b||^2 and ||A_s||_F^2

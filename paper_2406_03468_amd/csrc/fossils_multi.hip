@@ -34,7 +34,7 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
   if (opts_in) o = *opts_in;
   else FS_TRY(fs_options_default(m, n, &o));
   FS_TRY(fs_validate_options(m, n, o));
-  if (o.fixed_q != 0 || o.precision != FS_FP64) return FS_ERR_UNSUPPORTED;  // adaptive FP64 only
+  if (o.fixed_q != 0 || o.precision != FS_FP64 || o.init != FS_INIT_SKETCH) return FS_ERR_UNSUPPORTED;  // adaptive FP64 only
   FS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   FS_HIP(hipStreamSynchronize(s));

@@ -118,7 +118,7 @@ constexpr int SVD_BLOCK_NT = 512;
 // neighbours synchronize.  After NBLK-1 rounds every pair of columns has met once (one sweep) and
 // the blocks are back where they started; a grid barrier then sums the sweep's rotation count.
 __device__ __forceinline__ void jac_rotate_pair(double* __restrict__ x, double* __restrict__ y, int n, double tol,
-                                                int lane, int& nrot) {
+                                                int lane, int& nrot, double& c2max) {
   double sa = 0.0, sb = 0.0, sc = 0.0;
   for (int q = lane; q < n; q += 64) {
     const double a = x[q], bq = y[q];
@@ -129,6 +129,7 @@ __device__ __forceinline__ void jac_rotate_pair(double* __restrict__ x, double* 
   sa = wave_sum(sa);
   sb = wave_sum(sb);
   sc = wave_sum(sc);
+  if (sa > 0.0 && sb > 0.0) c2max = fmax(c2max, (sc * sc) / (sa * sb));
   if (sa > 0.0 && sb > 0.0 && fabs(sc) > tol * sqrt(sa) * sqrt(sb)) {
     const double zeta = (sb - sa) / (2.0 * sc);
     double t;
@@ -144,12 +145,33 @@ __device__ __forceinline__ void jac_rotate_pair(double* __restrict__ x, double* 
   }
 }
 
+// Full-wave sum with DPP lane moves (a few cycles each, instead of an LDS round trip per
+// ds_bpermute step): quad butterflies, half-row and row mirrors, then the gfx9 row broadcasts
+// gather the four row sums in lane 63, which is read back into every lane.  All 64 lanes active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_d<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_d<0x140, 0xf>(v);  // row_mirror: every lane holds its row's sum
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // The same rotation with the column pair held in registers (NQ = ceil(n / 64) elements per lane):
 // every LDS load is issued before the first use, so the dot products wait once for the whole column
 // instead of once per 64-element step.  Same arithmetic in the same order as jac_rotate_pair.
 template <int NQ>
 __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double* __restrict__ y, int n, double tol,
-                                                  int lane, int& nrot) {
+                                                  int lane, int& nrot, double& c2max) {
   double xr[NQ], yr[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
@@ -164,10 +186,12 @@ __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double
     sb = fma(yr[k], yr[k], sb);
     sc = fma(xr[k], yr[k], sc);
   }
-  sa = wave_sum(sa);
-  sb = wave_sum(sb);
-  sc = wave_sum(sc);
-  if (sa > 0.0 && sb > 0.0 && fabs(sc) > tol * sqrt(sa) * sqrt(sb)) {
+  sa = wave_sum_dpp(sa);
+  sb = wave_sum_dpp(sb);
+  sc = wave_sum_dpp(sc);
+  if (sa > 0.0 && sb > 0.0) c2max = fmax(c2max, (sc * sc) / (sa * sb));
+  // |cos| > tol without square roots (column norms of R are O(1): no overflow or underflow here)
+  if (sa > 0.0 && sb > 0.0 && sc * sc > (tol * tol) * (sa * sb)) {
     const double zeta = (sb - sa) / (2.0 * sc);
     double t;
     if (fabs(zeta) > 1e150) t = 0.5 / zeta;
@@ -187,9 +211,9 @@ __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double
 
 template <int NQ>
 __device__ __forceinline__ void jac_rotate(double* __restrict__ x, double* __restrict__ y, int n, double tol,
-                                           int lane, int& nrot) {
-  if constexpr (NQ > 0) jac_rotate_pair_r<NQ>(x, y, n, tol, lane, nrot);
-  else jac_rotate_pair(x, y, n, tol, lane, nrot);
+                                           int lane, int& nrot, double& c2max) {
+  if constexpr (NQ > 0) jac_rotate_pair_r<NQ>(x, y, n, tol, lane, nrot, c2max);
+  else jac_rotate_pair(x, y, n, tol, lane, nrot, c2max);
 }
 
 // 16-byte coherent mailbox traffic (two doubles per access; offsets are 16-byte aligned).
@@ -221,7 +245,8 @@ template <int NQ>
 __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
                                                       double tol, double* __restrict__ mbox, unsigned* __restrict__ flags,
                                                       int* __restrict__ rotcount, int* __restrict__ sweeps_out,
-                                                      GridBarrier bar) {
+                                                      GridBarrier bar, unsigned long long* __restrict__ maxcos2,
+                                                      double stop_cos2) {
   extern __shared__ double lds[];  // [2][b][n]
   const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
@@ -243,10 +268,12 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
   auto mb = [&](int wg, int sl, int par) { return (((size_t)wg * 2 + sl) * 2 + par) * blk; };  // element offset
   const auto rmbox = co_rsrc(mbox, sizeof(double) * (size_t)P * 4 * blk);
   __shared__ int s_nrot[16];
+  __shared__ double s_c2[16];
   int sweep = 0;
   unsigned rr = 0;  // global round counter
   for (; sweep < max_sweeps; ++sweep) {
     int nrot = 0;
+    double c2max = 0.0;  // largest cos^2 met this sweep (wave-uniform)
     for (int r = 0; r < NBLK - 1; ++r, ++rr) {
       const int nc0 = ncols(id[0]), nc1 = ncols(id[1]);
       if (r == 0) {
@@ -257,7 +284,8 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
             const int s2 = pp / (be / 2), k = pp % (be / 2);
             int a = circle_player(k, sr, be), c2 = circle_player(be - 1 - k, sr, be);
             const int nc = s2 ? nc1 : nc0;
-            if (a < nc && c2 < nc) jac_rotate<NQ>(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, lane, nrot);
+            if (a < nc && c2 < nc)
+              jac_rotate<NQ>(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, lane, nrot, c2max);
           }
           __syncthreads();
         }
@@ -266,7 +294,8 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
       for (int sr = 0; sr < b; ++sr) {
         for (int t = wv; t < b; t += nw) {
           const int c2 = (t + sr) % b;
-          if (t < nc0 && c2 < nc1) jac_rotate<NQ>(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, lane, nrot);
+          if (t < nc0 && c2 < nc1)
+            jac_rotate<NQ>(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, lane, nrot, c2max);
         }
         __syncthreads();
       }
@@ -354,17 +383,31 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
       id[0] = circle_player(p, r + 1, NBLK);
       id[1] = circle_player(NBLK - 1 - p, r + 1, NBLK);
     }
-    // sweep total
-    if (lane == 0) s_nrot[wv] = nrot;
+    // sweep total and largest cosine (positive doubles order like their bit patterns)
+    if (lane == 0) {
+      s_nrot[wv] = nrot;
+      s_c2[wv] = c2max;
+    }
     __syncthreads();
     if (tid == 0) {
       int t = 0;
-      for (int w = 0; w < nw; ++w) t += s_nrot[w];
+      double c2 = 0.0;
+      for (int w = 0; w < nw; ++w) {
+        t += s_nrot[w];
+        c2 = fmax(c2, s_c2[w]);
+      }
       if (t) __hip_atomic_fetch_add(&rotcount[sweep], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(&maxcos2[sweep], (unsigned long long)__double_as_longlong(c2), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
     }
     grid_barrier_co(bar, (unsigned)P, bgen);
     const int tot = __hip_atomic_load(&rotcount[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (tot == 0) {
+    const double c2s = __longlong_as_double(
+        (long long)__hip_atomic_load(&maxcos2[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    // Converged, or in the quadratic phase: a sweep whose largest cosine was <= sqrt(stop_cos2)
+    // leaves cosines of order n stop_cos2, which the orthogonality correction of V removes; the
+    // sweep that would only confirm convergence is skipped.
+    if (tot == 0 || c2s <= stop_cos2) {
       ++sweep;
       break;
     }
@@ -535,7 +578,10 @@ __global__ __launch_bounds__(256) void k_v_correct(const double* __restrict__ V,
 
 namespace {
 constexpr int SVD_LDS_BYTES = 144 * 1024;
-constexpr int SVD_CTR_DOUBLES = (72 + FS_BAR_WORDS + 1) / 2 + 1;  // counters region, in doubles
+// counters region (ints): rotation counts [0, 64) | fenced barrier [64, 67) | fence-free barrier
+// [72, 72 + FS_BAR_WORDS) | per-sweep largest cos^2 (64 x 8 bytes, 8-byte aligned); in doubles
+constexpr int SVD_MC_INT = (72 + FS_BAR_WORDS + 2) & ~1;
+constexpr int SVD_CTR_DOUBLES = (SVD_MC_INT + 128) / 2 + 1;
 // Block width for the systolic kernel: two blocks of b columns must fit in LDS.
 int svd_block_width(int n) {
   const int bmax = SVD_LDS_BYTES / (2 * 8 * n);
@@ -617,7 +663,10 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     (void)hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     int NB2 = NBLK;
     int bw2 = bw;
-    void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co};
+    unsigned long long* mc2 = (unsigned long long*)(rot + SVD_MC_INT);
+    double stop_cos2 = 1e-10;  // a sweep whose cosines all stayed <= 1e-5 ends the iteration
+    void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co, &mc2,
+                    &stop_cos2};
     e = fs_launch_resident(kfn, dim3(P), dim3(SVD_BLOCK_NT), args, shmem, s);
     if (e != hipSuccess) return e;
   } else {
@@ -633,12 +682,17 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // orthogonality correction of V (Gm and Uacc are free once sorted and written): Tc in Gm, the
   // corrected V in Uacc, copied back to V
+  // Two passes: the Jacobi stop leaves cosines up to ~n 1e-10; each pass squares the remainder.
   const unsigned T = (unsigned)((n + OC_T - 1) / OC_T);
-  hipLaunchKernelGGL(k_v_gram_upper, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm);
-  hipLaunchKernelGGL(k_v_correct, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm, Uacc);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return hipMemcpy2DAsync(V, sizeof(double) * ldv, Uacc, sizeof(double) * n, sizeof(double) * n, n,
-                          hipMemcpyDeviceToDevice, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    hipLaunchKernelGGL(k_v_gram_upper, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm);
+    hipLaunchKernelGGL(k_v_correct, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm, Uacc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = hipMemcpy2DAsync(V, sizeof(double) * ldv, Uacc, sizeof(double) * n, sizeof(double) * n, n,
+                         hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t fs_launch_svd(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, void* work,

@@ -220,3 +220,28 @@ def test_graph_sweeps_match_eager(ctx, method, kw_every, max_inner):
     for g, info, x in runs[1:]:
         assert abs(info.iters[0] - runs[0][1].iters[0]) <= 1 and abs(info.iters[1] - runs[0][1].iters[1]) <= 1
         assert np.linalg.norm(x - runs[0][2]) / np.linalg.norm(P.x_true) <= 10 * ref
+
+
+@pytest.mark.parametrize("kappa,rnorm", [(1e12, 1e12 * U), (1e10, 1e-6)])
+def test_section51_comparison_solvers_gpu(ctx, kappa, rnorm):
+    """The comparison methods of Section 5.1 on the GPU (options of the same kernels): one run of
+    sketch-and-precondition from x_0 = 0 (CG, LSQR) or from sketch-and-solve, iterative sketching
+    with momentum (FOSSILS, one step).  Each lands within 10x of the oracle's backward error for the
+    same variant, far above the 1e-14 that the two-step methods meet on the same problem."""
+    from paper_2406_03468_amd import binding
+    P = make_problem(4000, 50, kappa, rnorm, seed=5)
+    two = []
+    for meth in ("fossils", "spir"):
+        _, _, x = _solve(ctx, P, meth)
+        two.append(be.relative_backward_error(P.A, P.b, x, P.sigma, P.V))
+    assert max(two) <= 1e-14
+    for meth, kw, okw in [("spir", dict(steps=1, init=binding.FS_INIT_ZERO), dict(steps=1, init="zero")),
+                          ("spir_lsqr", dict(steps=1, init=binding.FS_INIT_ZERO), dict(steps=1, init="zero")),
+                          ("spir", dict(steps=1), dict(steps=1)),
+                          ("fossils", dict(steps=1), dict(steps=1))]:
+        _, info, x = _solve(ctx, P, meth, **kw)
+        ref = solvers.solve(P.A, P.b, meth, solvers.Options(precond="svd", **okw))
+        bg = be.relative_backward_error(P.A, P.b, x, P.sigma, P.V)
+        bo = be.relative_backward_error(P.A, P.b, ref.x, P.sigma, P.V)
+        assert bg >= 30 * max(two), (meth, kw, bg)
+        assert bo / 10 <= bg <= 10 * bo, (meth, kw, bg, bo)

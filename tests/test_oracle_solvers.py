@@ -285,3 +285,25 @@ def test_spir_lsqr_backward_stable(kappa, rnorm, precond):
     assert fe <= 10 * fq
     cg = solvers.spir(P.A, P.b, solvers.Options(precond=precond))
     assert abs(r.iters[0] - cg.iters[0]) <= 2
+
+
+@pytest.mark.parametrize("kappa,rnorm", [(1e12, 1e12 * U), (1e10, 1e-6)])
+def test_section51_comparison_solvers(kappa, rnorm):
+    """Section 5.1's comparison methods are not backward stable where FOSSILS and SPIR are:
+    sketch-and-precondition from x_0 = 0 (CG or LSQR, one run) and from the sketch-and-solve start,
+    and iterative sketching with momentum (FOSSILS with one refinement step)."""
+    P = make_problem(4000, 50, kappa, rnorm, seed=5)
+    bes, fes = {}, {}
+    for name, meth, o in [("spir", "spir", {}), ("fossils", "fossils", {}),
+                          ("sp_zero", "spir", dict(steps=1, init="zero")),
+                          ("sp_zero_lsqr", "spir_lsqr", dict(steps=1, init="zero")),
+                          ("sp_ss", "spir", dict(steps=1)), ("fossils1", "fossils", dict(steps=1))]:
+        r = solvers.solve(P.A, P.b, meth, solvers.Options(**o))
+        bes[name] = be.relative_backward_error(P.A, P.b, r.x, P.sigma, P.V)
+        fes[name] = np.linalg.norm(r.x - P.x_true) / np.linalg.norm(P.x_true)
+    assert bes["spir"] <= 1e-15 and bes["fossils"] <= 1e-15
+    for k in ("sp_zero", "sp_zero_lsqr", "sp_ss", "fossils1"):
+        assert bes[k] >= 30 * max(bes["spir"], bes["fossils"]), (k, bes)
+    # from x_0 = 0 the method is not even forward stable (Section 5.1): its forward error is far
+    # above that of the same run started from sketch-and-solve
+    assert fes["sp_zero"] >= 100 * fes["sp_ss"], fes
