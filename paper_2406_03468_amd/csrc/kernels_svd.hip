@@ -166,16 +166,32 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum over the 16 lanes of a DPP row (a pair handled by a 16-lane group); every lane of the row
+// receives the row's sum.
+__device__ __forceinline__ double row_sum_dpp(double v) {
+  v += dpp_d<0xB1, 0xf>(v);
+  v += dpp_d<0x4E, 0xf>(v);
+  v += dpp_d<0x141, 0xf>(v);
+  v += dpp_d<0x140, 0xf>(v);
+  return v;
+}
+template <int LP>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(LP == 16 || LP == 64, "pairs are handled by 16-lane rows or whole waves");
+  if constexpr (LP == 16) return row_sum_dpp(v);
+  else return wave_sum_dpp(v);
+}
+
 // The same rotation with the column pair held in registers (NQ = ceil(n / 64) elements per lane):
 // every LDS load is issued before the first use, so the dot products wait once for the whole column
 // instead of once per 64-element step.  Same arithmetic in the same order as jac_rotate_pair.
-template <int NQ>
+template <int NQ, int LP>
 __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double* __restrict__ y, int n, double tol,
                                                   int lane, int& nrot, double& c2max) {
   double xr[NQ], yr[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
-    const int q = lane + 64 * k;
+    const int q = lane + LP * k;
     xr[k] = (q < n) ? x[q] : 0.0;
     yr[k] = (q < n) ? y[q] : 0.0;
   }
@@ -186,9 +202,9 @@ __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double
     sb = fma(yr[k], yr[k], sb);
     sc = fma(xr[k], yr[k], sc);
   }
-  sa = wave_sum_dpp(sa);
-  sb = wave_sum_dpp(sb);
-  sc = wave_sum_dpp(sc);
+  sa = group_sum<LP>(sa);
+  sb = group_sum<LP>(sb);
+  sc = group_sum<LP>(sc);
   if (sa > 0.0 && sb > 0.0) c2max = fmax(c2max, (sc * sc) / (sa * sb));
   // |cos| > tol without square roots (column norms of R are O(1): no overflow or underflow here)
   if (sa > 0.0 && sb > 0.0 && sc * sc > (tol * tol) * (sa * sb)) {
@@ -199,7 +215,7 @@ __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double
     const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
-      const int q = lane + 64 * k;
+      const int q = lane + LP * k;
       if (q < n) {
         x[q] = cs * xr[k] - sn * yr[k];
         y[q] = sn * xr[k] + cs * yr[k];
@@ -209,11 +225,51 @@ __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double
   }
 }
 
-template <int NQ>
+// Rotation of a pair whose first column stays in registers (xr, NQ elements per lane) and whose
+// second column is in LDS: a group keeps its top column through all sub-rounds of a round, so only
+// the partner column moves through LDS.
+template <int NQ, int LP>
+__device__ __forceinline__ void jac_rotate_xreg(double (&xr)[NQ], double* __restrict__ y, int n, double tol,
+                                                int lane, int& nrot, double& c2max) {
+  double yr[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    const int q = lane + LP * k;
+    yr[k] = (q < n) ? y[q] : 0.0;
+  }
+  double sa = 0.0, sb = 0.0, sc = 0.0;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    sa = fma(xr[k], xr[k], sa);
+    sb = fma(yr[k], yr[k], sb);
+    sc = fma(xr[k], yr[k], sc);
+  }
+  sa = group_sum<LP>(sa);
+  sb = group_sum<LP>(sb);
+  sc = group_sum<LP>(sc);
+  if (sa > 0.0 && sb > 0.0) c2max = fmax(c2max, (sc * sc) / (sa * sb));
+  if (sa > 0.0 && sb > 0.0 && sc * sc > (tol * tol) * (sa * sb)) {
+    const double zeta = (sb - sa) / (2.0 * sc);
+    double t;
+    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+    else t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const int q = lane + LP * k;
+      const double xn = cs * xr[k] - sn * yr[k];
+      if (q < n) y[q] = sn * xr[k] + cs * yr[k];
+      xr[k] = (q < n) ? xn : 0.0;
+    }
+    ++nrot;
+  }
+}
+
+template <int NQ, int LP>
 __device__ __forceinline__ void jac_rotate(double* __restrict__ x, double* __restrict__ y, int n, double tol,
                                            int lane, int& nrot, double& c2max) {
-  if constexpr (NQ > 0) jac_rotate_pair_r<NQ>(x, y, n, tol, lane, nrot, c2max);
-  else jac_rotate_pair(x, y, n, tol, lane, nrot, c2max);
+  if constexpr (NQ > 0) jac_rotate_pair_r<NQ, LP>(x, y, n, tol, lane, nrot, c2max);
+  else jac_rotate_pair(x, y, n, tol, lane, nrot, c2max);  // LP == 64
 }
 
 // 16-byte coherent mailbox traffic (two doubles per access; offsets are 16-byte aligned).
@@ -241,7 +297,9 @@ __device__ __forceinline__ void wait_flag(unsigned* f, unsigned target, int* err
   }
 }
 
-template <int NQ>
+// NQ: elements per lane of a register-resident column (0: loop over LDS); LP: lanes per pair (16 for
+// n <= 256, so that a wave rotates four pairs at once, else 64).
+template <int NQ, int LP>
 __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
                                                       double tol, double* __restrict__ mbox, unsigned* __restrict__ flags,
                                                       int* __restrict__ rotcount, int* __restrict__ sweeps_out,
@@ -249,7 +307,7 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
                                                       double stop_cos2) {
   extern __shared__ double lds[];  // [2][b][n]
   const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  const int gl = tid % LP, grp = tid / LP, ngrp = blockDim.x / LP;  // pair groups (rows or waves)
   const size_t blk = (size_t)b * n;
   double* slot[2] = {lds, lds + blk};
   unsigned bgen = 0;
@@ -267,8 +325,8 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
   // mailbox layout: [P][2 slots][2 parities][b*n]
   auto mb = [&](int wg, int sl, int par) { return (((size_t)wg * 2 + sl) * 2 + par) * blk; };  // element offset
   const auto rmbox = co_rsrc(mbox, sizeof(double) * (size_t)P * 4 * blk);
-  __shared__ int s_nrot[16];
-  __shared__ double s_c2[16];
+  __shared__ int s_nrot[SVD_BLOCK_NT / 16];
+  __shared__ double s_c2[SVD_BLOCK_NT / 16];
   int sweep = 0;
   unsigned rr = 0;  // global round counter
   for (; sweep < max_sweeps; ++sweep) {
@@ -280,24 +338,60 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
         // pairs inside each block: round-robin over b' = b rounded up to even
         const int be = b + (b & 1);
         for (int sr = 0; sr < be - 1; ++sr) {
-          for (int pp = wv; pp < be; pp += nw) {  // be/2 pairs per block, two blocks
+          for (int pp = grp; pp < be; pp += ngrp) {  // be/2 pairs per block, two blocks
             const int s2 = pp / (be / 2), k = pp % (be / 2);
             int a = circle_player(k, sr, be), c2 = circle_player(be - 1 - k, sr, be);
             const int nc = s2 ? nc1 : nc0;
             if (a < nc && c2 < nc)
-              jac_rotate<NQ>(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, lane, nrot, c2max);
+              jac_rotate<NQ, LP>(slot[s2] + (size_t)a * n, slot[s2] + (size_t)c2 * n, n, tol, gl, nrot, c2max);
           }
           __syncthreads();
         }
       }
       // pairs between the two blocks: sub-round s pairs top column t with bottom column (t+s) mod b
-      for (int sr = 0; sr < b; ++sr) {
-        for (int t = wv; t < b; t += nw) {
-          const int c2 = (t + sr) % b;
-          if (t < nc0 && c2 < nc1)
-            jac_rotate<NQ>(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, lane, nrot, c2max);
+      if constexpr (NQ > 0) {
+        if (b <= ngrp) {
+          // group t holds top column t in registers for the whole round
+          const int t = grp;
+          const bool own = t < b && t < nc0;
+          double xr[NQ];
+#pragma unroll
+          for (int k = 0; k < NQ; ++k) {
+            const int q = gl + LP * k;
+            xr[k] = (own && q < n) ? slot[0][(size_t)t * n + q] : 0.0;
+          }
+          for (int sr = 0; sr < b; ++sr) {
+            const int c2 = (t + sr) % b;
+            if (own && c2 < nc1) jac_rotate_xreg<NQ, LP>(xr, slot[1] + (size_t)c2 * n, n, tol, gl, nrot, c2max);
+            __syncthreads();
+          }
+          if (own) {
+#pragma unroll
+            for (int k = 0; k < NQ; ++k) {
+              const int q = gl + LP * k;
+              if (q < n) slot[0][(size_t)t * n + q] = xr[k];
+            }
+          }
+          __syncthreads();
+        } else {
+          for (int sr = 0; sr < b; ++sr) {
+            for (int t = grp; t < b; t += ngrp) {
+              const int c2 = (t + sr) % b;
+              if (t < nc0 && c2 < nc1)
+                jac_rotate<NQ, LP>(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, gl, nrot, c2max);
+            }
+            __syncthreads();
+          }
         }
-        __syncthreads();
+      } else {
+        for (int sr = 0; sr < b; ++sr) {
+          for (int t = grp; t < b; t += ngrp) {
+            const int c2 = (t + sr) % b;
+            if (t < nc0 && c2 < nc1)
+              jac_rotate<NQ, LP>(slot[0] + (size_t)t * n, slot[1] + (size_t)c2 * n, n, tol, gl, nrot, c2max);
+          }
+          __syncthreads();
+        }
       }
       if (NBLK == 2) continue;  // a single work-group holds every column: nothing moves
       // ---- exchange.  In the next round position q >= 2 holds the block now at q + 1... i.e. blocks
@@ -384,15 +478,15 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
       id[1] = circle_player(NBLK - 1 - p, r + 1, NBLK);
     }
     // sweep total and largest cosine (positive doubles order like their bit patterns)
-    if (lane == 0) {
-      s_nrot[wv] = nrot;
-      s_c2[wv] = c2max;
+    if (gl == 0) {
+      s_nrot[grp] = nrot;
+      s_c2[grp] = c2max;
     }
     __syncthreads();
     if (tid == 0) {
       int t = 0;
       double c2 = 0.0;
-      for (int w = 0; w < nw; ++w) {
+      for (int w = 0; w < ngrp; ++w) {
         t += s_nrot[w];
         c2 = fmax(c2, s_c2[w]);
       }
@@ -587,7 +681,9 @@ int svd_block_width(int n) {
   const int bmax = SVD_LDS_BYTES / (2 * 8 * n);
   if (bmax < 1) return 0;                 // too large: pairwise fallback
   if (2 * bmax >= n) return (n + 1) / 2;  // everything in one work-group
-  return bmax < 8 ? bmax : 8;
+  // a work-group rotates 8 pairs at once with whole-wave pairs, 32 with 16-lane pairs (n <= 256)
+  const int bcap = (n <= 256) ? 32 : 8;
+  return bmax < bcap ? bmax : bcap;
 }
 }  // namespace
 
@@ -655,11 +751,13 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t shmem = (size_t)2 * bw * n * sizeof(double);
     // columns of up to 2048 rows are rotated from registers (NQ = elements per lane)
-    const void* kfn = (n <= 256)    ? (const void*)k_jacobi_block<4>
-                      : (n <= 512)  ? (const void*)k_jacobi_block<8>
-                      : (n <= 1024) ? (const void*)k_jacobi_block<16>
-                      : (n <= 2048) ? (const void*)k_jacobi_block<32>
-                                    : (const void*)k_jacobi_block<0>;
+    const void* kfn = (n <= 64)     ? (const void*)k_jacobi_block<4, 16>
+                      : (n <= 128)  ? (const void*)k_jacobi_block<8, 16>
+                      : (n <= 256)  ? (const void*)k_jacobi_block<16, 16>
+                      : (n <= 512)  ? (const void*)k_jacobi_block<8, 64>
+                      : (n <= 1024) ? (const void*)k_jacobi_block<16, 64>
+                      : (n <= 2048) ? (const void*)k_jacobi_block<32, 64>
+                                    : (const void*)k_jacobi_block<0, 64>;
     (void)hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
     int NB2 = NBLK;
     int bw2 = bw;
