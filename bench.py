@@ -38,7 +38,7 @@ HBM_PEAK_GBPS = 8000.0
 # by a 1 GiB copy (profiles/fused_pass_1e6x1000_hbm_traffic.md); valid only for the kernel source
 # with this hash (reported as null otherwise).
 PASS_TRAFFIC_BYTES = 8.0020e9
-PASS_TRAFFIC_SHA256 = "1234717bd0b6d2c65a3add37aa8696614cb0381f67f1a380903c5f4518f303d6"
+PASS_TRAFFIC_SHA256 = "1a485d88ec8c53282727de27a9bd80f844d0d3eedc2c4b60dca499af21a38fe2"
 
 
 def parse():
@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--precond", default="svd", choices=["qr", "svd"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=100)
+    ap.add_argument("--cpu-iters", type=int, default=300)
     ap.add_argument("--pass-repeats", type=int, default=20)
     ap.add_argument("--multi", type=int, default=64, help="right-hand sides of the multi-RHS line (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2048, help="requests of the serving line (0: skip)")

@@ -520,6 +520,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   // Sketch (Alg 1 first statement; Alg 4 column scaling in the same read of A), QR of the sketch,
   // SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate), then a read-back
   // of the statistics.  fp32: the mixed-precision form's sketch (FP32 accumulation, from A32 if given).
+  std::vector<double> rdiag(n);
+  bool early_fallback = false;
   auto factor = [&](bool fp32) -> fs_status {
     if (fp32)
       FS_K(fs_launch_sketch_apply_fp32(A, lda, A32, lda32, m, n, b, m, 1, W.idx.p, i16, d, zeta, Y, d, cn2,
@@ -533,6 +535,22 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     CoopSection coop(ctx, std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false)));
     FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
     FS_HIP(hipEventRecord(ev[2], s));
+    if (fp32) {
+      // max |r_ii| / min |r_ii| <= cond(R): when it alone passes the threshold, the FP32-copy sketch is
+      // dropped before its SVD (the costlier half of the factorization)
+      FS_HIP(hipMemcpy2DAsync(rdiag.data(), sizeof(double), R, sizeof(double) * (ldr + 1), sizeof(double), n,
+                              hipMemcpyDeviceToHost, s));
+      FS_HIP(hipStreamSynchronize(s));
+      double dmax = 0.0, dmin = INFINITY;
+      for (int j = 0; j < n; ++j) {
+        dmax = std::max(dmax, fabs(rdiag[j]));
+        dmin = std::min(dmin, fabs(rdiag[j]));
+      }
+      if (!(dmax * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION * dmin)) {
+        early_fallback = true;
+        return FS_OK;
+      }
+    }
     FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
                             svd_sweeps_dev, s));
     FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
@@ -557,7 +575,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   const bool mixed = (o.precision == FS_MIXED);
   int flags = 0;
   FS_TRY(factor(mixed));
-  if (mixed && !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
+  if (mixed && (early_fallback || !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION))) {
     // The FP32 sketch perturbs S A by about u32 ||A||: as a preconditioner its R keeps A_s R^{-1}
     // well conditioned only while condest u32 is small (the hazard of Lemma 6.3 at single precision).
     // Otherwise the sketch is redone in FP64 (the FP64 correction of R) and the solve continues in FP64.
