@@ -37,8 +37,8 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per launch of the fused pass at 1e6 x 1000 from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
 # by a 1 GiB copy (profiles/fused_pass_1e6x1000_hbm_traffic.md); valid only for the kernel source
 # with this hash (reported as null otherwise).
-PASS_TRAFFIC_BYTES = 8.0020e9
-PASS_TRAFFIC_SHA256 = "1a485d88ec8c53282727de27a9bd80f844d0d3eedc2c4b60dca499af21a38fe2"
+PASS_TRAFFIC_BYTES = 8.0081e9
+PASS_TRAFFIC_SHA256 = "bbacb874cbada7af009d0cd529cd957f7313bfff9fed99d6ce89f1a6a86c93f7"
 
 
 def parse():

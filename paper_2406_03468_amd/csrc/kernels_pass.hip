@@ -23,8 +23,10 @@
 
 namespace {
 
-template <int H, int NT, int L, bool RESID, bool VEC>
-__global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+typedef double fs_v2d __attribute__((ext_vector_type(2)));
+
+template <int H, int NT, int L, bool RESID, bool VEC, bool PF = true>
+__global__ __launch_bounds__(NT, PF ? 1 : 2) void k_fused_pass(const double* __restrict__ A, int64_t lda, int64_t m, int n,
                                                    const double* __restrict__ zs, const double* __restrict__ b,
                                                    double* __restrict__ partial, double* __restrict__ partial_r2,
                                                    const int* __restrict__ stop, double* __restrict__ rout) {
@@ -73,10 +75,16 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
   const uint32_t voff = (uint32_t)(((int64_t)cb * lda + 2 * rp) * (int64_t)sizeof(double));
   const uint32_t boff = (uint32_t)(2 * rp * sizeof(double));
   const uint32_t voffL = (cb + (L - 1) * CPR < n) ? voff : boff;
+  // Streaming loads carry the non-temporal hint: A is read once per pass and should not displace
+  // the reused data (z, the partials) from the caches (a read-only stream measured 6.2 -> 6.9 TB/s
+  // with it on this GPU).
   auto ld2 = [&](const char* p) -> double2 {
-    if (VEC) return *reinterpret_cast<const double2*>(p);
+    if (VEC) {
+      const fs_v2d t = __builtin_nontemporal_load(reinterpret_cast<const fs_v2d*>(p));
+      return make_double2(t.x, t.y);
+    }
     const double* q = reinterpret_cast<const double*>(p);
-    return make_double2(q[0], q[1]);
+    return make_double2(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
   };
   auto load = [&](double2 (&a)[L + 1], int64_t t) {  // a full tile
     // The tile's byte offset goes through readfirstlane: it stays a scalar, and the compiler
@@ -149,17 +157,26 @@ __global__ __launch_bounds__(NT) void k_fused_pass(const double* __restrict__ A,
     }
   };
 
-  double2 bufA[L + 1], bufB[L + 1];
+  double2 bufA[L + 1];
   int64_t t = lo + l0;
-  if (t < hi) load(bufA, t);
-  while (t < hi) {
-    if (t + step < hi) load(bufB, t + step);
-    process(bufA, t, 0);
-    t += step;
-    if (t >= hi) break;
-    if (t + step < hi) load(bufA, t + step);
-    process(bufB, t, 1);
-    t += step;
+  if constexpr (PF) {
+    double2 bufB[L + 1];
+    if (t < hi) load(bufA, t);
+    while (t < hi) {
+      if (t + step < hi) load(bufB, t + step);
+      process(bufA, t, 0);
+      t += step;
+      if (t >= hi) break;
+      if (t + step < hi) load(bufA, t + step);
+      process(bufB, t, 1);
+      t += step;
+    }
+  } else {
+    int par = 0;
+    for (; t < hi; t += step, par ^= 1) {
+      load(bufA, t);
+      process(bufA, t, par);
+    }
   }
   if (T * H < m && g == G - 1) {  // ragged last tile (uniform branch: whole work-group)
     __syncthreads();
