@@ -40,6 +40,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
   const int nr = (re > rs) ? re - rs : 0;
 
   __shared__ double pan[RBMAX][NB + 1];
+  __shared__ __align__(16) double vm[RBMAX][NB];  // the panel's V, zeros written out (row reads broadcast)
   __shared__ double T[NB][NB + 1];
   __shared__ double sred[QR_NT / 64][NB];
   __shared__ double sdots[NB], srow[NB], sw[NB], svtv[NB], srdiag[NB];
@@ -158,20 +159,33 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
     if (k1 < k) {
       const int ntr = k - k1;
       const int r_lo = (k0 > rs) ? k0 - rs : 0;
+      // V of the panel with its zeros written out (V[r][q] is nonzero only for q <= rs + r - k0 and
+      // q < nbp), so the trailing-update loops below carry no per-element selects
+      for (int i = tid; i < nr * NB; i += QR_NT) {
+        const int r = i / NB, q = i % NB;
+        vm[r][q] = (q <= rs + r - k0 && q < nbp) ? pan[r][q] : 0.0;
+      }
+      __syncthreads();
       // (T1) partial W_g = V_own^T Y_own[:, k1:k]
       for (int cc = tid; cc < ntr; cc += QR_NT) {
         double acc[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) acc[q] = 0.0;
         const double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
-        for (int r = r_lo; r < nr; ++r) {
-          const double y = ycol[r];
-          const int lim = rs + r - k0;  // V[r][q] nonzero for q <= lim
+        int r = r_lo;
+        for (; r + 8 <= nr; r += 8) {  // eight rows' loads in flight before their FMAs
+          double y[8];
 #pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            const double v = (q <= lim && q < nbp) ? pan[r][q] : 0.0;
-            acc[q] = fma(v, y, acc[q]);
-          }
+          for (int u = 0; u < 8; ++u) y[u] = ycol[r + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[q] = fma(vm[r + u][q], y[u], acc[q]);
+        }
+        for (; r < nr; ++r) {
+          const double y = ycol[r];
+#pragma unroll
+          for (int q = 0; q < NB; ++q) acc[q] = fma(vm[r][q], y, acc[q]);
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) st_cob(rwpart, 8 * (((size_t)g * NB + q) * k + cc), acc[q]);
@@ -216,14 +230,25 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
 #pragma unroll
         for (int q = 0; q < NB; ++q) wv[q] = (q < nbp) ? ld_cob(rwred, 8 * ((size_t)q * k + cc)) : 0.0;
         double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
-        for (int r = r_lo; r < nr; ++r) {
-          const int lim = rs + r - k0;
+        int r = r_lo;
+        for (; r + 4 <= nr; r += 4) {  // four rows' independent sums (each in the same q order)
+          double y[4], s2[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            y[u] = ycol[r + u];
+            s2[u] = 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s2[u] = fma(vm[r + u][q], wv[q], s2[u]);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) ycol[r + u] = y[u] - s2[u];
+        }
+        for (; r < nr; ++r) {
           double s2 = 0.0;
 #pragma unroll
-          for (int q = 0; q < NB; ++q) {
-            const double v = (q <= lim) ? pan[r][q] : 0.0;
-            s2 = fma(v, wv[q], s2);
-          }
+          for (int q = 0; q < NB; ++q) s2 = fma(vm[r][q], wv[q], s2);
           ycol[r] -= s2;
         }
       }
