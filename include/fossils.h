@@ -78,6 +78,12 @@ typedef struct fs_options {
   int32_t max_sweeps;     /* Jacobi sweep cap of the SVD of R */
   int32_t init;           /* FS_INIT_SKETCH: x_0 = sketch-and-solve (Alg 4); FS_INIT_ZERO: x_0 = 0 (the
                              zero start of plain sketch-and-precondition, for the Section 5.1 comparisons) */
+  int32_t overlap_svd;    /* 1 (P = V Sigma^{-1}, adaptive FOSSILS or CG-SPIR, FP64): the SVD of R runs on
+                             a second stream while the first refinement step iterates with P = R^{-1}
+                             (the same preconditioned system up to an orthogonal change of variables);
+                             its iterates are recorded and, once normest and condest are known, the step
+                             is cut back to the iteration where the first-step rule stops.  Falls back to
+                             the serial order when R turns out numerically rank deficient. */
   int32_t graph_sweeps;   /* 1: the inner iterations run as a captured HIP graph of kw_every iterations,
                              replayed until the device-side stop flag is set (one launch and one
                              host poll per kw_every iterations); 0: kernel-by-kernel launches */

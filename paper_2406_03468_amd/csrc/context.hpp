@@ -26,6 +26,7 @@ struct Workspace {
   DevBuf idx, Y, colnorm2, dinv, qrwork, svdwork, sigma, V, UR, partial, pr2, wscratch, gemvpart, vecs, state;
   DevBuf mwork, mvecs, mstate;  // multi-RHS solves
   DevBuf lsqr;                  // LSQR form of SPIR: the residual r and ubar = alpha u (2 m-vectors)
+  DevBuf hist;                  // first step beside the SVD: iterates and ||Delta||^2 per iteration
 };
 
 struct fs_context_s {
@@ -39,6 +40,8 @@ struct fs_context_s {
   // Set by a server whose slots share the GPU (see CoopBudget).
   struct CoopBudget* coop_budget = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream for graph capture (created on first use)
+  hipStream_t aux_stream = nullptr;  // second stream: the SVD of R beside the first refinement step
+  hipEvent_t ev_aux = nullptr;       // (both created on first use)
 };
 
 // Cooperative kernels (QR, SVD) need every work-group of their grid resident at once.  Slots of a
@@ -56,8 +59,9 @@ struct CoopBudget {
 // Holds a reservation of `need` work-groups (if the context has a budget) until the stream drains.
 struct CoopSection {
   fs_context_s* ctx;
+  hipStream_t strm;
   int need = 0;
-  CoopSection(fs_context_s* c, int need_wgs) : ctx(c) {
+  CoopSection(fs_context_s* c, int need_wgs, hipStream_t on = nullptr) : ctx(c), strm(on ? on : c->stream) {
     CoopBudget* b = c->coop_budget;
     if (!b) return;
     need = std::max(1, std::min(need_wgs, b->total));
@@ -67,7 +71,7 @@ struct CoopSection {
   }
   ~CoopSection() {
     if (!need) return;
-    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamSynchronize(strm);
     CoopBudget* b = ctx->coop_budget;
     {
       std::lock_guard<std::mutex> lk(b->mu);

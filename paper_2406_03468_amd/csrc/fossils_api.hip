@@ -87,6 +87,7 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
   if (o.graph_sweeps != 0 && o.graph_sweeps != 1) return FS_ERR_INVALID_ARG;
   if (o.init != FS_INIT_SKETCH && o.init != FS_INIT_ZERO) return FS_ERR_INVALID_ARG;
+  if (o.overlap_svd != 0 && o.overlap_svd != 1) return FS_ERR_INVALID_ARG;
   (void)m;
   return FS_OK;
 }
@@ -135,6 +136,7 @@ fs_status fs_options_default(int64_t m, int32_t n, fs_options* o) {
   o->precision = FS_FP64;
   o->max_sweeps = 40;
   o->init = FS_INIT_SKETCH;
+  o->overlap_svd = 1;
   o->graph_sweeps = 0;  // measured no faster than kernel-by-kernel launches (the host enqueues ahead)
   return FS_OK;
 }
@@ -171,9 +173,15 @@ fs_status fs_context_destroy(fs_context c) {
   (void)hipStreamSynchronize(c->stream);
   Workspace& w = c->ws;
   for (DevBuf* b : {&w.idx, &w.Y, &w.colnorm2, &w.dinv, &w.qrwork, &w.svdwork, &w.sigma, &w.V, &w.UR, &w.partial,
-                    &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate, &w.lsqr})
+                    &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate, &w.lsqr,
+                    &w.hist})
     free_buf(*b);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->aux_stream) {
+    (void)hipStreamSynchronize(c->aux_stream);
+    (void)hipStreamDestroy(c->aux_stream);
+  }
+  if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -467,8 +475,12 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   FS_HIP(hipStreamSynchronize(s));  // workspace may be reallocated below
+  if (ctx->aux_stream) FS_HIP(hipStreamSynchronize(ctx->aux_stream));
   Workspace& W = ctx->ws;
   const int d = o.d, zeta = o.zeta, k = n + 1;
+  // The SVD of R beside the first refinement step (see fs_options.overlap_svd).
+  bool defer = o.overlap_svd && o.precond == FS_PRECOND_SVD && o.precision == FS_FP64 && o.fixed_q == 0 &&
+               (method == M_FOSSILS || method == M_SPIR);
   const bool i16 = idx16_ok(d);
 
   // ---- workspace
@@ -486,6 +498,13 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_TRY(grow(W.vecs, sizeof(double) * (size_t)NV * n));
   FS_TRY(grow(W.state, sizeof(DevState) + 64));
   FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  if (defer) {
+    FS_TRY(grow(W.hist, sizeof(double) * ((size_t)o.max_inner * n + o.max_inner + 8)));
+    if (!ctx->aux_stream) FS_HIP(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+    if (!ctx->ev_aux) FS_HIP(hipEventCreateWithFlags(&ctx->ev_aux, hipEventDisableTiming));
+  }
+  double* hist_dy = defer ? (double*)W.hist.p : nullptr;
+  double* hist_dn = defer ? hist_dy + (size_t)o.max_inner * n : nullptr;
   const bool lsqr = (method == M_SPIR_LSQR);
   if (lsqr) FS_TRY(grow(W.lsqr, sizeof(double) * 2 * (size_t)m));
   double* rbuf = lsqr ? (double*)W.lsqr.p : nullptr;  // r of the last LSQR pass (m)
@@ -522,7 +541,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   // of the statistics.  fp32: the mixed-precision form's sketch (FP32 accumulation, from A32 if given).
   std::vector<double> rdiag(n);
   bool early_fallback = false;
-  auto factor = [&](bool fp32) -> fs_status {
+  auto factor = [&](bool fp32, bool defer_svd) -> fs_status {
     if (fp32)
       FS_K(fs_launch_sketch_apply_fp32(A, lda, A32, lda32, m, n, b, m, 1, W.idx.p, i16, d, zeta, Y, d, cn2,
                                        o.column_scaling != 0, true, ctx->lds_bytes, s));
@@ -532,7 +551,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
     FS_HIP(hipEventRecord(ev[1], s));
     // grid-synchronizing kernels: work-groups reserved against other slots of a server
-    CoopSection coop(ctx, std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false)));
+    CoopSection coop(ctx, defer_svd ? fs_qr_grid_size(d, ctx->num_cu)
+                                    : std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false)));
     FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
     FS_HIP(hipEventRecord(ev[2], s));
     if (fp32) {
@@ -551,17 +571,27 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
         return FS_OK;
       }
     }
-    FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
-                            svd_sweeps_dev, s));
-    FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
-    FS_HIP(hipEventRecord(ev[3], s));
+    if (defer_svd) {
+      // the SVD is launched by the caller on the second stream; until it fills in normest and
+      // condest they hold lower bounds from diag(R), so the first step can stop on its own no later
+      // than the true rule would (its threshold is recomputed and the step cut back once known)
+      FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
+      FS_HIP(hipEventRecord(ctx->ev_aux, s));
+    } else {
+      FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+                              svd_sweeps_dev, s));
+      FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
+      FS_HIP(hipEventRecord(ev[3], s));
+    }
     FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     FS_HIP(hipMemcpyAsync(cnh.data(), cn2, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, s));
     int bar_err[2] = {0, 0};
-    FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     FS_HIP(hipMemcpyAsync(&bar_err[0], fs_qr_err_word(W.qrwork.p, d, k, ctx->num_cu), sizeof(int),
                           hipMemcpyDeviceToHost, s));
-    FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
+    if (!defer_svd) {
+      FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
+    }
     FS_HIP(hipStreamSynchronize(s));
     if (bar_err[0] || bar_err[1]) {
       fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the QR/SVD kernels gave up waiting", __FILE__,
@@ -574,13 +604,43 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   };
   const bool mixed = (o.precision == FS_MIXED);
   int flags = 0;
-  FS_TRY(factor(mixed));
+  FS_TRY(factor(mixed, defer));
+  if (defer && cnh[n] == 0.0) {  // b = 0 ends the solve below: no overlap, the SVD runs here
+    defer = false;
+    CoopSection cs(ctx, fs_svd_grid_size(n, ctx->num_cu, false));
+    FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+                            svd_sweeps_dev, s));
+    FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));
+    FS_HIP(hipEventRecord(ev[3], s));
+    FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+  }
+  // The deferred SVD: on the second stream after the QR, with its work-group reservation held
+  // until that stream drains; the guard drains it on every exit path (the workspace is shared).
+  std::unique_ptr<CoopSection> svd_coop;
+  struct AuxDrain {
+    hipStream_t a = nullptr;
+    ~AuxDrain() {
+      if (a) (void)hipStreamSynchronize(a);
+    }
+  } aux_drain;
+  if (defer) {
+    hipStream_t a = ctx->aux_stream;
+    aux_drain.a = a;
+    FS_HIP(hipStreamWaitEvent(a, ctx->ev_aux, 0));
+    svd_coop = std::make_unique<CoopSection>(ctx, fs_svd_grid_size(n, ctx->num_cu, false), a);
+    FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+                            svd_sweeps_dev, a));
+    FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, a));
+    FS_HIP(hipEventRecord(ev[3], a));
+  }
   if (mixed && (early_fallback || !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION))) {
     // The FP32 sketch perturbs S A by about u32 ||A||: as a preconditioner its R keeps A_s R^{-1}
     // well conditioned only while condest u32 is small (the hazard of Lemma 6.3 at single precision).
     // Otherwise the sketch is redone in FP64 (the FP64 correction of R) and the solve continues in FP64.
     flags |= FS_FLAG_FP64_SKETCH;
-    FS_TRY(factor(false));
+    FS_TRY(factor(false, false));
   }
   const double b2 = cnh[n];
   DevState hs = *ctx->st_host;
@@ -595,9 +655,10 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     if (info) *info = inf;
     return FS_OK;
   }
-  bool use_svd = (o.precond == FS_PRECOND_SVD);
+  bool use_svd = (o.precond == FS_PRECOND_SVD) && !defer;  // the deferred first step uses P = R^{-1}
   int rk = n;
-  if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {  // Alg 4: numerically rank deficient
+  // Alg 4: numerically rank deficient -> truncated SVD preconditioner (needs the SVD's statistics)
+  auto set_rank_deficient = [&]() -> fs_status {
     flags |= 1;
     rk = hs.rank_trunc > 0 ? hs.rank_trunc : 1;
     use_svd = true;
@@ -605,9 +666,11 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     // (rank-deficient problems only)
     CoopSection cs(ctx, fs_svd_grid_size(n, ctx->num_cu, true));
     FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, UR, n, W.svdwork.p, ctx->num_cu, o.max_sweeps, svd_sweeps_dev, s));
-  }
+    return FS_OK;
+  };
+  if (!defer && !(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) FS_TRY(set_rank_deficient());
   inf.rank = rk;
-  const int nr = use_svd ? rk : n;  // length of the preconditioned variables dy, c, ...
+  int nr = use_svd ? rk : n;  // length of the preconditioned variables dy, c, ...
 
   // P y (into out, n) and P^T v (into out, nr); yscale/xscale fold D^{-1}.
   auto applyP = [&](const double* y, double* out, const double* oscale, const double* addv, const int* stp) -> fs_status {
@@ -629,15 +692,19 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   };
 
   // ---- x_0: sketch-and-solve (eq:sketch-and-solve-2.3; Alg 4 with the SVD factors)
-  if (flags & 1) {
-    // truncated SVD start (Alg 4): x_0 = V_r Sigma_r^{-1} U_r^T t
-    FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));
-    FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
-  } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
-    FS_K(fs_launch_trsv(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, s));
-  }
-  if (o.init == FS_INIT_ZERO) FS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));  // (not captured)
-  FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));
+  auto start_x0 = [&]() -> fs_status {
+    if (flags & 1) {
+      // truncated SVD start (Alg 4): x_0 = V_r Sigma_r^{-1} U_r^T t
+      FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));
+      FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
+    } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
+      FS_K(fs_launch_trsv(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, s));
+    }
+    if (o.init == FS_INIT_ZERO) FS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));  // (not captured)
+    FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));
+    return FS_OK;
+  };
+  FS_TRY(start_x0());
 
   // theta^2 and the first-step threshold need ||b||^2 and ||A_s||_F^2
   {
@@ -665,6 +732,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_HIP(hipEventRecord(ev[4], s));
 
   for (int step = 0; step < o.steps; ++step) {
+    const bool dstep = defer && step == 0;  // first step beside the SVD (P = R^{-1}, iterates recorded)
+    bool thr_known = !dstep;
     // residual pass at x (scaled coordinates): g = D^{-1} A^T (b - A D^{-1} x), r2
     FS_K(fs_vec_mul(n, v.x, dinv, v.zs, nullptr, s));
     FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, nullptr, rbuf));
@@ -700,6 +769,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
         FS_TRY(applyPT(v.v, v.u, stop));                                 // u = P^T v
         if (method == M_FOSSILS) FS_K(fs_vec_polyak(nr, v.c, v.u, v.dy, v.dy_old, st, first, s));
         else FS_K(fs_vec_cg(nr, v.p, v.u, v.res, v.dy, st, first, s));
+        if (dstep) FS_K(fs_vec_record_iter(j, nr, v.dy, hist_dy, hist_dn, st, s));
       }
       const bool kw_now = (!fixed) && (step == 1) && (j % o.kw_every == 0);
       if (kw_now) {  // second-step rule (Alg 4): sketched KW at x_hat = x + P dy
@@ -718,8 +788,27 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       if (ctx->st_host->stop) stopped = true;
       return FS_OK;
     };
+    // the SVD's statistics have arrived: the real first-step threshold, then the cut back to the
+    // first recorded iteration that meets it
+    auto apply_threshold = [&]() -> fs_status {
+      FS_HIP(hipStreamWaitEvent(s, ev[3], 0));
+      FS_K(fs_vec_first_threshold(n, v.x0, o.gamma, o.rho, st, s));
+      FS_K(fs_vec_rollback(nr, hist_dy, hist_dn, v.dy, st, s));
+      thr_known = true;
+      return FS_OK;
+    };
     const int sweep = o.kw_every;
-    if (o.graph_sweeps && !fixed && cap % sweep == 0) {
+    if (dstep) {
+      for (int j = 0; j < cap && !stopped; ++j) {
+        FS_TRY(iteration(j));
+        const bool poll = ((j + 1) % sweep) == 0 || j == cap - 1;
+        if (poll) {
+          if (!thr_known && hipEventQuery(ev[3]) == hipSuccess) FS_TRY(apply_threshold());
+          FS_TRY(poll_stop());
+        }
+      }
+      if (!thr_known) FS_TRY(apply_threshold());
+    } else if (o.graph_sweeps && !fixed && cap % sweep == 0) {
       // kw_every iterations (the KW check, when due, is the first of them) captured once as a graph
       // and replayed; the host polls the stop flag after each replay, as the launch-by-launch loop does
       FS_TRY(sweep_graph_run(ctx, s, sweep, cap / sweep, iteration, poll_stop, stopped));
@@ -740,6 +829,40 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     cnorm[step] = sqrt(ctx->st_host->cnorm2);
     conv_last = ctx->st_host->converged != 0 || fixed;
     if (fixed) FS_K(fs_vec_set_int(&st->max_inner, o.max_inner, s));  // restore the cap
+    if (dstep) {
+      // join the SVD: statistics, barrier status; then the second step with P = V Sigma^{-1}
+      FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+      svd_coop.reset();
+      int bar_err = 0;
+      FS_HIP(hipMemcpyAsync(&bar_err, fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
+      FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+      FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+      FS_HIP(hipStreamSynchronize(s));
+      if (bar_err) {
+        fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the SVD kernel gave up waiting", __FILE__,
+                              __LINE__);
+        return FS_ERR_DEVICE;
+      }
+      hs.normest = ctx->st_host->normest;
+      hs.condest = ctx->st_host->condest;
+      hs.rank_trunc = ctx->st_host->rank_trunc;
+      inf.normest = hs.normest;
+      inf.condest = hs.condest;
+      inf.svd_sweeps = svd_sweeps;
+      defer = false;
+      if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {
+        // numerically rank deficient after all: start over in the serial order with the truncated
+        // preconditioner (the overlapped first step is discarded)
+        FS_TRY(set_rank_deficient());
+        inf.rank = rk;
+        nr = rk;
+        FS_TRY(start_x0());
+        iters[0] = 0;
+        step = -1;
+        continue;
+      }
+      use_svd = true;  // P = V Sigma^{-1} for the second step (full rank: nr = n)
+    }
   }
   // x_out = D^{-1} x
   FS_K(fs_vec_mul(n, v.x, dinv, x_out, nullptr, s));

@@ -313,6 +313,79 @@ __global__ __launch_bounds__(256) void k_lsqr_ubar(int64_t m, const double* __re
     ubar[i] = f * r[i];
 }
 
+// Lower bounds of normest and condest from the diagonal of R (|r_ii| lies between sigma_min and
+// sigma_max), used for the first-step threshold until the SVD of R has produced the true values:
+// the threshold they give is never above the true one.
+__global__ __launch_bounds__(VNT) void k_diag_bounds(int n, const double* __restrict__ R, int64_t ldr,
+                                                     DevState* __restrict__ st) {
+  __shared__ double smax[VNT / 64], smin[VNT / 64];
+  double mx = 0.0, mn = INFINITY;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double a = fabs(R[(int64_t)i * ldr + i]);
+    mx = fmax(mx, a);
+    mn = fmin(mn, a);
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    smax[w] = mx;
+    smin[w] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < VNT / 64; ++i) {
+      mx = fmax(mx, smax[i]);
+      mn = fmin(mn, smin[i]);
+    }
+    mx = fmax(mx, smax[0]);
+    mn = fmin(mn, smin[0]);
+    st->normest = mx;
+    st->condest = (mn > 0.0) ? mx / mn : 0.0;  // a zero diagonal: no usable bound
+  }
+}
+
+// First-step history while the SVD of R is still running (its normest and condest, hence the
+// first-step threshold, are not known yet): after inner iteration j (0-based) the iterate dy and
+// ||Delta||^2 are recorded when the iteration ran (iters == j + 1).
+__global__ __launch_bounds__(VNT) void k_record_iter(int j, int n, const double* __restrict__ dy,
+                                                     double* __restrict__ hist_dy, double* __restrict__ hist_dn,
+                                                     const DevState* __restrict__ st) {
+  if (st->iters != j + 1) return;
+  for (int i = threadIdx.x; i < n; i += VNT) hist_dy[(int64_t)j * n + i] = dy[i];
+  if (threadIdx.x == 0) hist_dn[j] = st->dnorm2;
+}
+
+// Once the threshold is known: the first recorded iteration with ||Delta|| <= thr_first is where
+// the first-step rule stops (Alg 4); its iterate becomes dy and the step ends there.
+__global__ __launch_bounds__(VNT) void k_rollback(int n, const double* __restrict__ hist_dy,
+                                                  const double* __restrict__ hist_dn, double* __restrict__ dy,
+                                                  DevState* __restrict__ st) {
+  __shared__ int sj;
+  if (threadIdx.x == 0) {
+    int jj = -1;
+    const double thr = st->thr_first;
+    for (int i = 0; i < st->iters; ++i)
+      if (sqrt(hist_dn[i]) <= thr) {
+        jj = i;
+        break;
+      }
+    sj = jj;
+  }
+  __syncthreads();
+  const int jj = sj;
+  if (jj < 0) return;
+  for (int i = threadIdx.x; i < n; i += VNT) dy[i] = hist_dy[(int64_t)jj * n + i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->iters = jj + 1;
+    st->stop = 1;
+    st->converged = 1;
+  }
+}
+
 // Start of a refinement step: dy = dy_old = c (FOSSILS) or dy = 0, res = p = c (SPIR); rho = c^T c.
 __global__ __launch_bounds__(VNT) void k_step_init(int n, const double* __restrict__ c, double* __restrict__ a,
                                                    double* __restrict__ b, double* __restrict__ dy, int spir,
@@ -497,6 +570,20 @@ hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, do
   return hipGetLastError();
 }
 
+hipError_t fs_vec_diag_bounds(int n, const double* R, int64_t ldr, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_bounds, dim3(1), dim3(VNT), 0, s, n, R, ldr, st);
+  return hipGetLastError();
+}
+hipError_t fs_vec_record_iter(int j, int n, const double* dy, double* hist_dy, double* hist_dn, const DevState* st,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_record_iter, dim3(1), dim3(VNT), 0, s, j, n, dy, hist_dy, hist_dn, st);
+  return hipGetLastError();
+}
+hipError_t fs_vec_rollback(int n, const double* hist_dy, const double* hist_dn, double* dy, DevState* st,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_rollback, dim3(1), dim3(VNT), 0, s, n, hist_dy, hist_dn, dy, st);
+  return hipGetLastError();
+}
 hipError_t fs_vec_lsqr_init(int n, const double* c, double* v, double* w, double* dy, DevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_lsqr_init, dim3(1), dim3(VNT), 0, s, n, c, v, w, dy, st);
   return hipGetLastError();

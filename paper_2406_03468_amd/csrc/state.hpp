@@ -37,6 +37,13 @@ hipError_t fs_vec_gemv_vt(const double* V, int64_t ldv, int n, int k, const doub
                           const int* stop, hipStream_t s);
 hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, double* dy_old, DevState* st,
                          bool first_step, hipStream_t s);
+// First step overlapped with the SVD of R: per-iteration record of dy and ||Delta||^2, and the
+// rollback to the first recorded iteration that meets the first-step rule once thr_first is known.
+hipError_t fs_vec_diag_bounds(int n, const double* R, int64_t ldr, DevState* st, hipStream_t s);
+hipError_t fs_vec_record_iter(int j, int n, const double* dy, double* hist_dy, double* hist_dn, const DevState* st,
+                              hipStream_t s);
+hipError_t fs_vec_rollback(int n, const double* hist_dy, const double* hist_dn, double* dy, DevState* st,
+                           hipStream_t s);
 // LSQR form of SPIR: start of a step (needs st->r2 = ||r||^2 and c = P^T A_s^T r), one bidiagonalization
 // and rotation step (h = P^T A_s^T (alpha u - A_s P v), st->r2 its squared residual), and the
 // m-vector ubar = alpha u from the stored residual r (sign -1 inside the iteration).

@@ -245,3 +245,47 @@ def test_section51_comparison_solvers_gpu(ctx, kappa, rnorm):
         bo = be.relative_backward_error(P.A, P.b, ref.x, P.sigma, P.V)
         assert bg >= 30 * max(two), (meth, kw, bg)
         assert bo / 10 <= bg <= 10 * bo, (meth, kw, bg, bo)
+
+
+@pytest.mark.parametrize("method", ["fossils", "spir"])
+@pytest.mark.parametrize("m,n,kappa,rnorm", [(20000, 200, 1e10, 1e-6), (4000, 50, 1e12, 1e-3), (30000, 300, 1e14, 1e-4),
+                                             (4000, 50, 1e2, 1.0)])
+def test_overlapped_svd_matches_serial(ctx, method, m, n, kappa, rnorm):
+    """The SVD of R beside the first refinement step (P = R^{-1} there, iterates recorded and cut
+    back once the first-step threshold is known) reproduces the serial order: the same first-step
+    iteration count up to the rounding of the two preconditioners, the same statistics, the bar."""
+    P = make_problem(m, n, kappa, rnorm, seed=8)
+    st0, i0, x0 = _solve(ctx, P, method, overlap_svd=0)
+    st1, i1, x1 = _solve(ctx, P, method, overlap_svd=1)
+    assert st0 in (0, 2) and st1 in (0, 2)
+    for x in (x0, x1):
+        assert be.relative_backward_error(P.A, P.b, x, P.sigma, P.V) <= 1e-14
+    assert abs(i0.iters[0] - i1.iters[0]) <= 1, (i0.to_dict(), i1.to_dict())
+    assert abs(i0.iters[1] - i1.iters[1]) <= 5
+    # (two sketches: their atomic sums round differently, so condest agrees to about condest u)
+    assert abs(i1.condest - i0.condest) <= (1e-9 + 1e3 * i0.condest * U) * i0.condest
+    xq = hh.qr_lstsq(P.A, P.b)
+    assert np.linalg.norm(x1 - x0) / np.linalg.norm(P.x_true) <= 10 * _fe_ref(P, xq)
+
+
+def test_overlapped_svd_rank_deficient_restart(ctx):
+    """A numerically rank-deficient A (repeated columns): the overlapped first step is discarded
+    once the SVD reports condest beyond 1/(30 u), and the solve restarts with the truncated
+    preconditioner, as in the serial order."""
+    rng = np.random.default_rng(3)
+    B = rng.standard_normal((3000, 20))
+    A = np.column_stack([B, B[:, :5]])
+    b = rng.standard_normal(3000)
+    import torch
+    from paper_2406_03468_amd import binding
+    res = []
+    for ov in (0, 1):
+        o = binding.fs_options_default(3000, 25)
+        o.overlap_svd = ov
+        x = torch.zeros(25, dtype=torch.float64, device="cuda")
+        st, info = binding.fossils_solve(ctx, dev_colmajor(A), dev_vec(b), x, o)
+        assert st == binding.FS_WARN_RANK_DEFICIENT and info.flags & 1 and info.rank == 20, info.to_dict()
+        res.append(host(x))
+    r0, r1 = (b - A @ res[0]), (b - A @ res[1])
+    assert np.linalg.norm(A.T @ r1) <= 1e-10 * np.linalg.norm(A) * np.linalg.norm(b)
+    assert abs(np.linalg.norm(r1) - np.linalg.norm(r0)) <= 1e-12 * np.linalg.norm(b)
