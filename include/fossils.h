@@ -240,7 +240,8 @@ typedef struct {
  * passes of different solves overlap on the GPU; the cooperative QR/SVD kernels of different slots
  * are serialized (a cooperative grid must be fully resident).  hbm_budget bounds the workspace:
  * each slot may use hbm_budget / max_slots bytes, and a request whose workspace footprint exceeds
- * that share is refused at submission with FS_ERR_TOO_LARGE. */
+ * that share is refused at submission with FS_ERR_TOO_LARGE.  With more than one slot the solves
+ * run in the serial order (opts->overlap_svd is treated as 0): the slots already share the GPU. */
 fs_status fs_server_create(fs_context ctx, size_t hbm_budget, int32_t max_slots, fs_server* out);
 /* Finishes every queued request, then frees the slots. */
 fs_status fs_server_destroy(fs_server srv);
