@@ -692,12 +692,19 @@ int* fs_svd_err_word(void* work, int n) {
   return (int*)(norms + n) + 66;
 }
 
-int fs_svd_grid_size(int n, int num_cu, bool with_u) {
+// Work-groups of the block (systolic) variant, or 0 when it does not apply: U_R wanted, columns too
+// long for two blocks in LDS, or more block pairs than compute units (n above ~2170).
+static int svd_block_grid(int n, int num_cu, bool with_u) {
   const int bw = svd_block_width(n);
-  if (!with_u && bw > 0) {
-    const int nblk = (n + bw - 1) / bw;
-    return (nblk + (nblk & 1)) / 2;
-  }
+  if (with_u || bw <= 0) return 0;
+  const int nblk = (n + bw - 1) / bw;
+  const int P = (nblk + (nblk & 1)) / 2;
+  return (P <= num_cu) ? P : 0;
+}
+
+int fs_svd_grid_size(int n, int num_cu, bool with_u) {
+  const int Pb = svd_block_grid(n, num_cu, with_u);
+  if (Pb > 0) return Pb;
   const int G = (n + 1) / 2;
   return G < num_cu ? (G < 1 ? 1 : G) : num_cu;
 }
@@ -738,12 +745,11 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
   double tol = (double)(n > 1 ? n : 1) * 2.220446049250313e-16;
   double* Uarg = Uout ? Uacc : nullptr;
   const int bw = svd_block_width(n);
-  if (!Uout && bw > 0) {
+  if (svd_block_grid(n, num_cu, Uout != nullptr) > 0) {
     // systolic block Jacobi (no accumulation of U_R)
     const int nblk = (n + bw - 1) / bw;
     const int NBLK = nblk + (nblk & 1);
     const int P = NBLK / 2;
-    if (P > num_cu) return hipErrorInvalidValue;
     // after the counters, 16-byte aligned (the workspace has 1 KB of slack)
     double* mbox = (double*)(((uintptr_t)(norms + n + SVD_CTR_DOUBLES) + 15) & ~(uintptr_t)15);
     unsigned* flg = (unsigned*)(mbox + (size_t)P * 4 * bw * n);

@@ -289,3 +289,36 @@ def test_overlapped_svd_rank_deficient_restart(ctx):
     r0, r1 = (b - A @ res[0]), (b - A @ res[1])
     assert np.linalg.norm(A.T @ r1) <= 1e-10 * np.linalg.norm(A) * np.linalg.norm(b)
     assert abs(np.linalg.norm(r1) - np.linalg.norm(r0)) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("d_factor,zeta", [(2, 1), (3, 3), (20, 16), (12, 64)])
+def test_embedding_parameters(ctx, d_factor, zeta):
+    """Other sketch sizes and sparsities than Alg 4's (d = 12 n, zeta = 8): the non-packed index path
+    (zeta != 8), zeta = 1, the largest zeta, and d = 2 n (the paper's small-d LSQR remark). The bar
+    holds, and the iteration counts follow the oracle run with the same d, zeta and seed."""
+    m, n = 6000, 60
+    P = make_problem(m, n, 1e8, 1e-6, seed=12)
+    for method in ("fossils", "spir"):
+        status, info, x = _solve(ctx, P, method, d=d_factor * n, zeta=zeta)
+        assert status in (0, 2), info.to_dict()
+        assert be.relative_backward_error(P.A, P.b, x, P.sigma, P.V) <= 1e-14
+        ref = solvers.solve(P.A, P.b, method, solvers.Options(d=d_factor * n, zeta=zeta, precond="svd"))
+        assert abs(info.iters[0] - ref.iters[0]) <= 3, (info.to_dict(), ref.iters)
+
+
+def test_square_and_wide_sketch(ctx):
+    """m = n (a square system; the sketch has more rows than A) and d > m."""
+    P = make_problem(400, 400, 1e6, 0.0, seed=4)
+    for method in ("fossils", "spir"):
+        status, info, x = _solve(ctx, P, method)
+        assert status in (0, 2), info.to_dict()
+        assert be.relative_backward_error(P.A, P.b, x, P.sigma, P.V) <= 1e-14
+
+
+def test_wide_n_loop_jacobi(ctx):
+    """n = 2100: two LDS blocks hold only 4 columns each, giving more block pairs than compute units, so
+    the SVD of R takes the pairwise cooperative variant (the block variant refused such n before)."""
+    P = make_problem(30000, 2100, 1e6, 1e-4, seed=5)
+    status, info, x = _solve(ctx, P, "fossils")
+    assert status == 0, info.to_dict()
+    assert be.relative_backward_error(P.A, P.b, x, P.sigma, P.V) <= 1e-14
