@@ -29,7 +29,7 @@ constexpr int LOG2NB = 5;
 constexpr int NRG = QR_NT / NB;   // row groups
 
 __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64_t ldy, int d, int k, int RB,
-                                                   double* __restrict__ part,   // [2][G][2*NB]
+                                                   double* __restrict__ part,   // [2][G][NB] partial dots, then [2][NB] row j
                                                    double* __restrict__ wpart,  // [G][NB][k]
                                                    double* __restrict__ wred,   // [NB][k]
                                                    GridBarrier bar) {
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
   __shared__ double sred[QR_NT / 64][NB];
   __shared__ double sdots[NB], srow[NB], sw[NB], svtv[NB], srdiag[NB];
   __shared__ double sW[NRG][NB + 1];
-  __shared__ double sred4[QR_NT / 64][2 * NB + 1];
+  __shared__ double swt[NB];
   __shared__ signed char sneg[RBMAX];
 
   for (int r = tid; r < RBMAX; r += QR_NT) sneg[r] = 0;
@@ -77,39 +77,42 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
       s = wave_sum_high<LOG2NB>(s);
       if ((tid & 63) < NB) sred[tid >> 6][c] = s;
       __syncthreads();
+      // partial dots [par][G][NB]; row j (one owner) in its own slot [par][NB] after them
+      const size_t prow = (size_t)2 * G * NB;
       if (tid < NB) {
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < QR_NT / 64; ++w) t += sred[w][tid];
-        const size_t pp = ((size_t)par * G + g) * (2 * NB);
-        st_cob(rpart, 8 * (pp + tid), t);
-        st_cob(rpart, 8 * (pp + NB + tid), (j >= rs && j < re && tid < nbp) ? pan[j - rs][tid] : 0.0);
+        st_cob(rpart, 8 * (((size_t)par * G + g) * NB + tid), t);
+        if (j >= rs && j < re) st_cob(rpart, 8 * (prow + (size_t)par * NB + tid), (tid < nbp) ? pan[j - rs][tid] : 0.0);
       }
       grid_barrier_co(bar, (unsigned)G, bgen);
-      // (2) every work-group reduces all partials in the same order: entry e = tid % 64, four
-      //     groups of work-groups per entry (independent loads in flight), then a fixed-order sum.
+      // (2) every work-group reduces all partial dots in the same order: entry e = tid % NB, eight
+      //     groups of work-groups per entry (independent loads in flight), then a fixed-order sum;
+      //     the owner's row j is read directly.
       {
-        const int e = tid & 63, grp = tid >> 6;
+        const int e = tid % NB, grp = tid / NB;
         // batches of 16 independent loads in flight (offsets past G read 0 through the range check)
         double t = 0.0;
-        for (int g0 = grp; g0 < G; g0 += 16 * (QR_NT / 64)) {
+        for (int g0 = grp; g0 < G; g0 += 16 * NRG) {
           double vals[16];
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
-            const int gg = g0 + q * (QR_NT / 64);
-            vals[q] = ld_cob(rpart, gg < G ? 8 * (((size_t)par * G + gg) * (2 * NB) + e) : (size_t)0xFFFFFFF0u);
+            const int gg = g0 + q * NRG;
+            vals[q] = ld_cob(rpart, gg < G ? 8 * (((size_t)par * G + gg) * NB + e) : (size_t)0xFFFFFFF0u);
           }
 #pragma unroll
           for (int q = 0; q < 16; ++q) t += vals[q];
         }
-        sred4[grp][e] = t;
+        sW[grp][e] = t;
+        const double rowv = (tid < NB) ? ld_cob(rpart, 8 * (prow + (size_t)par * NB + tid)) : 0.0;
         __syncthreads();
-        if (tid < 2 * NB) {
+        if (tid < NB) {
           double t2 = 0.0;
 #pragma unroll
-          for (int q = 0; q < QR_NT / 64; ++q) t2 += sred4[q][tid];
-          if (tid < NB) sdots[tid] = t2;
-          else srow[tid - NB] = t2;
+          for (int q = 0; q < NRG; ++q) t2 += sW[q][tid];
+          sdots[tid] = t2;
+          srow[tid] = rowv;
         }
       }
       __syncthreads();
@@ -213,12 +216,12 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
           double w = 0.0;
 #pragma unroll
           for (int q = 0; q < NRG; ++q) w += sW[q][tid];
-          sred4[0][tid] = w;
+          swt[tid] = w;
         }
         __syncthreads();
         if (tid < nbp) {
           double wp = 0.0;
-          for (int c2 = 0; c2 <= tid; ++c2) wp = fma(T[c2][tid], sred4[0][c2], wp);
+          for (int c2 = 0; c2 <= tid; ++c2) wp = fma(T[c2][tid], swt[c2], wp);
           st_cob(rwred, 8 * ((size_t)tid * k + cc), wp);
         }
         __syncthreads();
