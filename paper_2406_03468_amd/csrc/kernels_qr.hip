@@ -12,7 +12,8 @@
 //     fixed order, so all copies agree bit for bit;
 //   * the trailing columns are updated as Y <- Y - V T^T (V^T Y): V^T Y is summed over row blocks
 //     (per-work-group partials, then a column-distributed fixed-order reduction), then each
-//     work-group updates its own rows.
+//     work-group updates its own rows; both products run on the FP64 matrix cores
+//     (v_mfma_f64_16x16x4f64).
 // Y is only ever touched by the work-group owning the rows; the partials exchanged between
 // work-groups go through coherent stores/loads, so the grid barriers need no cache flushes.
 // R is left in the upper triangle of Y[0:k, 0:k] with a non-negative diagonal (rows of R whose
@@ -23,14 +24,15 @@
 namespace {
 
 constexpr int NB = 32;        // panel width (divides 64)
-constexpr int QR_NT = 256;    // threads per work-group
+constexpr int QR_NT = 512;    // threads per work-group (two waves per SIMD: one work-group per CU by LDS)
 constexpr int RBMAX = 256;    // max rows owned by one work-group
 constexpr int LOG2NB = 5;
 constexpr int NRG = QR_NT / NB;   // row groups
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64_t ldy, int d, int k, int RB,
                                                    double* __restrict__ part,   // [2][G][NB] partial dots, then [2][NB] row j
-                                                   double* __restrict__ wpart,  // [G][NB][k]
+                                                   double* __restrict__ wpart,  // [k][G][NB]
                                                    double* __restrict__ wred,   // [NB][k]
                                                    GridBarrier bar) {
   unsigned bgen = 0;
@@ -40,7 +42,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
   const int nr = (re > rs) ? re - rs : 0;
 
   __shared__ double pan[RBMAX][NB + 1];
-  __shared__ __align__(16) double vm[RBMAX][NB];  // the panel's V, zeros written out (row reads broadcast)
+  __shared__ double vm[RBMAX][NB + 1];  // the panel's V, zeros written out (rows past nr stay zero)
   __shared__ double T[NB][NB + 1];
   __shared__ double sred[QR_NT / 64][NB];
   __shared__ double sdots[NB], srow[NB], sw[NB], svtv[NB], srdiag[NB];
@@ -49,6 +51,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
   __shared__ signed char sneg[RBMAX];
 
   for (int r = tid; r < RBMAX; r += QR_NT) sneg[r] = 0;
+  for (int i = tid; i < RBMAX * (NB + 1); i += QR_NT) (&vm[0][0])[i] = 0.0;
   // coherent views of the exchange buffers (bulk SC1 loads/stores)
   const auto rpart = co_rsrc(part, sizeof(double) * (size_t)2 * G * 2 * NB);
   const auto rwpart = co_rsrc(wpart, sizeof(double) * (size_t)G * NB * k);
@@ -56,6 +59,9 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
 
   const int c = tid % NB;
   const int rg = tid / NB;
+  // MFMA lane roles (v_mfma_f64_16x16x4f64: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+  // holds D[4i + l/16][l%16], i = 0..3)
+  const int wid = tid >> 6, lj = tid & 15, lk = (tid & 63) >> 4;
 
   for (int k0 = 0; k0 < k; k0 += NB) {
     const int nbp = (k - k0 < NB) ? k - k0 : NB;
@@ -169,29 +175,38 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         vm[r][q] = (q <= rs + r - k0 && q < nbp) ? pan[r][q] : 0.0;
       }
       __syncthreads();
-      // (T1) partial W_g = V_own^T Y_own[:, k1:k]
-      for (int cc = tid; cc < ntr; cc += QR_NT) {
-        double acc[NB];
+      // (T1) partial W_g = V_own^T Y_own[:, k1:k] on the matrix cores, as its transpose
+      //      Y_own[:, k1:k]^T V_own: one 16 x 16 tile (16 trailing columns, 16 entries q) per wave at
+      //      a time, rows in chunks of 64 where the k-slot l/16 of step s takes row 16 (l/16) + s
+      //      (each lane reads 16 consecutive rows of its column); rows below r_lo or past nr carry
+      //      zero V.  Partials are stored column by column, [cc][g][q], so that each column's G x NB
+      //      partials are contiguous for the reduction.
+      const int nct = (ntr + 15) / 16;
+      const int c_lo = (r_lo / 64) * 64;
+      for (int t = wid; t < 2 * nct; t += QR_NT / 64) {
+        const int qt = (t & 1) * 16, ct = (t >> 1) * 16, cc = ct + lj;
+        const bool cin = cc < ntr;
+        const double* ycol = Y + (int64_t)(k1 + (cin ? cc : 0)) * ldy + rs;
+        v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};  // two chains (even, odd steps)
+        for (int c0 = c_lo; c0 < nr; c0 += 64) {
+          double bv[16];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) acc[q] = 0.0;
-        const double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
-        int r = r_lo;
-        for (; r + 8 <= nr; r += 8) {  // eight rows' loads in flight before their FMAs
-          double y[8];
+          for (int u = 0; u < 16; ++u) {
+            const int row = c0 + 16 * lk + u;
+            bv[u] = (cin && row < nr) ? ycol[row] : 0.0;
+          }
 #pragma unroll
-          for (int u = 0; u < 8; ++u) y[u] = ycol[r + u];
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int q = 0; q < NB; ++q) acc[q] = fma(vm[r + u][q], y[u], acc[q]);
+          for (int u = 0; u < 16; u += 2) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u], vm[c0 + 16 * lk + u][qt + lj], acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[u + 1], vm[c0 + 16 * lk + u + 1][qt + lj], acc2, 0, 0, 0);
+          }
         }
-        for (; r < nr; ++r) {
-          const double y = ycol[r];
+        acc += acc2;
 #pragma unroll
-          for (int q = 0; q < NB; ++q) acc[q] = fma(vm[r][q], y, acc[q]);
+        for (int i = 0; i < 4; ++i) {
+          const int cs = ct + 4 * i + lk;
+          if (cs < ntr) st_cob(rwpart, 8 * (((size_t)cs * G + g) * NB + qt + lj), acc[i]);
         }
-#pragma unroll
-        for (int q = 0; q < NB; ++q) st_cob(rwpart, 8 * (((size_t)g * NB + q) * k + cc), acc[q]);
       }
       grid_barrier_co(bar, (unsigned)G, bgen);
       // (T2) W = sum_g W_g (fixed order), W' = T^T W, for a slice of columns per work-group: thread
@@ -204,7 +219,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               const int gg = g0 + q * NRG;
-              vals[q] = ld_cob(rwpart, gg < G ? 8 * (((size_t)gg * NB + c) * k + cc) : (size_t)0xFFFFFFF0u);
+              vals[q] = ld_cob(rwpart, gg < G ? 8 * (((size_t)cc * G + gg) * NB + c) : (size_t)0xFFFFFFF0u);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) wsum += vals[q];
@@ -227,36 +242,48 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
         __syncthreads();
       }
       grid_barrier_co(bar, (unsigned)G, bgen);
-      // (T3) own rows: Y[:, k1:k] -= V W'
-      for (int cc = tid; cc < ntr; cc += QR_NT) {
-        double wv[NB];
+      // (T3) own rows: Y[:, k1:k] -= V W' on the matrix cores, as (W'^T V^T)^T: per wave a tile of
+      //      16 trailing columns (W' loaded once) against every 16-row tile from r_lo; each of the
+      //      four results is 16 consecutive rows of one column across 16 lanes.
+      for (int t = wid; t < nct; t += QR_NT / 64) {
+        const int ct = t * 16;
+        double av[NB / 4];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) wv[q] = (q < nbp) ? ld_cob(rwred, 8 * ((size_t)q * k + cc)) : 0.0;
-        double* ycol = Y + (int64_t)(k1 + cc) * ldy + rs;
-        int r = r_lo;
-        for (; r + 4 <= nr; r += 4) {  // four rows' independent sums (each in the same q order)
-          double y[4], s2[4];
+        for (int u = 0; u < NB / 4; ++u) {
+          const int q = 4 * u + lk, cc = ct + lj;
+          av[u] = (q < nbp && cc < ntr) ? ld_cob(rwred, 8 * ((size_t)q * k + cc)) : 0.0;
+        }
+        // two row tiles at a time: their Y loads are in flight during the products
+        for (int rt = (r_lo / 16) * 16; rt < nr; rt += 32) {
+          double yv[2][4];
+          bool ok[2][4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            y[u] = ycol[r + u];
-            s2[u] = 0.0;
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = rt + 16 * h + lj, cc = ct + 4 * i + lk;
+              ok[h][i] = row >= r_lo && row < nr && cc < ntr;
+              yv[h][i] = ok[h][i] ? Y[(int64_t)(k1 + cc) * ldy + rs + row] : 0.0;
+            }
+          const int r2 = (rt + 16 + lj < RBMAX) ? rt + 16 + lj : RBMAX - 1;  // past nr: unused
+          v4d acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int u = 0; u < NB / 4; ++u) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], vm[rt + lj][4 * u + lk], acc, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], vm[r2][4 * u + lk], acc2, 0, 0, 0);
           }
 #pragma unroll
-          for (int q = 0; q < NB; ++q)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) s2[u] = fma(vm[r + u][q], wv[q], s2[u]);
-#pragma unroll
-          for (int u = 0; u < 4; ++u) ycol[r + u] = y[u] - s2[u];
-        }
-        for (; r < nr; ++r) {
-          double s2 = 0.0;
-#pragma unroll
-          for (int q = 0; q < NB; ++q) s2 = fma(vm[r][q], wv[q], s2);
-          ycol[r] -= s2;
+          for (int i = 0; i < 4; ++i) {
+            const int cc = ct + 4 * i + lk;
+            if (ok[0][i]) Y[(int64_t)(k1 + cc) * ldy + rs + rt + lj] = yv[0][i] - acc[i];
+            if (ok[1][i]) Y[(int64_t)(k1 + cc) * ldy + rs + rt + 16 + lj] = yv[1][i] - acc2[i];
+          }
         }
       }
     }
-    // diagonal of R for this panel's rows owned here
+    // diagonal of R for this panel's rows owned here (after every thread's write-back of the panel:
+    // without a trailing update, nothing else orders the two stores to the diagonal)
+    __syncthreads();
     for (int jj = tid; jj < nbp; jj += QR_NT) {
       const int j = k0 + jj;
       if (j >= rs && j < re) Y[(int64_t)j * ldy + j] = srdiag[jj];

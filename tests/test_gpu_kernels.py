@@ -84,8 +84,9 @@ def test_sketch_apply_matches_oracle(ctx, m, n, d, scale):
 
 
 # ---------------------------------------------------------------- QR of the sketch
-@pytest.mark.parametrize("d,k", [(600, 51), (3600, 301), (1000, 33), (64, 64), (130, 1)])
+@pytest.mark.parametrize("d,k", [(600, 51), (3600, 301), (1000, 33), (64, 64), (130, 1), (128, 64), (4096, 96)])
 def test_qr_matches_householder_oracle(ctx, d, k):
+    """(k a multiple of the 32-column panel: the last panel has no trailing update.)"""
     from paper_2406_03468_amd import binding
     rng = np.random.default_rng(d * 7 + k)
     Y0 = rng.standard_normal((d, k))
