@@ -28,6 +28,8 @@ constexpr int QR_NT = 512;    // threads per work-group (two waves per SIMD: one
 constexpr int RBMAX = 256;    // max rows owned by one work-group
 constexpr int LOG2NB = 5;
 constexpr int NRG = QR_NT / NB;   // row groups
+constexpr int LOG2NRG = 4;
+static_assert(NRG == 1 << LOG2NRG && NRG <= 64, "a row group's lanes lie in one wave");
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64_t ldy, int d, int k, int RB,
@@ -135,14 +137,13 @@ __global__ __launch_bounds__(QR_NT) void k_qr_coop(double* __restrict__ Y, int64
       }
       if (tid == 0) srdiag[jj] = -sg * alpha;
       __syncthreads();
-      if (tid <= jj) {  // column jj of T
-        if (tid == jj) {
-          T[jj][jj] = tau;
-        } else {
-          double t = 0.0;
-          for (int c2 = tid; c2 < jj; ++c2) t = fma(T[tid][c2], svtv[c2], t);
-          T[tid][jj] = -tau * t;
-        }
+      {  // column jj of T: entry i < jj is -tau T[i][i:jj] svtv[i:jj], summed by the NRG lanes of row i
+        const int i = tid / NRG, l = tid % NRG;
+        double t = 0.0;
+        if (i < jj)
+          for (int c2 = i + l; c2 < jj; c2 += NRG) t = fma(T[i][c2], svtv[c2], t);
+        t = wave_sum_low<LOG2NRG>(t);
+        if (l == 0 && i <= jj) T[i][jj] = (i == jj) ? tau : -tau * t;
       }
       // (4) apply the reflector to the rest of the panel (own rows i >= j).
       if (c > jj && c < nbp) {
