@@ -62,9 +62,12 @@ def test_c1_backward_stable_vs_oracle(ctx, kappa, rnorm, method, precond):
     P = make_problem(4000, 50, kappa, rnorm, seed=0)
     status, info, x = _solve(ctx, P, method, precond=precond)
     ref = solvers.solve(P.A, P.b, method, solvers.Options(precond="qr" if precond == 0 else "svd"))
-    # the second-step KW noise floor (kappa = 1e12, ||r|| = kappa u) may leave a step at the cap
-    # with a backward-stable iterate: accepted there (status NOT_CONVERGED), the BE bar still holds
-    floor = kappa >= 1e12 and method == "spir_lsqr"
+    # SPIR's second-step KW estimate settles around ||A||_F u at kappa >= 1e12: the rule fires at a
+    # check that depends on the sketch's rounding, or not before the cap (the oracle's SPIR on this
+    # problem with P = R^{-1}: 11 iterations on 26 of 30 sketch seeds, 16, 26 and the cap on the
+    # rest).  There a step at the cap is accepted (status NOT_CONVERGED), the count is not compared,
+    # and the BE bar still holds.
+    floor = kappa >= 1e12 and method in ("spir", "spir_lsqr")
     assert status == 0 or (floor and status == 2), (status, info.to_dict())
     xq = hh.qr_lstsq(P.A, P.b)
     bg = be.relative_backward_error(P.A, P.b, x, P.sigma, P.V)
@@ -74,7 +77,7 @@ def test_c1_backward_stable_vs_oracle(ctx, kappa, rnorm, method, precond):
     # the GPU and oracle iterates agree to the forward-error scale
     assert np.linalg.norm(x - ref.x) / np.linalg.norm(P.x_true) <= 10 * _fe_ref(P, xq, ref.x)
     assert abs(info.iters[0] - ref.iters[0]) <= 3
-    if not (floor and (status == 2 or ref.flags & 2)):
+    if not floor:
         assert abs(info.iters[1] - ref.iters[1]) <= 5
     # sketch statistics agree with the oracle's (same sketch bits; the sketches differ by summation
     # order, so sigma_min, hence condest, agrees only to about condest * u relative)
