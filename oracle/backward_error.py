@@ -112,3 +112,35 @@ def relative_backward_error(A, b, x, sigma=None, V=None):
     if sigma is not None:
         return kw_known_svd(A, b, x, sigma, V, theta) / fro
     return kw_estimate(A, b, x, theta) / fro
+
+
+# ---------------------------------------------------------------- complex problems
+# The same estimate over C (Section 4.1's formula with conjugate transposes):
+#   KW_theta(x) = theta / sqrt(1 + theta^2 ||x||^2) * || (A^H A + lambda I)^{-1/2} A^H r ||,
+# evaluated from an SVD A = U diag(sigma) V^H as ||diag((sigma^2 + lambda)^{-1/2}) V^H A^H r||.
+
+
+def kw_complex(A, b, x, theta, sigma=None, V=None):
+    """Complex KW; g = A^H r and ||r|| accumulated in extended precision (numpy clongdouble)."""
+    xl = np.asarray(x, dtype=np.clongdouble)
+    g = np.zeros(A.shape[1], dtype=np.clongdouble)
+    rr = np.longdouble(0.0)
+    for i0 in range(0, A.shape[0], 8192):
+        Al = np.asarray(A[i0:i0 + 8192], dtype=np.clongdouble)
+        r = np.asarray(b[i0:i0 + 8192], dtype=np.clongdouble) - Al @ xl
+        g += Al.conj().T @ r
+        rr += np.sum(np.abs(r) ** 2)
+    g = np.asarray(g, dtype=np.complex128)
+    if sigma is None:
+        _, sigma, Vh = np.linalg.svd(A, full_matrices=False)
+        V = Vh.conj().T
+    lam, pref = _lambda(theta, float(np.sqrt(rr)), np.linalg.norm(x))
+    w = V.conj().T @ g
+    return pref * np.sqrt(np.sum(np.abs(w) ** 2 / (sigma**2 + lam)))
+
+
+def relative_backward_error_complex(A, b, x, sigma=None, V=None):
+    """KW_theta(x) / ||A||_F with theta = ||A||_F / ||b|| for complex A, b, x."""
+    fro = np.linalg.norm(A)
+    theta = fro / np.linalg.norm(b)
+    return kw_complex(A, b, x, theta, sigma, V) / fro

@@ -99,3 +99,70 @@ def qr_lstsq_lapack(A: np.ndarray, b: np.ndarray) -> np.ndarray:
 
     Q, R = sl.qr(A, mode="economic")
     return sl.solve_triangular(R, Q.T @ b, lower=False)
+
+
+# ---------------------------------------------------------------- complex least squares
+# The Prony problems of Section 5.2 are complex.  Textbook complex Householder QR: for x = A[k:, k]
+# the reflector H = I - 2 v v^H / (v^H v) with v = x + e^{i arg x_0} ||x|| e_1 (e^{i arg 0} = 1)
+# maps x to -e^{i arg x_0} ||x|| e_1; H is Hermitian and unitary.  Rows of R are multiplied by a
+# unit-modulus phase so that diag(R) is real and non-negative.
+
+
+def householder_qr_complex(M: np.ndarray):
+    """Return ((reflectors, phases), R) for complex M (m x k, m >= k); diag(R) >= 0 real."""
+    A = np.array(M, dtype=np.complex128, order="F", copy=True)
+    m, k = A.shape
+    if m < k:
+        raise ValueError("householder_qr_complex expects m >= k")
+    refl = []
+    for j in range(k):
+        x = A[j:, j]
+        alpha = np.linalg.norm(x)
+        if alpha == 0.0:
+            refl.append((j, None))
+            continue
+        ph = x[0] / abs(x[0]) if x[0] != 0 else 1.0 + 0.0j
+        v = x.copy()
+        v[0] += ph * alpha
+        vv = float(np.real(np.vdot(v, v)))
+        if j + 1 < k:
+            w = v.conj() @ A[j:, j + 1:]
+            A[j:, j + 1:] -= np.multiply.outer(v * (2.0 / vv), w)
+        A[j, j] = -ph * alpha
+        A[j + 1:, j] = 0.0
+        refl.append((j, (v, vv)))
+    R = np.triu(A[:k, :k])
+    d = np.diag(R)
+    rph = np.where(d == 0, 1.0 + 0.0j, d / np.where(d == 0, 1.0, np.abs(d)))
+    R = R * rph.conj()[:, None]
+    R[np.diag_indices(k)] = np.abs(d)  # exactly real (the product above rounds its imaginary part)
+    return (refl, rph), R
+
+
+def apply_qh_complex(Qinfo, y: np.ndarray) -> np.ndarray:
+    """Q^H y for the factorization of householder_qr_complex (first k entries carry the phases)."""
+    refl, rph = Qinfo
+    z = np.array(y, dtype=np.complex128, copy=True)
+    for j, rv in refl:
+        if rv is None:
+            continue
+        v, vv = rv
+        z[j:] -= v * (2.0 * np.vdot(v, z[j:]) / vv)
+    z[: len(rph)] *= rph.conj()
+    return z
+
+
+def back_substitution_complex(R: np.ndarray, y: np.ndarray) -> np.ndarray:
+    n = R.shape[0]
+    x = np.zeros(n, dtype=np.complex128)
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - R[i, i + 1:] @ x[i + 1:]) / R[i, i]
+    return x
+
+
+def qr_lstsq_complex(A: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """x = argmin ||b - A x|| over C^n by complex Householder QR: R x = (Q^H b)[:n]."""
+    m, n = A.shape
+    Qinfo, R = householder_qr_complex(A)
+    c = apply_qh_complex(Qinfo, b)
+    return back_substitution_complex(R, c[:n])

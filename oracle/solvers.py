@@ -423,3 +423,23 @@ def sketch_and_solve(A, b, d, zeta=8, seed=12345):
     Y = sketch_Ab(A, b, d, zeta, seed)
     _, Rfull = householder_qr(Y)
     return back_substitution(Rfull[:n, :n], Rfull[:n, n])
+
+
+# ---------------------------------------------------------------- complex problems (Section 5.2)
+
+def realify(A, b):
+    """A_R = [Re A, -Im A; Im A, Re A], b_R = [Re b; Im b]: ||A_R [Re x; Im x] - b_R|| = ||A x - b||."""
+    Ar = np.block([[A.real, -A.imag], [A.imag, A.real]])
+    return np.asfortranarray(Ar), np.concatenate([b.real, b.imag])
+
+
+def solve_complex(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
+    """FOSSILS / SPIR for complex A, b: the real method on the realification, x = x_R[:n] + i x_R[n:]
+    (the sketch has 12 (2n) rows by default)."""
+    n = A.shape[1]
+    Ar, br = realify(A, b)
+    res = solve(Ar, br, method, opts)
+    res.x = res.x[:n] + 1j * res.x[n:]
+    res.x0 = res.x0[:n] + 1j * res.x0[n:]
+    res.xs = [v[:n] + 1j * v[n:] for v in res.xs]
+    return res

@@ -18,4 +18,8 @@ from .problems import (  # noqa: F401
     make_problem_torch,
     log_spaced_sigma,
     haar_cholqr2,
+    ComplexProblem,
+    make_complex_problem,
+    make_prony_problem,
+    prony_samples,
 )

@@ -185,3 +185,88 @@ def make_problem_torch(m: int, n: int, kappa: float, resid_norm: float, seed: in
     A = At.T  # (m, n) view with strides (1, m)
     return Problem(A=A, b=b, x_true=x_true, sigma=sigma, V=V, kappa=float(kappa),
                    resid_norm=float(resid_norm), seed=int(seed), U=None, meta=meta)
+
+
+# ---------------------------------------------------------------- complex-valued problems
+#
+# Section 5.2's second dense workload is complex (Prony's method, Appendix B).  Two generators:
+#   * make_complex_problem: the Figure 1 recipe over C (complex Haar U, V from the QR of complex
+#     Gaussian matrices with a positive real diag(R); A = U diag(sigma) V^H; x_true and r_perp
+#     complex Gaussian, r_perp in the orthogonal complement of range(A));
+#   * make_prony_problem: the first least-squares solve of Prony's method (Appendix B, line 1 of
+#     its algorithm): samples f_j = sum_k mu_k z_k^j + eps_j, j = 0 .. m+n-1, the Toeplitz
+#     A = (f_{n-1+i-j}) (1 <= i <= m, 1 <= j <= n) and b = (f_{n-1+i}).  The paper's samples come
+#     from a 16-site transverse-field Ising model on a quantum device; here they are synthesized
+#     with the same structure: K unit-modulus z_k = exp(-i dt lambda_k) for eigenvalues lambda_k
+#     drawn uniformly in [-1, 1], positive weights mu_k decaying like exp(-3 k / K) (a few
+#     dominant overlaps, normalized to sum 1) and complex Gaussian noise eps_j of standard
+#     deviation `noise` (1e-6 in the paper).  With K < n the noise-free system is consistent and
+#     rank deficient, so the noise sets condition number and residual: K = 10, n = 100,
+#     m = 20000 gives about 4e6 and 2e-6 (the paper reports about 1e6 and 1e-6).
+
+
+@dataclass
+class ComplexProblem:
+    A: np.ndarray                      # m x n complex128, column-major
+    b: np.ndarray                      # m complex128
+    x_true: Optional[np.ndarray]       # n (None for Prony problems)
+    sigma: Optional[np.ndarray]        # exact singular values when known
+    V: Optional[np.ndarray]            # n x n right singular vectors when known
+    kappa: float
+    meta: dict = field(default_factory=dict)
+
+
+def _complex_haar(rng: np.random.Generator, m: int, n: int) -> np.ndarray:
+    import scipy.linalg as sl
+
+    G = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    Q, R = sl.qr(G, mode="economic")
+    d = np.diag(R)
+    ph = np.where(d == 0, 1.0, d / np.abs(d))
+    return np.asfortranarray(Q * ph)
+
+
+def make_complex_problem(m: int, n: int, kappa: float, resid_norm: float, seed: int) -> ComplexProblem:
+    if not (m >= n >= 1):
+        raise ValueError("need m >= n >= 1")
+    rng = np.random.default_rng(seed)
+    U = _complex_haar(rng, m, n)
+    V = _complex_haar(rng, n, n)
+    sigma = log_spaced_sigma(n, kappa)
+    A = np.asfortranarray((U * sigma) @ V.conj().T)
+    x_true = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    g = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    r = g - U @ (U.conj().T @ g)
+    r = r - U @ (U.conj().T @ r)
+    nr = np.linalg.norm(r)
+    r = r * (resid_norm / nr) if nr > 0 else r
+    b = A @ x_true + r
+    return ComplexProblem(A=A, b=b, x_true=x_true, sigma=sigma, V=V, kappa=float(kappa),
+                          meta={"resid_norm": float(resid_norm), "seed": int(seed), "U": U if m * n <= 4_000_000 else None})
+
+
+def prony_samples(count: int, K: int, noise: float, seed: int, dt: float = 1.0):
+    """f_j = sum_k mu_k z_k^j + eps_j for j < count; returns (f, z, mu)."""
+    rng = np.random.default_rng(seed)
+    lam = np.sort(rng.uniform(-1.0, 1.0, K))
+    z = np.exp(-1j * dt * lam)
+    mu = np.exp(-3.0 * np.arange(K) / K) * rng.uniform(0.5, 1.0, K)  # a few dominant overlaps
+    mu = mu / mu.sum()
+    j = np.arange(count)
+    f = np.zeros(count, dtype=np.complex128)
+    for k in range(K):  # z_k^j through the angle (exact unit modulus for every j)
+        f += mu[k] * np.exp(-1j * dt * lam[k] * j)
+    f += noise * (rng.standard_normal(count) + 1j * rng.standard_normal(count)) / np.sqrt(2.0)
+    return f, z, mu
+
+
+def make_prony_problem(m: int, n: int, K: int, noise: float = 1e-6, seed: int = 0, dt: float = 1.0) -> ComplexProblem:
+    if not (m >= n >= 1) or K < 1:
+        raise ValueError("need m >= n >= 1 and K >= 1")
+    f, z, mu = prony_samples(m + n, K, noise, seed, dt)
+    i = np.arange(1, m + 1)[:, None]
+    jj = np.arange(1, n + 1)[None, :]
+    A = np.asfortranarray(f[n - 1 + i - jj])
+    b = f[n - 1 + np.arange(1, m + 1)].copy()
+    return ComplexProblem(A=A, b=b, x_true=None, sigma=None, V=None, kappa=float("nan"),
+                          meta={"z": z, "mu": mu, "K": K, "noise": noise, "seed": seed, "dt": dt})
