@@ -138,6 +138,20 @@ fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int6
 fs_status spir_lsqr_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                           double* x, const fs_options* opts, fs_info* info);
 
+/* Complex least squares, min ||A x - b|| with A in C^{m x n} (m >= n), b in C^m: the Prony problems
+ * of Section 5.2 (Appendix B, the first least-squares solve of Prony's method).  A (lda >= m), b and
+ * x are complex128 column-major device arrays of interleaved (re, im) doubles, 16-byte aligned.
+ * Solved by FOSSILS on the realification A_R = [Re A, -Im A; Im A, Re A] (2m x 2n), b_R = [Re b;
+ * Im b], x = x_R[0:n] + i x_R[n:2n]: the map is an isometry of the residual and A_R has A's
+ * singular values, each twice, so the backward-error estimate and the stopping rules carry over.
+ * opts, if not NULL, describe the realified problem (fs_options_default(2m, 2n): d = 24 n); info
+ * reports the realified solve.  Workspace: the realified copy, 32 m n + 16 (m + n) bytes. */
+fs_status fossils_solve_complex(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                                double* x, const fs_options* opts, fs_info* info);
+/* The same with SPIR (conjugate gradient) as the inner solver. */
+fs_status spir_solve_complex(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                             double* x, const fs_options* opts, fs_info* info);
+
 /* FOSSILS for k (1..64) right-hand sides sharing A: column j of X (n x k, ldx >= n) solves the
  * least-squares problem with column j of B (m x k, ldb >= m), both column-major device arrays.
  * One sketch S [A B], one QR and one SVD serve every column (x_0 = R^{-1} t_j); the inner

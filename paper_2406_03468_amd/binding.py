@@ -98,6 +98,10 @@ _SIGS = [
                              ctypes.POINTER(FsInfo)]),
     ("spir_lsqr_solve", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
                                   ctypes.POINTER(FsInfo)]),
+    ("fossils_solve_complex", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
+                                        ctypes.POINTER(FsInfo)]),
+    ("spir_solve_complex", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
+                                     ctypes.POINTER(FsInfo)]),
     ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
     ("fossils_solve_mixed", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64, c_vp, c_vp,
@@ -234,6 +238,27 @@ def spir_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
 
 def spir_lsqr_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
     s, info = _solve(load().spir_lsqr_solve, ctx, A, b, x, opts)
+    _check(s)
+    return s, info
+
+
+def _complex_ld(M):
+    """Leading dimension (in complex elements) of a column-major complex128 matrix or vector."""
+    import torch
+    if M.dtype != torch.complex128:
+        raise ValueError("complex solves take complex128 tensors")
+    return _colmajor(M)
+
+
+def fossils_solve_complex(ctx: Context, A, b, x, opts: Optional[FsOptions] = None, method: str = "fossils"):
+    """Complex least squares (complex128 column-major A (m, n), b (m,), x (n,) on the device)."""
+    m, n = A.shape
+    fn = {"fossils": load().fossils_solve_complex, "spir": load().spir_solve_complex}[method]
+    for v in (b, x):
+        _complex_ld(v)
+    info = FsInfo()
+    s = fn(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_complex_ld(A)), c_vp(_ptr(b)), c_vp(_ptr(x)),
+           ctypes.byref(opts) if opts is not None else None, ctypes.byref(info))
     _check(s)
     return s, info
 

@@ -174,7 +174,7 @@ fs_status fs_context_destroy(fs_context c) {
   Workspace& w = c->ws;
   for (DevBuf* b : {&w.idx, &w.Y, &w.colnorm2, &w.dinv, &w.qrwork, &w.svdwork, &w.sigma, &w.V, &w.UR, &w.partial,
                     &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate, &w.lsqr,
-                    &w.hist})
+                    &w.hist, &w.cplx})
     free_buf(*b);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->aux_stream) {
@@ -909,6 +909,44 @@ fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int6
 fs_status spir_lsqr_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                           double* x, const fs_options* opts, fs_info* info) {
   return solve(ctx, M_SPIR_LSQR, m, n, A, lda, b, x, opts, info);
+}
+
+// Complex least squares (the Prony problems of Section 5.2): the real solver on the realification
+// (2m x 2n, same residual norms, each singular value twice), its solution mapped back.
+static fs_status solve_complex(fs_context ctx, Method method, int64_t m, int32_t n, const double* A, int64_t lda,
+                               const double* b, double* x, const fs_options* opts, fs_info* info) {
+  if (!ctx || !A || !b || !x) return FS_ERR_INVALID_ARG;
+  if (((uintptr_t)A | (uintptr_t)b | (uintptr_t)x) & 15) return FS_ERR_INVALID_ARG;  // complex128 alignment
+  if (n < 1 || m < n || lda < m || n > (1 << 29)) return FS_ERR_SHAPE;
+  const int64_t M2 = 2 * m;
+  const int32_t N2 = 2 * n;
+  fs_options o;
+  if (opts) o = *opts;
+  else FS_TRY(fs_options_default(M2, N2, &o));
+  FS_TRY(validate_options(M2, N2, o));
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));  // the realification buffer may be reallocated
+  Workspace& W = ctx->ws;
+  FS_TRY(grow(W.cplx, sizeof(double) * ((size_t)M2 * N2 + M2 + N2)));
+  double* Ar = (double*)W.cplx.p;
+  double* br = Ar + (size_t)M2 * N2;
+  double* xr = br + M2;
+  FS_K(fs_launch_realify(m, n, A, lda, b, Ar, br, ctx->stream));
+  const fs_status st = solve(ctx, method, M2, N2, Ar, M2, br, xr, &o, info);
+  if (st < 0) return st;
+  FS_K(fs_launch_complexify_x(n, xr, x, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return st;
+}
+
+fs_status fossils_solve_complex(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                                double* x, const fs_options* opts, fs_info* info) {
+  return solve_complex(ctx, M_FOSSILS, m, n, A, lda, b, x, opts, info);
+}
+
+fs_status spir_solve_complex(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                             double* x, const fs_options* opts, fs_info* info) {
+  return solve_complex(ctx, M_SPIR, m, n, A, lda, b, x, opts, info);
 }
 
 fs_status fossils_solve_mixed(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const float* A32,

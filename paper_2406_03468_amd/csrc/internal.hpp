@@ -48,6 +48,11 @@ hipError_t fs_launch_sketch_apply_fp32(const double* A, int64_t lda, const float
                                        bool scale_by_norm, bool write_bnorm, int lds_bytes, hipStream_t s);
 // A32 = fl32(A) (column-major, lda32 >= m).
 hipError_t fs_launch_to_fp32(const double* A, int64_t lda, int64_t m, int n, float* A32, int64_t lda32, hipStream_t s);
+// Realification of a complex least-squares problem (complex128 interleaved, column-major):
+// Ar = [Re A, -Im A; Im A, Re A] (2m x 2n, ld 2m), br = [Re b; Im b]; and x = xr[0:n] + i xr[n:2n].
+hipError_t fs_launch_realify(int64_t m, int n, const double* A, int64_t lda, const double* b, double* Ar, double* br,
+                             hipStream_t s);
+hipError_t fs_launch_complexify_x(int n, const double* xr, double* x, hipStream_t s);
 
 // ---------------------------------------------------------------- QR of the sketch
 // In-place Householder QR of the d x k matrix Y (ldy), d >= k.  On exit the upper triangle of
