@@ -17,7 +17,10 @@ Printed as one JSON line:
   cpu_baseline   the CPU oracle's heavy-ball iterations (oracle.solvers.polyak with the oracle's
                  normal_pass and substitutions, numpy float64) on the same 1e6 x 1000 matrix, in GB/s
                  of algorithmic bytes;
-  accuracy       relative backward error (Karlson-Walden, known SVD, long double) per problem.
+  accuracy       relative backward error (Karlson-Walden, known SVD, long double) per problem;
+  multi_rhs, mixed, prony, serving
+                 the 64-RHS solve, the mixed-precision form (C4), the complex Prony problem at
+                 5e5 x 1000 (Section 5.2), and the served stream (C5).
 """
 
 from __future__ import annotations
@@ -59,6 +62,7 @@ def parse():
                          "A^T(A z) at m=1e6, n=1000, --pass-repeats times; prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-precision line")
+    ap.add_argument("--no-prony", dest="prony", action="store_false", help="skip the complex (Prony) line")
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
     return ap.parse_args()
 
@@ -243,7 +247,7 @@ def mixed_bench(ctx, args, dev, P10):
         out.append(rec)
     del A32
     return {"cases": out, "workload": "C4: 1e6 x 1000, ||r_perp|| = 1e-4, kappa in {1e10, 1e14, 1e6}; the FP32 "
-                                      "sketch is kept while u32 condest <= 0.5, else redone in FP64"}
+                                      "sketch is kept while u32 condest <= 2, else redone in FP64"}
 
 
 def pass_only(args):
@@ -272,13 +276,72 @@ def pass_only(args):
     ctx.close()
 
 
+def prony_bench(ctx, args, dev):
+    """Complex least squares at the paper's Prony shape (Section 5.2, Appendix B): the first solve of
+    Prony's method, m = 5e5, n = 1000, Toeplitz A = (f_{n-1+i-j}), b = (f_{n-1+i}), f_j the sum of
+    K = 10 unit-modulus exponentials plus complex noise of standard deviation 1e-6 (synthetic stand-in
+    for the paper's TFIM samples).  fossils_solve_complex (FOSSILS on the 1e6 x 2000 realification,
+    built inside the timed region); best of two after a warm-up.  BE from the complex KW formula with
+    A's singular values and right vectors taken from the SVD of its R factor (GPU QR, CPU SVD)."""
+    import numpy as np
+    import torch
+
+    from paper_2406_03468_amd import binding
+    from synth import prony_samples
+
+    m, n, K = 500_000, 1000, 10
+    f_h, _, _ = prony_samples(m + n, K, 1e-6, seed=0)
+    f = torch.as_tensor(f_h).to(dev)
+    buf = torch.empty((n, m), dtype=torch.complex128, device=dev)  # column j = f[n-1-j : n-1-j+m]
+    for j in range(n):
+        buf[j] = f[n - 1 - j:n - 1 - j + m]
+    A = buf.t()
+    b = f[n:n + m].clone()
+    x = torch.zeros(n, dtype=torch.complex128, device=dev)
+    binding.fossils_solve_complex(ctx, A, b, x)  # warm-up
+    ts, info = [], None
+    for _ in range(2):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, info = binding.fossils_solve_complex(ctx, A, b, x)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    ms = 1e3 * min(ts)
+    rec = {"m": m, "n": n, "K": K, "noise": 1e-6, "ms_per_solve": round(ms, 2), "status": st,
+           "iters": list(info.iters), "condest": info.condest, "svd_sweeps": info.svd_sweeps,
+           "phase_ms": [round(p, 2) for p in info.phase_ms],
+           "passes": passes_of(info),
+           "workload": "first least-squares solve of Prony's method (Appendix B), complex 5e5 x 1000, "
+                       "solved as its 1e6 x 2000 realification (d = 24000)"}
+    if not args.no_check:
+        try:
+            R = torch.linalg.qr(A, mode="r")[1]
+            _, sig, Vh = np.linalg.svd(R.cpu().numpy())
+            r = b - A @ x
+            g = (A.conj().t() @ r).cpu().numpy()
+            fro = float(torch.linalg.norm(A))
+            theta = fro / float(torch.linalg.norm(b))
+            rn, xn = float(torch.linalg.norm(r)), float(torch.linalg.norm(x))
+            lam = theta**2 * rn**2 / (1 + theta**2 * xn**2)
+            w = Vh @ g
+            kw = theta / np.sqrt(1 + theta**2 * xn**2) * np.sqrt(np.sum(np.abs(w) ** 2 / (sig**2 + lam)))
+            rec["be"] = float(kw / fro)
+            rec["rel_resid"] = rn / float(torch.linalg.norm(b))
+            del R, r
+        except Exception as e:  # the check is reported, never fatal to the bench line
+            rec["be_error"] = repr(e)[:200]
+    print(f"# prony: {rec}", file=sys.stderr, flush=True)
+    del buf, A, b, f
+    return rec
+
+
 def main():
     args = parse()
     if args.pass_only:
         return pass_only(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU row sharding is design only "
-                                   "(see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "one GPU only: the row-sharded multi-GPU form is a design, "
+                                   "not built", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -381,6 +444,8 @@ def main():
 
     mixed = mixed_bench(ctx, args, dev, probs[1]) if args.mixed else None
 
+    prony = prony_bench(ctx, args, dev) if args.prony else None
+
     serving = serve_bench(ctx, args, dev) if args.serve_requests > 0 else None
 
     # ---- accuracy (CPU, long double; outside the timed region)
@@ -463,6 +528,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy,
         "multi_rhs": multi,
         "mixed": mixed,
+        "prony": prony,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
