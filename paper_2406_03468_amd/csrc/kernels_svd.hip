@@ -227,26 +227,41 @@ __device__ __forceinline__ void jac_rotate_pair_r(double* __restrict__ x, double
 
 // Rotation of a pair whose first column stays in registers (xr, NQ elements per lane) and whose
 // second column is in LDS: a group keeps its top column through all sub-rounds of a round, so only
-// the partner column moves through LDS.
+// the partner column moves through LDS.  The squared norms are carried between sub-rounds instead of
+// summed again: the top column's in sa_x, each bottom column's in *ynorm (LDS, one per column);
+// a rotation with tangent t maps them to sa - t c and sb + t c (c = x^T y), and a norm that falls
+// below half its value (where that update cancels) is marked stale (-1) and summed at its next use.
+// Only x^T y is summed on every call.
 template <int NQ, int LP>
-__device__ __forceinline__ void jac_rotate_xreg(double (&xr)[NQ], double* __restrict__ y, int n, double tol,
-                                                int lane, int& nrot, double& c2max) {
+__device__ __forceinline__ void jac_rotate_xreg(double (&xr)[NQ], double& sa_x, double* __restrict__ y,
+                                                double* __restrict__ ynorm, int n, double tol, int lane, int& nrot,
+                                                double& c2max) {
   double yr[NQ];
 #pragma unroll
   for (int k = 0; k < NQ; ++k) {
     const int q = lane + LP * k;
     yr[k] = (q < n) ? y[q] : 0.0;
   }
+  const double yn = *ynorm;
+  // wave-uniform choices: the group sums below run in every active lane of the wave
+  const bool need_a = __ballot(!(sa_x >= 0.0)) != 0ull;
+  const bool need_b = __ballot(!(yn >= 0.0)) != 0ull;
   double sa = 0.0, sb = 0.0, sc = 0.0;
 #pragma unroll
-  for (int k = 0; k < NQ; ++k) {
-    sa = fma(xr[k], xr[k], sa);
-    sb = fma(yr[k], yr[k], sb);
-    sc = fma(xr[k], yr[k], sc);
+  for (int k = 0; k < NQ; ++k) sc = fma(xr[k], yr[k], sc);
+  if (need_a) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) sa = fma(xr[k], xr[k], sa);
   }
-  sa = group_sum<LP>(sa);
-  sb = group_sum<LP>(sb);
+  if (need_b) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) sb = fma(yr[k], yr[k], sb);
+  }
   sc = group_sum<LP>(sc);
+  if (need_a) sa = group_sum<LP>(sa);
+  else sa = sa_x;
+  if (need_b) sb = group_sum<LP>(sb);
+  else sb = yn;
   if (sa > 0.0 && sb > 0.0) c2max = fmax(c2max, (sc * sc) / (sa * sb));
   if (sa > 0.0 && sb > 0.0 && sc * sc > (tol * tol) * (sa * sb)) {
     const double zeta = (sb - sa) / (2.0 * sc);
@@ -254,6 +269,9 @@ __device__ __forceinline__ void jac_rotate_xreg(double (&xr)[NQ], double* __rest
     if (fabs(zeta) > 1e150) t = 0.5 / zeta;
     else t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
     const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    const double tc = t * sc, sa2 = sa - tc, sb2 = sb + tc;
+    sa_x = (sa2 > 0.5 * sa) ? sa2 : -1.0;
+    if (lane == 0) *ynorm = (sb2 > 0.5 * sb) ? sb2 : -1.0;
 #pragma unroll
     for (int k = 0; k < NQ; ++k) {
       const int q = lane + LP * k;
@@ -262,6 +280,9 @@ __device__ __forceinline__ void jac_rotate_xreg(double (&xr)[NQ], double* __rest
       xr[k] = (q < n) ? xn : 0.0;
     }
     ++nrot;
+  } else {
+    sa_x = sa;
+    if (lane == 0) *ynorm = sb;
   }
 }
 
@@ -327,6 +348,7 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
   const auto rmbox = co_rsrc(mbox, sizeof(double) * (size_t)P * 4 * blk);
   __shared__ int s_nrot[SVD_BLOCK_NT / 16];
   __shared__ double s_c2[SVD_BLOCK_NT / 16];
+  __shared__ double s_ynorm[SVD_BLOCK_NT / 16];  // b <= groups <= SVD_BLOCK_NT / 16
   int sweep = 0;
   unsigned rr = 0;  // global round counter
   for (; sweep < max_sweeps; ++sweep) {
@@ -360,9 +382,13 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
             const int q = gl + LP * k;
             xr[k] = (own && q < n) ? slot[0][(size_t)t * n + q] : 0.0;
           }
+          double sa_x = -1.0;            // ||x_t||^2, summed at the first sub-round
+          if (tid < b) s_ynorm[tid] = -1.0;  // ||y_c||^2 of the bottom columns, likewise
+          __syncthreads();
           for (int sr = 0; sr < b; ++sr) {
             const int c2 = (t + sr) % b;
-            if (own && c2 < nc1) jac_rotate_xreg<NQ, LP>(xr, slot[1] + (size_t)c2 * n, n, tol, gl, nrot, c2max);
+            if (own && c2 < nc1)
+              jac_rotate_xreg<NQ, LP>(xr, sa_x, slot[1] + (size_t)c2 * n, &s_ynorm[c2], n, tol, gl, nrot, c2max);
             __syncthreads();
           }
           if (own) {
