@@ -87,6 +87,10 @@ typedef struct fs_options {
   int32_t graph_sweeps;   /* 1: the inner iterations run as a captured HIP graph of kw_every iterations,
                              replayed until the device-side stop flag is set (one launch and one
                              host poll per kw_every iterations); 0: kernel-by-kernel launches */
+  int32_t overlap_pass_groups; /* work-groups of each pass over A in the first step while the SVD runs
+                             beside it (overlap_svd); 0: the compute units the SVD's work-groups leave
+                             free (rounded down to a multiple of 8), so that every pass work-group is
+                             resident at once; other passes take one per compute unit */
 } fs_options;
 
 /* Per-solve report. */

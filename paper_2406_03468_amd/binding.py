@@ -47,7 +47,7 @@ class FsOptions(ctypes.Structure):
         ("gamma", c_double), ("rho", c_double), ("kw_every", c_int32), ("max_inner", c_int32),
         ("tau_factor", c_double), ("column_scaling", c_int32), ("precond", c_int32), ("fixed_q", c_int32),
         ("steps", c_int32), ("precision", c_int32), ("max_sweeps", c_int32), ("init", c_int32),
-        ("overlap_svd", c_int32), ("graph_sweeps", c_int32),
+        ("overlap_svd", c_int32), ("graph_sweeps", c_int32), ("overlap_pass_groups", c_int32),
     ]
 
 

@@ -34,6 +34,7 @@ struct fs_context_s {
   int device = 0;
   hipStream_t stream = nullptr;
   int num_cu = 0;
+  int pass_group_cap = 0;  // > 0: at most this many work-groups per fused pass (the first step beside the SVD)
   int lds_bytes = 0;
   Workspace ws;
   DevState* st_host = nullptr;  // pinned copy for read-back

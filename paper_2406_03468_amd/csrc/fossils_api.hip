@@ -86,6 +86,7 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if ((int64_t)o.d > 65536) return FS_ERR_TOO_LARGE;  // QR row blocks
   if (o.max_sweeps < 1) return FS_ERR_INVALID_ARG;
   if (o.graph_sweeps != 0 && o.graph_sweeps != 1) return FS_ERR_INVALID_ARG;
+  if (o.overlap_pass_groups < 0) return FS_ERR_INVALID_ARG;
   if (o.init != FS_INIT_SKETCH && o.init != FS_INIT_ZERO) return FS_ERR_INVALID_ARG;
   if (o.overlap_svd != 0 && o.overlap_svd != 1) return FS_ERR_INVALID_ARG;
   (void)m;
@@ -138,6 +139,7 @@ fs_status fs_options_default(int64_t m, int32_t n, fs_options* o) {
   o->init = FS_INIT_SKETCH;
   o->overlap_svd = 1;
   o->graph_sweeps = 0;  // measured no faster than kernel-by-kernel launches (the host enqueues ahead)
+  o->overlap_pass_groups = 0;
   return FS_OK;
 }
 
@@ -296,6 +298,9 @@ fs_status fs_svd_triangular(fs_context ctx, int32_t n, const double* R, int64_t 
 
 static PassConfig pass_config(fs_context ctx, int64_t m, int32_t n, int64_t lda) {
   PassConfig cfg = fs_pass_config(m, n, ctx->num_cu);
+  // a cap on the fused pass's work-groups (multiples of 8 keep its XCD banding)
+  if (cfg.H && ctx->pass_group_cap > 0 && cfg.G > ctx->pass_group_cap)
+    cfg.G = std::max(8, ctx->pass_group_cap / 8 * 8);
   // 32-bit lane offsets inside a column slot (see the fused-pass kernel)
   if (cfg.H) {
     const int64_t cpr = 512 / (cfg.H / 2);
@@ -731,9 +736,20 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   }
   FS_HIP(hipEventRecord(ev[4], s));
 
+  struct PassCapReset {  // the cap applies to this solve's overlapped step only, on every exit path
+    fs_context c;
+    ~PassCapReset() { c->pass_group_cap = 0; }
+  } pass_cap_reset{ctx};
   for (int step = 0; step < o.steps; ++step) {
     const bool dstep = defer && step == 0;  // first step beside the SVD (P = R^{-1}, iterates recorded)
     bool thr_known = !dstep;
+    // beside the SVD the passes take only the compute units its work-groups leave free: a pass
+    // with more work-groups than free units runs a second, partial wave of them
+    ctx->pass_group_cap =
+        !dstep ? 0
+               : (o.overlap_pass_groups > 0
+                      ? o.overlap_pass_groups
+                      : std::max(8, (ctx->num_cu - fs_svd_grid_size(n, ctx->num_cu, false)) / 8 * 8));
     // residual pass at x (scaled coordinates): g = D^{-1} A^T (b - A D^{-1} x), r2
     FS_K(fs_vec_mul(n, v.x, dinv, v.zs, nullptr, s));
     FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, nullptr, rbuf));

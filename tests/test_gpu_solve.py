@@ -229,8 +229,12 @@ def test_graph_sweeps_match_eager(ctx, method, kw_every, max_inner):
 def test_section51_comparison_solvers_gpu(ctx, kappa, rnorm):
     """The comparison methods of Section 5.1 on the GPU (options of the same kernels): one run of
     sketch-and-precondition from x_0 = 0 (CG, LSQR) or from sketch-and-solve, iterative sketching
-    with momentum (FOSSILS, one step).  Each lands within 10x of the oracle's backward error for the
-    same variant, far above the 1e-14 that the two-step methods meet on the same problem."""
+    with momentum (FOSSILS, one step).  Each lands near the oracle's backward error for the
+    same variant, far above the 1e-14 that the two-step methods meet on the same problem.  These
+    variants are not backward stable, so their BE depends on the sketch's rounding: the oracle's own
+    spreads about 10x across sketch seeds (SPIR from x_0 = 0 at kappa 1e12: 1.6e-13 .. 9.6e-13 with
+    P = V Sigma^{-1}, 2.2e-13 .. 2.0e-12 with P = R^{-1}, which the GPU's first step uses beside the
+    SVD), so the GPU and the oracle run are compared within 30x."""
     from paper_2406_03468_amd import binding
     P = make_problem(4000, 50, kappa, rnorm, seed=5)
     two = []
@@ -247,7 +251,7 @@ def test_section51_comparison_solvers_gpu(ctx, kappa, rnorm):
         bg = be.relative_backward_error(P.A, P.b, x, P.sigma, P.V)
         bo = be.relative_backward_error(P.A, P.b, ref.x, P.sigma, P.V)
         assert bg >= 30 * max(two), (meth, kw, bg)
-        assert bo / 10 <= bg <= 10 * bo, (meth, kw, bg, bo)
+        assert bo / 30 <= bg <= 30 * bo, (meth, kw, bg, bo)
 
 
 @pytest.mark.parametrize("method", ["fossils", "spir"])
