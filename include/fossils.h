@@ -83,7 +83,9 @@ typedef struct fs_options {
                              (the same preconditioned system up to an orthogonal change of variables);
                              its iterates are recorded and, once normest and condest are known, the step
                              is cut back to the iteration where the first-step rule stops.  Falls back to
-                             the serial order when R turns out numerically rank deficient. */
+                             the serial order when R turns out numerically rank deficient; not used when
+                             the SVD's work-groups would hold more than half of the compute units
+                             (n above ~1500 on 256 compute units). */
   int32_t graph_sweeps;   /* 1: the inner iterations run as a captured HIP graph of kw_every iterations,
                              replayed until the device-side stop flag is set (one launch and one
                              host poll per kw_every iterations); 0: kernel-by-kernel launches */

@@ -484,8 +484,11 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   Workspace& W = ctx->ws;
   const int d = o.d, zeta = o.zeta, k = n + 1;
   // The SVD of R beside the first refinement step (see fs_options.overlap_svd).
+  // (only while the SVD leaves at least half of the compute units to the passes: an SVD grid that
+  // holds nearly all of them would leave the step's passes a few units, slower than the serial order)
   bool defer = o.overlap_svd && o.precond == FS_PRECOND_SVD && o.precision == FS_FP64 && o.fixed_q == 0 &&
-               (method == M_FOSSILS || method == M_SPIR);
+               (method == M_FOSSILS || method == M_SPIR) &&
+               2 * fs_svd_grid_size(n, ctx->num_cu, false) <= ctx->num_cu;
   const bool i16 = idx16_ok(d);
 
   // ---- workspace
@@ -743,13 +746,14 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   for (int step = 0; step < o.steps; ++step) {
     const bool dstep = defer && step == 0;  // first step beside the SVD (P = R^{-1}, iterates recorded)
     bool thr_known = !dstep;
-    // beside the SVD the passes take only the compute units its work-groups leave free: a pass
-    // with more work-groups than free units runs a second, partial wave of them
-    ctx->pass_group_cap =
-        !dstep ? 0
-               : (o.overlap_pass_groups > 0
-                      ? o.overlap_pass_groups
-                      : std::max(8, (ctx->num_cu - fs_svd_grid_size(n, ctx->num_cu, false)) / 8 * 8));
+    // beside the SVD the passes take only the compute units its work-groups leave free (at least
+    // half of them here): a pass with more work-groups than free units runs a second, partial wave
+    int group_cap = 0;
+    if (dstep) {
+      const int free_cu = ctx->num_cu - fs_svd_grid_size(n, ctx->num_cu, false);
+      group_cap = (o.overlap_pass_groups > 0) ? o.overlap_pass_groups : free_cu / 8 * 8;
+    }
+    ctx->pass_group_cap = group_cap;
     // residual pass at x (scaled coordinates): g = D^{-1} A^T (b - A D^{-1} x), r2
     FS_K(fs_vec_mul(n, v.x, dinv, v.zs, nullptr, s));
     FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, nullptr, rbuf));

@@ -243,9 +243,12 @@ __device__ __forceinline__ void jac_rotate_xreg(double (&xr)[NQ], double& sa_x, 
     yr[k] = (q < n) ? y[q] : 0.0;
   }
   const double yn = *ynorm;
-  // wave-uniform choices: the group sums below run in every active lane of the wave
-  const bool need_a = __ballot(!(sa_x >= 0.0)) != 0ull;
-  const bool need_b = __ballot(!(yn >= 0.0)) != 0ull;
+  // wave-uniform choices: the group sums below run in every active lane of the wave.  With 32
+  // elements per lane the carried norms cost registers the kernel does not have (it would spill),
+  // so that variant sums all three products every time.
+  constexpr bool carry = NQ < 32;
+  const bool need_a = !carry || __ballot(!(sa_x >= 0.0)) != 0ull;
+  const bool need_b = !carry || __ballot(!(yn >= 0.0)) != 0ull;
   double sa = 0.0, sb = 0.0, sc = 0.0;
 #pragma unroll
   for (int k = 0; k < NQ; ++k) sc = fma(xr[k], yr[k], sc);

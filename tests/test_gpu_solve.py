@@ -280,6 +280,25 @@ def test_overlapped_svd_matches_serial(ctx, method, m, n, kappa, rnorm):
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(P.x_true) <= 10 * _fe_ref(P, xq)
 
 
+@pytest.mark.parametrize("groups", [0, 16, 64, 1000])
+def test_overlap_pass_groups(ctx, groups):
+    """The first step's passes beside the SVD with a chosen number of work-groups (0: the compute
+    units the SVD leaves free; more than the passes' own grid: no cap): the same solve up to the
+    rounding of the passes' partial sums.  A negative value is refused."""
+    from paper_2406_03468_amd import binding
+    P = make_problem(20000, 200, 1e10, 1e-6, seed=12)
+    st0, i0, x0 = _solve(ctx, P, "fossils")
+    st1, i1, x1 = _solve(ctx, P, "fossils", overlap_pass_groups=groups)
+    assert st0 == 0 and st1 == 0
+    assert be.relative_backward_error(P.A, P.b, x1, P.sigma, P.V) <= 1e-14
+    assert abs(i0.iters[0] - i1.iters[0]) <= 1 and abs(i0.iters[1] - i1.iters[1]) <= 1
+    xq = hh.qr_lstsq(P.A, P.b)
+    assert np.linalg.norm(x1 - x0) / np.linalg.norm(P.x_true) <= 10 * _fe_ref(P, xq)
+    if groups == 0:
+        with pytest.raises(binding.FossilsError):
+            _solve(ctx, P, "fossils", overlap_pass_groups=-1)
+
+
 def test_overlapped_svd_rank_deficient_restart(ctx):
     """A numerically rank-deficient A (repeated columns): the overlapped first step is discarded
     once the SVD reports condest beyond 1/(30 u), and the solve restarts with the truncated
