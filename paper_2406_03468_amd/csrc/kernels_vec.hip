@@ -49,11 +49,17 @@ __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int6
         if (b0 + lane < b1) xs[b0 + lane] = xi;
       }
       __syncthreads();
-      // x[0:b0] -= R[0:b0, b0:b1] x[b0:b1]
+      // x[0:b0] -= R[0:b0, b0:b1] x[b0:b1]: eight independent sums per row, so that eight loads of R
+      // are in flight at a time instead of one
       for (int i = tid; i < b0; i += VNT) {
-        double s = 0.0;
-        for (int j = b0; j < b1; ++j) s = fma(R[(int64_t)j * ldr + i], xs[j], s);
-        xs[i] -= s;
+        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int j = b0;
+        for (; j + 8 <= b1; j += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) s8[u] = fma(R[(int64_t)(j + u) * ldr + i], xs[j + u], s8[u]);
+        }
+        for (; j < b1; ++j) s8[0] = fma(R[(int64_t)j * ldr + i], xs[j], s8[0]);
+        xs[i] -= ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
       }
       __syncthreads();
     }
@@ -65,9 +71,17 @@ __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int6
       {
         const int o = tid >> 4, sub = tid & 15;
         const int i = b0 + o;
-        double s = 0.0;
-        if (i < b1)
-          for (int j = sub; j < b0; j += 16) s = fma(R[(int64_t)i * ldr + j], xs[j], s);
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};  // four loads of R in flight per thread
+        if (i < b1) {
+          const double* Ri = R + (int64_t)i * ldr;
+          int j = sub;
+          for (; j + 48 < b0; j += 64) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s4[u] = fma(Ri[j + 16 * u], xs[j + 16 * u], s4[u]);
+          }
+          for (; j < b0; j += 16) s4[0] = fma(Ri[j], xs[j], s4[0]);
+        }
+        double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) s += __shfl_xor(s, off, 64);
         __syncthreads();
