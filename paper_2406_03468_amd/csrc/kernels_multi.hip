@@ -66,14 +66,15 @@ __global__ __launch_bounds__(512) void k_mr_apply(const double* __restrict__ A, 
       if (q < AP_KC * KP) zsh[buf][q / KP][q % KP] = zreg[u];
     }
   };
-  double a0[2][KS], a1[2][KS];
-  auto aload = [&](int sl, int c0) {
+  // A operands two chunks ahead, in three register slots (chunk c in slot c % 3)
+  double a0[3][KS], a1[3][KS];
+  auto aload = [&](double (&p0)[KS], double (&p1)[KS], int c0) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       int c = c0 + 4 * s + lk;
       if (c >= n) c = n - 1;  // matching Zs rows are zero
-      a0[sl][s] = A[(int64_t)c * lda + ra0];
-      a1[sl][s] = A[(int64_t)c * lda + ra1];
+      p0[s] = A[(int64_t)c * lda + ra0];
+      p1[s] = A[(int64_t)c * lda + ra1];
     }
   };
 
@@ -83,28 +84,33 @@ __global__ __launch_bounds__(512) void k_mr_apply(const double* __restrict__ A, 
     acc0[b] = v4d{0.0, 0.0, 0.0, 0.0};
     acc1[b] = v4d{0.0, 0.0, 0.0, 0.0};
   }
-  zload(0);
-  zstore(0);
-  aload(0, 0);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1, sl = ch & 1;
+  // one chunk: x = its operands, p = the slot that receives chunk ch + 2
+  auto chunk_step = [&](int ch, const double (&x0)[KS], const double (&x1)[KS], double (&p0)[KS], double (&p1)[KS]) {
+    const int buf = ch & 1;
     const bool more = ch + 1 < nch;
-    if (more) {
-      zload((ch + 1) * AP_KC);
-      aload(sl ^ 1, (ch + 1) * AP_KC);
-    }
+    if (more) zload((ch + 1) * AP_KC);
+    if (ch + 2 < nch) aload(p0, p1, (ch + 2) * AP_KC);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const double zb = zsh[buf][4 * s + lk][16 * b + li];
-        acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[sl][s], zb, acc0[b], 0, 0, 0);
-        acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[sl][s], zb, acc1[b], 0, 0, 0);
+        acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0[s], zb, acc0[b], 0, 0, 0);
+        acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1[s], zb, acc1[b], 0, 0, 0);
       }
     }
     if (more) zstore(buf ^ 1);  // buf^1 was last read in chunk ch-1 (synchronized below)
     __syncthreads();
+  };
+  zload(0);
+  zstore(0);
+  aload(a0[0], a1[0], 0);
+  if (nch > 1) aload(a0[1], a1[1], AP_KC);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ch += 3) {  // (the conditions are uniform over the work-group)
+    chunk_step(ch, a0[0], a1[0], a0[2], a1[2]);
+    if (ch + 1 < nch) chunk_step(ch + 1, a0[1], a1[1], a0[0], a1[0]);
+    if (ch + 2 < nch) chunk_step(ch + 2, a0[2], a1[2], a0[1], a1[1]);
   }
 
   // epilogue: lane (li, lk), register r -> row 4r + lk of the 16-row block, column 16b + li
@@ -178,42 +184,80 @@ __global__ __launch_bounds__(512) void k_mr_gather(const double* __restrict__ A,
   const int64_t r_lo = chunk * rc, r_hi = (r_lo + rc < m) ? r_lo + rc : m;
   const double* Ac = A + (int64_t)c * lda;
 
-  v4d acc[NB], tot[NB];
+  v4d acc[NB], acc2[NB], tot[NB];  // acc: even k-steps, acc2: odd ones (two chains per block)
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+    acc2[b] = v4d{0.0, 0.0, 0.0, 0.0};
     tot[b] = v4d{0.0, 0.0, 0.0, 0.0};
   }
+  // W rows of a group (4 GA_GS rows x KP) are staged once per work-group in LDS (double-buffered)
+  // instead of being loaded by each of the 8 waves; A operands and the next group's W are loaded
+  // one group ahead.
+  constexpr int GR = 4 * GA_GS;               // rows per group
+  constexpr int WPT = (GR * KP + 511) / 512;  // W entries per thread per group
+  __shared__ double wsh[2][GR][KP];
+  double wreg[WPT], av[2][GA_GS];
+  auto wload = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int q = tid + 512 * u;
+      const int64_t row = r0 + q / KP;
+      wreg[u] = (q < GR * KP && row < r_hi) ? W[row * KP + q % KP] : 0.0;
+    }
+  };
+  auto wstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < WPT; ++u) {
+      const int q = tid + 512 * u;
+      if (q < GR * KP) wsh[buf][q / KP][q % KP] = wreg[u];
+    }
+  };
+  auto aload = [&](int sl, int64_t r0) {
+#pragma unroll
+    for (int s = 0; s < GA_GS; ++s) {
+      const int64_t row = r0 + 4 * s + lk;
+      av[sl][s] = (row < r_hi) ? Ac[row] : 0.0;
+    }
+  };
   int since = 0;
-  for (int64_t r = r_lo; r < r_hi; r += 4 * GA_GS) {
-    double av[GA_GS], wvv[GA_GS][NB];
-#pragma unroll
-    for (int s = 0; s < GA_GS; ++s) {
-      const int64_t row = r + 4 * s + lk;
-      const bool ok = row < r_hi;
-      av[s] = ok ? Ac[row] : 0.0;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) wvv[s][b] = ok ? W[row * KP + 16 * b + li] : 0.0;
+  wload(r_lo);
+  wstore(0);
+  aload(0, r_lo);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t r = r_lo; r < r_hi; r += GR, buf ^= 1) {
+    const bool more = r + GR < r_hi;
+    if (more) {
+      wload(r + GR);
+      aload(buf ^ 1, r + GR);
     }
 #pragma unroll
-    for (int s = 0; s < GA_GS; ++s) {
+    for (int s = 0; s < GA_GS; s += 2) {
 #pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s], wvv[s][b], acc[b], 0, 0, 0);
+      for (int b = 0; b < NB; ++b) {
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[buf][s], wsh[buf][4 * s + lk][16 * b + li], acc[b], 0, 0, 0);
+        acc2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[buf][s + 1], wsh[buf][4 * s + 4 + lk][16 * b + li], acc2[b],
+                                                      0, 0, 0);
+      }
     }
+    if (more) wstore(buf ^ 1);  // buf ^ 1 was last read in the previous group (synchronized below)
+    __syncthreads();
     since += GA_GS;
     if (since >= GA_FLUSH) {  // two-level summation: bounded accumulation chains
       since = 0;
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        tot[b] += acc[b];
+        tot[b] += acc[b] + acc2[b];
         acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+        acc2[b] = v4d{0.0, 0.0, 0.0, 0.0};
       }
     }
   }
   // D layout: register r holds column (row of V) 4r + lk of the wave's 16-column block, RHS 16b + li
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    tot[b] += acc[b];
+    tot[b] += acc[b] + acc2[b];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int cc = cb * GA_TN + wv * 16 + 4 * r + lk;
