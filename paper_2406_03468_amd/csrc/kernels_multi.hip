@@ -197,7 +197,7 @@ __global__ __launch_bounds__(512) void k_mr_gather(const double* __restrict__ A,
   constexpr int GR = 4 * GA_GS;               // rows per group
   constexpr int WPT = (GR * KP + 511) / 512;  // W entries per thread per group
   __shared__ double wsh[2][GR][KP];
-  double wreg[WPT], av[2][GA_GS];
+  double wreg[WPT], av[3][GA_GS];
   auto wload = [&](int64_t r0) {
 #pragma unroll
     for (int u = 0; u < WPT; ++u) {
@@ -213,31 +213,26 @@ __global__ __launch_bounds__(512) void k_mr_gather(const double* __restrict__ A,
       if (q < GR * KP) wsh[buf][q / KP][q % KP] = wreg[u];
     }
   };
-  auto aload = [&](int sl, int64_t r0) {
+  auto aload = [&](double (&p)[GA_GS], int64_t r0) {
 #pragma unroll
     for (int s = 0; s < GA_GS; ++s) {
       const int64_t row = r0 + 4 * s + lk;
-      av[sl][s] = (row < r_hi) ? Ac[row] : 0.0;
+      p[s] = (row < r_hi) ? Ac[row] : 0.0;
     }
   };
   int since = 0;
-  wload(r_lo);
-  wstore(0);
-  aload(0, r_lo);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t r = r_lo; r < r_hi; r += GR, buf ^= 1) {
+  // one group of rows: x = its A operands (loaded two groups earlier), p = the slot that receives
+  // the A operands of the group after next
+  auto group_step = [&](int64_t r, int buf, const double (&x)[GA_GS], double (&p)[GA_GS]) {
     const bool more = r + GR < r_hi;
-    if (more) {
-      wload(r + GR);
-      aload(buf ^ 1, r + GR);
-    }
+    if (more) wload(r + GR);
+    if (r + 2 * GR < r_hi) aload(p, r + 2 * GR);
 #pragma unroll
     for (int s = 0; s < GA_GS; s += 2) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[buf][s], wsh[buf][4 * s + lk][16 * b + li], acc[b], 0, 0, 0);
-        acc2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[buf][s + 1], wsh[buf][4 * s + 4 + lk][16 * b + li], acc2[b],
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s], wsh[buf][4 * s + lk][16 * b + li], acc[b], 0, 0, 0);
+        acc2[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s + 1], wsh[buf][4 * s + 4 + lk][16 * b + li], acc2[b],
                                                       0, 0, 0);
       }
     }
@@ -252,6 +247,25 @@ __global__ __launch_bounds__(512) void k_mr_gather(const double* __restrict__ A,
         acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
         acc2[b] = v4d{0.0, 0.0, 0.0, 0.0};
       }
+    }
+  };
+  wload(r_lo);
+  wstore(0);
+  aload(av[0], r_lo);
+  if (r_lo + GR < r_hi) aload(av[1], r_lo + GR);
+  __syncthreads();
+  // groups g, g+1, g+2 use slots 0, 1, 2 and LDS buffers alternating (uniform conditions)
+  int buf = 0;
+  for (int64_t r = r_lo; r < r_hi; r += 3 * GR) {
+    group_step(r, buf, av[0], av[2]);
+    buf ^= 1;
+    if (r + GR < r_hi) {
+      group_step(r + GR, buf, av[1], av[0]);
+      buf ^= 1;
+    }
+    if (r + 2 * GR < r_hi) {
+      group_step(r + 2 * GR, buf, av[2], av[1]);
+      buf ^= 1;
     }
   }
   // D layout: register r holds column (row of V) 4r + lk of the wave's 16-column block, RHS 16b + li
