@@ -281,34 +281,53 @@ __global__ __launch_bounds__(512) void k_mr_gather(const double* __restrict__ A,
   (void)cvalid;
 }
 
-// V[c][j] = scale[c] * sum_chunk Vpart[chunk][c][j] (fixed order, compensated); r2[j] likewise.
+// V[c][j] = scale[c] * sum_chunk Vpart[chunk][c][j] (fixed order, compensated), one thread per entry
+// in the first ceil(n kp / 256) work-groups; r2[j] = sum_g r2part[g][j] in one work-group per j after
+// them (each thread a strided compensated sum, then the 256 partial sums in thread order).
 __global__ __launch_bounds__(256) void k_mr_reduce(const double* __restrict__ Vpart, int64_t nchunk, int n, int kp,
                                                    const double* __restrict__ scale, double* __restrict__ V,
                                                    const double* __restrict__ r2part, int64_t nr2, double* __restrict__ r2,
                                                    const int* __restrict__ stop) {
   if (fs_stopped(stop)) return;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = (int64_t)n * kp;
-  if (q < tot) {
-    double s = 0.0, e = 0.0;
-    for (int64_t ch = 0; ch < nchunk; ++ch) {
-      double t, d;
-      two_sum(s, Vpart[ch * tot + q], t, d);
-      s = t;
-      e += d;
+  const int64_t nbv = (tot + 255) / 256;
+  if ((int64_t)blockIdx.x < nbv) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < tot) {
+      double s = 0.0, e = 0.0;
+      for (int64_t ch = 0; ch < nchunk; ++ch) {
+        double t, d;
+        two_sum(s, Vpart[ch * tot + q], t, d);
+        s = t;
+        e += d;
+      }
+      s += e;
+      V[q] = scale ? s * scale[q / kp] : s;
     }
-    s += e;
-    V[q] = scale ? s * scale[q / kp] : s;
-  } else if (r2part && q < tot + kp) {
-    const int j = (int)(q - tot);
-    double s = 0.0, e = 0.0;
-    for (int64_t g = 0; g < nr2; ++g) {
-      double t, d;
-      two_sum(s, r2part[g * kp + j], t, d);
-      s = t;
-      e += d;
+    return;
+  }
+  const int j = (int)((int64_t)blockIdx.x - nbv);  // r2 work-groups (launched only with r2part)
+  if (!r2part || j >= kp) return;
+  __shared__ double ss[256], se[256];
+  double s = 0.0, e = 0.0;
+  for (int64_t g = threadIdx.x; g < nr2; g += 256) {
+    double t, d;
+    two_sum(s, r2part[g * kp + j], t, d);
+    s = t;
+    e += d;
+  }
+  ss[threadIdx.x] = s;
+  se[threadIdx.x] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0, te = 0.0;
+    for (int q = 0; q < 256; ++q) {
+      double u, d;
+      two_sum(t, ss[q], u, d);
+      t = u;
+      te += d + se[q];
     }
-    r2[j] = s + e;
+    r2[j] = t + te;
   }
 }
 
@@ -329,8 +348,8 @@ hipError_t launch_nb(const MultiPassArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_mr_gather<NB>), dim3((unsigned)(slots * 8)), dim3(512), 0, s, a.A, a.lda, a.m, a.n, a.W,
                      a.rc, ncb, a.Vpart, a.stop);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int64_t nout = (int64_t)a.n * 16 * NB + (a.B ? 16 * NB : 0);
-  hipLaunchKernelGGL(k_mr_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, a.Vpart, nchunk, a.n,
+  const int64_t nbv = ((int64_t)a.n * 16 * NB + 255) / 256;  // V work-groups, then one per r2 entry
+  hipLaunchKernelGGL(k_mr_reduce, dim3((unsigned)(nbv + (a.B ? 16 * NB : 0))), dim3(256), 0, s, a.Vpart, nchunk, a.n,
                      16 * NB, a.scale, a.V, a.B ? a.r2part : (const double*)nullptr, (int64_t)G1, a.r2, a.stop);
   return hipGetLastError();
 }
