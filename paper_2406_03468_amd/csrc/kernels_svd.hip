@@ -499,8 +499,35 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
           }
         }
       };
-      if (recv_top) recv(slot[0], mb(p, 0, par));
-      if (recv_bot) recv(slot[1], mb(p, 1, par));
+      // (not in the 32-elements-per-lane variant: its registers are spent on the columns)
+      if (NQ != 32 && (blk & 1) == 0 && blk <= 16 * (size_t)blockDim.x) {
+        // both blocks in one batch of coherent loads (one round trip instead of two)
+        const size_t s0 = mb(p, 0, par), s1 = mb(p, 1, par);
+        fs_f64x2 v0[8], v1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const size_t q = 2 * tid + (size_t)u * 2 * blockDim.x;
+          v0[u] = ld_cob2(rmbox, (recv_top && q < blk) ? 8 * (s0 + q) : (size_t)0xFFFFFFF0u);
+          v1[u] = ld_cob2(rmbox, (recv_bot && q < blk) ? 8 * (s1 + q) : (size_t)0xFFFFFFF0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const size_t q = 2 * tid + (size_t)u * 2 * blockDim.x;
+          if (q < blk) {
+            if (recv_top) {
+              slot[0][q] = v0[u][0];
+              slot[0][q + 1] = v0[u][1];
+            }
+            if (recv_bot) {
+              slot[1][q] = v1[u][0];
+              slot[1][q + 1] = v1[u][1];
+            }
+          }
+        }
+      } else {
+        if (recv_top) recv(slot[0], mb(p, 0, par));
+        if (recv_bot) recv(slot[1], mb(p, 1, par));
+      }
       __syncthreads();
       // block ids after the move (round r + 1 of this sweep)
       id[0] = circle_player(p, r + 1, NBLK);
