@@ -486,9 +486,11 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   // The SVD of R beside the first refinement step (see fs_options.overlap_svd).
   // (only while the SVD leaves at least half of the compute units to the passes: an SVD grid that
   // holds nearly all of them would leave the step's passes a few units, slower than the serial order)
-  bool defer = o.overlap_svd && o.precond == FS_PRECOND_SVD && o.precision == FS_FP64 && o.fixed_q == 0 &&
-               (method == M_FOSSILS || method == M_SPIR) &&
-               2 * fs_svd_grid_size(n, ctx->num_cu, false) <= ctx->num_cu;
+  // (the mixed form overlaps only once it has fallen back to an FP64 sketch before its SVD)
+  const bool defer_fp64 = o.overlap_svd && o.precond == FS_PRECOND_SVD && o.fixed_q == 0 &&
+                          (method == M_FOSSILS || method == M_SPIR) &&
+                          2 * fs_svd_grid_size(n, ctx->num_cu, false) <= ctx->num_cu;
+  bool defer = defer_fp64 && o.precision == FS_FP64;
   const bool i16 = idx16_ok(d);
 
   // ---- workspace
@@ -506,13 +508,13 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_TRY(grow(W.vecs, sizeof(double) * (size_t)NV * n));
   FS_TRY(grow(W.state, sizeof(DevState) + 64));
   FS_TRY(ensure_pass_ws(ctx, m, n, lda));
-  if (defer) {
+  if (defer_fp64) {  // (also for a mixed solve, which may fall back to an FP64 sketch and overlap)
     FS_TRY(grow(W.hist, sizeof(double) * ((size_t)o.max_inner * n + o.max_inner + 8)));
     if (!ctx->aux_stream) FS_HIP(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
     if (!ctx->ev_aux) FS_HIP(hipEventCreateWithFlags(&ctx->ev_aux, hipEventDisableTiming));
   }
-  double* hist_dy = defer ? (double*)W.hist.p : nullptr;
-  double* hist_dn = defer ? hist_dy + (size_t)o.max_inner * n : nullptr;
+  double* hist_dy = defer_fp64 ? (double*)W.hist.p : nullptr;
+  double* hist_dn = defer_fp64 ? hist_dy + (size_t)o.max_inner * n : nullptr;
   const bool lsqr = (method == M_SPIR_LSQR);
   if (lsqr) FS_TRY(grow(W.lsqr, sizeof(double) * 2 * (size_t)m));
   double* rbuf = lsqr ? (double*)W.lsqr.p : nullptr;  // r of the last LSQR pass (m)
@@ -613,6 +615,16 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   const bool mixed = (o.precision == FS_MIXED);
   int flags = 0;
   FS_TRY(factor(mixed, defer));
+  if (mixed && (early_fallback || !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION))) {
+    // The FP32 sketch perturbs S A by about u32 ||A||: as a preconditioner its R keeps A_s R^{-1}
+    // well conditioned only while condest u32 is small (the hazard of Lemma 6.3 at single precision).
+    // Otherwise (decided from diag(R) alone before the SVD, or from the SVD's condest) the sketch is
+    // redone in FP64 (the FP64 correction of R) and the solve continues as an FP64 one, with the SVD
+    // beside the first step when that applies.
+    flags |= FS_FLAG_FP64_SKETCH;
+    defer = defer_fp64;
+    FS_TRY(factor(false, defer));
+  }
   if (defer && cnh[n] == 0.0) {  // b = 0 ends the solve below: no overlap, the SVD runs here
     defer = false;
     CoopSection cs(ctx, fs_svd_grid_size(n, ctx->num_cu, false));
@@ -642,13 +654,6 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
                             svd_sweeps_dev, a));
     FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, a));
     FS_HIP(hipEventRecord(ev[3], a));
-  }
-  if (mixed && (early_fallback || !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION))) {
-    // The FP32 sketch perturbs S A by about u32 ||A||: as a preconditioner its R keeps A_s R^{-1}
-    // well conditioned only while condest u32 is small (the hazard of Lemma 6.3 at single precision).
-    // Otherwise the sketch is redone in FP64 (the FP64 correction of R) and the solve continues in FP64.
-    flags |= FS_FLAG_FP64_SKETCH;
-    FS_TRY(factor(false, false));
   }
   const double b2 = cnh[n];
   DevState hs = *ctx->st_host;
