@@ -486,11 +486,12 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   // The SVD of R beside the first refinement step (see fs_options.overlap_svd).
   // (only while the SVD leaves at least half of the compute units to the passes: an SVD grid that
   // holds nearly all of them would leave the step's passes a few units, slower than the serial order)
-  // (the mixed form overlaps only once it has fallen back to an FP64 sketch before its SVD)
+  // (the mixed form too: a kept FP32 sketch whose SVD then reports u32 condest too large restarts
+  // the solve from an FP64 sketch, see the join below)
   const bool defer_fp64 = o.overlap_svd && o.precond == FS_PRECOND_SVD && o.fixed_q == 0 &&
                           (method == M_FOSSILS || method == M_SPIR) &&
                           2 * fs_svd_grid_size(n, ctx->num_cu, false) <= ctx->num_cu;
-  bool defer = defer_fp64 && o.precision == FS_FP64;
+  bool defer = defer_fp64;
   const bool i16 = idx16_ok(d);
 
   // ---- workspace
@@ -645,7 +646,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       if (a) (void)hipStreamSynchronize(a);
     }
   } aux_drain;
-  if (defer) {
+  auto launch_aux_svd = [&]() -> fs_status {
     hipStream_t a = ctx->aux_stream;
     aux_drain.a = a;
     FS_HIP(hipStreamWaitEvent(a, ctx->ev_aux, 0));
@@ -654,7 +655,9 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
                             svd_sweeps_dev, a));
     FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, a));
     FS_HIP(hipEventRecord(ev[3], a));
-  }
+    return FS_OK;
+  };
+  if (defer) FS_TRY(launch_aux_svd());
   const double b2 = cnh[n];
   DevState hs = *ctx->st_host;
   fs_info inf{};
@@ -830,6 +833,11 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
         if (poll) {
           if (!thr_known && hipEventQuery(ev[3]) == hipSuccess) FS_TRY(apply_threshold());
           FS_TRY(poll_stop());
+          // a kept FP32 sketch whose SVD reports u32 condest too large: this step will be discarded
+          // (the join restarts from an FP64 sketch), so it stops here
+          if (thr_known && mixed && !(flags & FS_FLAG_FP64_SKETCH) &&
+              !(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION))
+            stopped = true;
         }
       }
       if (!thr_known) FS_TRY(apply_threshold());
@@ -875,6 +883,22 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       inf.condest = hs.condest;
       inf.svd_sweeps = svd_sweeps;
       defer = false;
+      if (mixed && !(flags & FS_FLAG_FP64_SKETCH) && !(hs.condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
+        // the FP32 sketch kept on diag(R)'s evidence fails on its SVD's condest: discard the
+        // overlapped first step and restart from an FP64 sketch, its SVD again beside the first step
+        flags |= FS_FLAG_FP64_SKETCH;
+        FS_TRY(factor(false, true));
+        FS_TRY(launch_aux_svd());
+        defer = true;
+        hs = *ctx->st_host;
+        FS_K(fs_vec_set_double(&st->theta2, hs.fro2 / b2, s));  // ||A_s||_F of the FP64 column scaling
+        use_svd = false;
+        nr = n;
+        FS_TRY(start_x0());
+        iters[0] = 0;
+        step = -1;
+        continue;
+      }
       if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {
         // numerically rank deficient after all: start over in the serial order with the truncated
         // preconditioner (the overlapped first step is discarded)
