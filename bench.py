@@ -378,7 +378,8 @@ def main():
         times.append(time.perf_counter() - ts)
         infos.append((i, st, info))
         print(f"# step {k}: problem {i} status {st} {1e3 * times[-1]:.2f} ms iters {list(info.iters)} "
-              f"kw {info.kw_evals} svd sweeps {info.svd_sweeps} phases {[round(p, 2) for p in info.phase_ms]}",
+              f"kw {info.kw_evals} flags {info.flags} svd sweeps {info.svd_sweeps} "
+              f"phases {[round(p, 2) for p in info.phase_ms]}",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start

@@ -47,6 +47,8 @@ def test_options_default_is_algorithm4(clib):
     assert (o.gamma, o.rho, o.tau_factor) == (10.0, 0.4, 30.0)
     assert o.column_scaling == 1 and o.steps == 2 and o.fixed_q == 0
     assert o.precond == binding.FS_PRECOND_SVD  # Alg 4: P = V Sigma^{-1}
+    # the last fields: the ctypes layout agrees with the header's
+    assert (o.overlap_svd, o.graph_sweeps, o.overlap_pass_groups) == (1, 0, 0)
 
 
 def test_status_strings(clib):
