@@ -43,7 +43,7 @@ typedef enum fs_status {
   FS_ERR_NOMEM = -3,           /* device allocation failed */
   FS_ERR_DEVICE = -4,          /* a HIP call failed (see fs_last_error_detail) */
   FS_ERR_NONFINITE = -5,       /* A or b holds NaN or Inf */
-  FS_ERR_TOO_LARGE = -6,       /* size beyond what this build supports (n > 15000, d > 65536) */
+  FS_ERR_TOO_LARGE = -6,       /* size beyond what the library supports (n > 15000, d > 65536) */
   FS_ERR_UNKNOWN_TICKET = -7,  /* batched_poll / fs_server_ticket_times: no such ticket */
   FS_ERR_UNSUPPORTED = -8
 } fs_status;
