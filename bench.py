@@ -18,6 +18,8 @@ Printed as one JSON line:
                  normal_pass and substitutions, numpy float64) on the same 1e6 x 1000 matrix, in GB/s
                  of algorithmic bytes;
   accuracy       relative backward error (Karlson-Walden, known SVD, long double) per problem;
+  pass_autotune  fs_tune_pass at this shape (every admissible tile height and work-group count of
+                 the fused pass timed, the fastest kept) against the built-in rule;
   multi_rhs, mixed, prony, serving
                  the 64-RHS solve, the mixed-precision form (C4), the complex Prony problem at
                  5e5 x 1000 (Section 5.2), and the served stream (C5).
@@ -415,6 +417,17 @@ def main():
                 "kernel": "k_fused_pass (v = A^T(A z), H=16 rows x 1000 cols per tile)",
                 "ms_kernel": round(ms_kernel, 4), "ms_pass_with_reduction": round(ms_pass, 4)}
 
+    # ---- the fused pass's autotuner at this shape (a context of its own: the numbers above use the
+    # built-in tile rule); every admissible (tile height, work-group count), the fastest kept
+    tctx = binding.Context(0)
+    try:
+        tH, tG, tms = binding.fs_tune_pass(tctx, probs[0].A, z, v, repeats=5)
+    finally:
+        tctx.close()
+    autotune_rec = {"H": tH, "G": tG, "ms_pass_tuned": round(tms, 4), "ms_pass_builtin": round(ms_pass, 4)}
+    print(f"# pass autotune: kept H={tH} G={tG} {tms:.4f} ms per pass (built-in rule {ms_pass:.4f} ms)",
+          file=sys.stderr, flush=True)
+
     # ---- multi-RHS form: one solve for k right-hand sides sharing A (k = 64, C3 shapes)
     multi = None
     if args.multi > 0:
@@ -526,7 +539,7 @@ def main():
         "loop_GBps": None if loop_gbps is None else round(loop_gbps, 1),
         "iters": iters, "kw_evals": [inf.kw_evals for _, _, inf in infos],
         "phase_ms_last": [round(p, 3) for p in infos[-1][2].phase_ms],
-        "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy,
+        "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy, "pass_autotune": autotune_rec,
         "multi_rhs": multi,
         "mixed": mixed,
         "prony": prony,

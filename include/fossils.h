@@ -232,6 +232,24 @@ fs_status fs_residual_pass(fs_context ctx, int64_t m, int32_t n, const double* A
 fs_status fs_time_normal_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z,
                               double* v, int32_t repeats, double* ms_per_pass_host, double* ms_kernel_host);
 
+/* Autotuning of the fused pass over A (the refinement loop's kernel, the operator of
+ * eq:precond-normal).  Its two knobs are the tile height H (rows per work-group tile, held in
+ * registers between the products A z and A^T w; 64, 32, 16, 8 or 4, as far as the kernel is built
+ * for ceil(n H / 1024) column slots per lane) and the work-group count G (the schedule: a multiple of
+ * 8, the rows banded across the 8 XCDs, at most 2 x the compute units).  fs_tune_pass times every
+ * admissible (H, G) on the caller's A (m x n column-major, lda >= m; z and v device n-vectors) with
+ * `repeats` back-to-back passes each and keeps the fastest in the context, keyed by (n, floor(log2 m)):
+ * every later pass of that key on this context uses it (solves included).  v receives A^T (A z)
+ * from the kept configuration; *H_out, *G_out, *ms_out (each may be NULL) the kept pair and its time
+ * per pass.  FS_ERR_SHAPE when no fused configuration fits (n > 4096, or lda too large).
+ * fs_set_pass_tuning stores a pair directly (for instance from a saved cache), FS_ERR_INVALID_ARG
+ * when it is not admissible; fs_clear_pass_tuning drops all.  Results are the same up to the
+ * rounding of the partial sums, whatever the pair. */
+fs_status fs_tune_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z, double* v,
+                       int32_t repeats, int32_t* H_out, int32_t* G_out, double* ms_out);
+fs_status fs_set_pass_tuning(fs_context ctx, int64_t m, int32_t n, int32_t H, int32_t G);
+fs_status fs_clear_pass_tuning(fs_context ctx);
+
 /* x = R^{-1} y (transpose = 0, back substitution) or x = R^{-T} y (transpose = 1, forward
  * substitution) for upper-triangular R (ldr >= n); x may equal y.  n <= 15000. */
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,

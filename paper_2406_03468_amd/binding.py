@@ -128,6 +128,10 @@ _SIGS = [
     ("fs_trsv", c_int32, [c_vp, c_int32, c_vp, c_int64, c_int32, c_vp, c_vp]),
     ("fs_time_normal_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_int32,
                                       ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
+    ("fs_tune_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_int32,
+                               ctypes.POINTER(c_int32), ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    ("fs_set_pass_tuning", c_int32, [c_vp, c_int64, c_int32, c_int32, c_int32]),
+    ("fs_clear_pass_tuning", c_int32, [c_vp]),
 ]
 
 
@@ -435,3 +439,21 @@ def fs_time_normal_pass(ctx: Context, A, z, v, repeats: int = 20):
     _check(load().fs_time_normal_pass(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(z)),
                                       c_vp(_ptr(v)), int(repeats), ctypes.byref(t), ctypes.byref(tk)))
     return t.value, tk.value
+
+
+def fs_tune_pass(ctx: Context, A, z, v, repeats: int = 5):
+    """Time every admissible (tile height, work-group count) of the fused pass on A and keep the
+    fastest in the context for this (n, m-bucket); returns (H, G, ms per pass)."""
+    m, n = A.shape
+    H, G, ms = c_int32(0), c_int32(0), c_double(0.0)
+    _check(load().fs_tune_pass(ctx.h, int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(z)), c_vp(_ptr(v)),
+                               int(repeats), ctypes.byref(H), ctypes.byref(G), ctypes.byref(ms)))
+    return H.value, G.value, ms.value
+
+
+def fs_set_pass_tuning(ctx: Context, m: int, n: int, H: int, G: int):
+    _check(load().fs_set_pass_tuning(ctx.h, int(m), int(n), int(H), int(G)))
+
+
+def fs_clear_pass_tuning(ctx: Context):
+    _check(load().fs_clear_pass_tuning(ctx.h))

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <condition_variable>
+#include <map>
 #include <mutex>
 
 #include "../../include/fossils.h"
@@ -44,6 +45,11 @@ struct fs_context_s {
   hipStream_t cap_stream = nullptr;  // private stream for graph capture (created on first use)
   hipStream_t aux_stream = nullptr;  // second stream: the SVD of R beside the first refinement step
   hipEvent_t ev_aux = nullptr;       // (both created on first use)
+  // Fused-pass configurations picked by fs_tune_pass (or loaded with fs_set_pass_tuning), keyed
+  // by (n, floor(log2 m)); used by every pass of that shape instead of the built-in rule.
+  std::map<std::pair<int, int>, std::pair<int, int>> pass_tuned;  // -> (H, G)
+  bool pass_force = false;     // while tuning: every pass uses pass_force_cfg
+  int pass_force_H = 0, pass_force_G = 0;
 };
 
 // Cooperative kernels (QR, SVD) need every work-group of their grid resident at once.  Slots of a

@@ -296,8 +296,34 @@ fs_status fs_svd_triangular(fs_context ctx, int32_t n, const double* R, int64_t 
   return FS_OK;
 }
 
+// Tile heights the fused pass is built for at this n: L = ceil(n H / 1024) column slots per lane
+// must lie in the instantiated range of that height.
+static bool pass_tile_ok(int H, int n) {
+  const int64_t L = ((int64_t)n * H + 1023) / 1024;
+  switch (H) {
+    case 64: return L >= 1 && L <= 4;
+    case 32: return L >= 1 && L <= 8;
+    case 16: return L >= 1 && L <= 16;
+    case 8:
+    case 4: return L >= 5 && L <= 16;
+    default: return false;
+  }
+}
+static int m_bucket(int64_t m) {
+  int b = 0;
+  while ((int64_t(2) << b) <= m) ++b;
+  return b;  // floor(log2 m)
+}
+static bool pass_groups_ok(int G, int num_cu) { return G >= 8 && G % 8 == 0 && G <= 2 * num_cu; }
+
 static PassConfig pass_config(fs_context ctx, int64_t m, int32_t n, int64_t lda) {
   PassConfig cfg = fs_pass_config(m, n, ctx->num_cu);
+  if (ctx->pass_force) {
+    cfg = PassConfig{ctx->pass_force_H, ctx->pass_force_G};
+  } else if (!ctx->pass_tuned.empty()) {
+    const auto it = ctx->pass_tuned.find({n, m_bucket(m)});
+    if (it != ctx->pass_tuned.end()) cfg = PassConfig{it->second.first, it->second.second};
+  }
   // a cap on the fused pass's work-groups (multiples of 8 keep its XCD banding)
   if (cfg.H && ctx->pass_group_cap > 0 && cfg.G > ctx->pass_group_cap)
     cfg.G = std::max(8, ctx->pass_group_cap / 8 * 8);
@@ -385,6 +411,76 @@ fs_status fs_time_normal_pass(fs_context ctx, int64_t m, int32_t n, const double
   return FS_OK;
 }
 
+fs_status fs_tune_pass(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* z, double* v,
+                       int32_t repeats, int32_t* H_out, int32_t* G_out, double* ms_out) {
+  if (!ctx || !A || !z || !v) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < 1 || lda < m || repeats < 1) return FS_ERR_SHAPE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  struct ForceReset {  // the override ends on every exit path
+    fs_context c;
+    ~ForceReset() { c->pass_force = false; }
+  } force_reset{ctx};
+  const int nc = ctx->num_cu;
+  const int gs[4] = {std::max(8, nc / 2 / 8 * 8), std::max(8, nc * 3 / 4 / 8 * 8), std::max(8, nc / 8 * 8),
+                     std::max(8, 2 * nc / 8 * 8)};
+  double best = INFINITY;
+  int bH = 0, bG = 0;
+  hipEvent_t* ev = ctx->ev;
+  for (int H : {64, 32, 16, 8, 4}) {
+    if (!pass_tile_ok(H, n)) continue;
+    for (int G : gs) {
+      if (!pass_groups_ok(G, nc)) continue;
+      ctx->pass_force = true;
+      ctx->pass_force_H = H;
+      ctx->pass_force_G = G;
+      if (pass_config(ctx, m, n, lda).H != H) continue;  // (lda too large for the fused pass)
+      FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+      FS_TRY(run_pass(ctx, m, n, A, lda, z, nullptr, v, nullptr, nullptr, nullptr));  // warm-up
+      FS_HIP(hipEventRecord(ev[0], ctx->stream));
+      for (int r = 0; r < repeats; ++r) FS_TRY(run_pass(ctx, m, n, A, lda, z, nullptr, v, nullptr, nullptr, nullptr));
+      FS_HIP(hipEventRecord(ev[1], ctx->stream));
+      FS_HIP(hipEventSynchronize(ev[1]));
+      float t = 0;
+      FS_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+      const double ms = (double)t / repeats;
+      if (ms < best) {
+        best = ms;
+        bH = H;
+        bG = G;
+      }
+    }
+  }
+  ctx->pass_force = false;
+  if (bH == 0) return FS_ERR_SHAPE;  // no fused configuration at this shape
+  ctx->pass_tuned[{n, m_bucket(m)}] = {bH, bG};
+  FS_TRY(ensure_pass_ws(ctx, m, n, lda));
+  FS_TRY(run_pass(ctx, m, n, A, lda, z, nullptr, v, nullptr, nullptr, nullptr));  // v from the kept one
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  if (H_out) *H_out = bH;
+  if (G_out) *G_out = bG;
+  if (ms_out) *ms_out = best;
+  return FS_OK;
+}
+
+fs_status fs_set_pass_tuning(fs_context ctx, int64_t m, int32_t n, int32_t H, int32_t G) {
+  if (!ctx) return FS_ERR_INVALID_ARG;
+  if (n < 1 || m < 1) return FS_ERR_SHAPE;
+  if (!pass_tile_ok(H, n) || !pass_groups_ok(G, ctx->num_cu)) return FS_ERR_INVALID_ARG;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));  // (the workspace is sized per call; nothing in flight)
+  ctx->pass_tuned[{n, m_bucket(m)}] = {H, G};
+  return FS_OK;
+}
+
+fs_status fs_clear_pass_tuning(fs_context ctx) {
+  if (!ctx) return FS_ERR_INVALID_ARG;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->pass_tuned.clear();
+  return FS_OK;
+}
+
 size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts) {
   fs_options o;
   if (opts) o = *opts;
@@ -396,7 +492,8 @@ size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts) {
   b += 8 * d * k;                                                // sketch Y
   b += fs_qr_work_bytes(o.d, (int)k, 256) + fs_svd_work_bytes(n);
   b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 16 * N);  // V, U_R, vectors
-  b += 8 * ((size_t)cfg.G * N + cfg.G + 64) + sizeof(DevState) + 64;
+  const size_t gmax = std::max<size_t>((size_t)cfg.G, 512);  // (a tuned pass: up to 2 x 256 work-groups)
+  b += 8 * (gmax * N + gmax + 64) + sizeof(DevState) + 64;
   if (!cfg.H) b += 8 * (size_t)m;
   b += 16 * (size_t)m;  // the LSQR form's two m-vectors (counted for every method)
   return b;
