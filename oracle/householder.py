@@ -101,6 +101,77 @@ def qr_lstsq_lapack(A: np.ndarray, b: np.ndarray) -> np.ndarray:
     return sl.solve_triangular(R, Q.T @ b, lower=False)
 
 
+def _tsqr_r(M_of_rows, m: int, k: int, block_rows: int, workers: int) -> np.ndarray:
+    """Triangular factor (k x k) of an m x k matrix given by row blocks, by TSQR: LAPACK's
+    Householder QR (dgeqrf) of each block of rows, then the same on the stacked triangles until
+    one block remains."""
+    import scipy.linalg as sl
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
+    def leaf(i0, i1):
+        M = np.array(M_of_rows(i0, i1), dtype=np.float64, order="F", copy=True)
+        R = sl.qr(M, mode="r", overwrite_a=True, check_finite=False)[0]
+        return R[: min(k, i1 - i0)]
+
+    bounds = [(i, min(m, i + block_rows)) for i in range(0, m, block_rows)]
+    # one LAPACK thread per block, the blocks spread over the workers
+    with threadpool_limits(1), ThreadPoolExecutor(max(1, workers)) as ex:
+        Rs = list(ex.map(lambda bl: leaf(*bl), bounds))
+    while len(Rs) > 1:
+        stacked = np.vstack(Rs)
+        group = max(2, block_rows // k)
+        parts = [stacked[i:i + group * k] for i in range(0, stacked.shape[0], group * k)]
+        if len(parts) == 1:
+            Rs = [sl.qr(np.asfortranarray(parts[0]), mode="r", check_finite=False)[0][:k]]
+            break
+        with threadpool_limits(1), ThreadPoolExecutor(max(1, workers)) as ex:
+            Rs = list(ex.map(lambda p: sl.qr(np.asfortranarray(p), mode="r", check_finite=False)[0][:k], parts))
+    R = Rs[0]
+    if R.shape[0] < k:
+        R = np.vstack([R, np.zeros((k - R.shape[0], k))])
+    return np.triu(R)
+
+
+def qr_lstsq_tsqr(A: np.ndarray, B: np.ndarray, block_rows: int = 5000, workers: int = 0) -> np.ndarray:
+    """Householder-QR least squares for a tall A (m x n) and one or more right-hand sides B (m or
+    m x k), as the forward-error reference at sizes where the plain loop above is out of reach.
+
+    The augmented matrix [A B] is reduced to triangular form by TSQR (Demmel, Grigori, Hoemmen,
+    Langou, "Communication-optimal parallel and sequential QR and LU factorizations", 2012):
+    LAPACK's Householder QR of row blocks, then of the stacked triangles.  The result is the
+    triangle of a Householder QR of [A B] = Q [R T; 0 *], whose leading columns give R and T =
+    (Q^T B)[:n]; x = R^{-1} T.  A sequence of Householder reflections, so the solver keeps the
+    backward stability of Householder QR least squares (labelled "LAPACK TSQR" where reported).
+    """
+    import os
+
+    import scipy.linalg as sl
+
+    A = np.asarray(A)
+    Bm = np.asarray(B, dtype=np.float64)
+    vec = Bm.ndim == 1
+    if vec:
+        Bm = Bm[:, None]
+    m, n = A.shape
+    k = Bm.shape[1]
+    if m < n:
+        raise ValueError("qr_lstsq_tsqr expects m >= n")
+    workers = workers or min(16, os.cpu_count() or 1)
+    block_rows = max(block_rows, 2 * (n + k))
+
+    def rows(i0, i1):
+        M = np.empty((i1 - i0, n + k), order="F")
+        M[:, :n] = A[i0:i1]
+        M[:, n:] = Bm[i0:i1]
+        return M
+
+    Rt = _tsqr_r(rows, m, n + k, block_rows, workers)
+    X = sl.solve_triangular(Rt[:n, :n], Rt[:n, n:], lower=False, check_finite=False)
+    return X[:, 0] if vec else X
+
+
 # ---------------------------------------------------------------- complex least squares
 # The Prony problems of Section 5.2 are complex.  Textbook complex Householder QR: for x = A[k:, k]
 # the reflector H = I - 2 v v^H / (v^H v) with v = x + e^{i arg x_0} ||x|| e_1 (e^{i arg 0} = 1)

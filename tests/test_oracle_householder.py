@@ -108,3 +108,55 @@ def test_triangular_solvers():
     y = rng.standard_normal(9)
     assert np.allclose(R @ hh.back_substitution(R, y), y, atol=1e-13)
     assert np.allclose(R.T @ hh.forward_substitution_transposed(R, y), y, atol=1e-13)
+
+
+# ---------------------------------------------------------------- TSQR reference (large problems)
+
+def test_tsqr_exact_rational_integer_system():
+    """A tree of three levels (block_rows small) on an integer system: the exact rational LS
+    solution (normal equations in Fractions) to rounding."""
+    rng = np.random.default_rng(7)
+    A = rng.integers(-9, 10, size=(90, 4)).astype(float)
+    b = rng.integers(-9, 10, size=90).astype(float)
+    xr = np.array([float(v) for v in _rational_lstsq(A.tolist(), b.tolist())])
+    x = hh.qr_lstsq_tsqr(A, b, block_rows=10, workers=3)
+    assert np.max(np.abs(x - xr)) <= 1e3 * U * np.linalg.cond(A) * np.linalg.norm(xr)
+
+
+def test_tsqr_special_cases():
+    rng = np.random.default_rng(8)
+    a = rng.standard_normal(500)
+    b = rng.standard_normal(500)
+    x = hh.qr_lstsq_tsqr(a[:, None], b, block_rows=40)
+    assert abs(x[0] - (a @ b) / (a @ a)) <= 20 * U * abs(x[0])
+    Q = np.linalg.qr(rng.standard_normal((400, 6)))[0]
+    x = hh.qr_lstsq_tsqr(Q, b[:400], block_rows=30)
+    assert np.linalg.norm(x - Q.T @ b[:400]) <= 100 * U * np.linalg.norm(b[:400])
+
+
+def test_tsqr_triangle_reproduces_gram_matrix():
+    """R of the stacked tree satisfies R^T R = M^T M to the backward error of Householder QR."""
+    rng = np.random.default_rng(9)
+    M = rng.standard_normal((700, 9)) @ np.diag(10.0 ** -np.arange(9))
+    R = hh._tsqr_r(lambda i0, i1: M[i0:i1], 700, 9, 40, 4)
+    assert np.allclose(R, np.triu(R))
+    assert np.linalg.norm(R.T @ R - M.T @ M) <= 700 * U * np.linalg.norm(M) ** 2
+    # singular values are those of M (QR is an orthogonal reduction)
+    assert np.allclose(np.linalg.svd(R, compute_uv=False), np.linalg.svd(M, compute_uv=False), rtol=1e-10, atol=0)
+
+
+def test_tsqr_matches_plain_householder_and_multi_rhs():
+    """On an ill-conditioned problem the blocked reference and the plain loop agree within the
+    Wedin scale; several right-hand sides give each column's single solve."""
+    from synth import make_problem
+    P = make_problem(3000, 25, 1e9, 1e-5, seed=2)
+    x = hh.qr_lstsq(P.A, P.b)
+    xt = hh.qr_lstsq_tsqr(P.A, P.b, block_rows=200, workers=4)
+    scale = 1e9 * np.linalg.norm(P.x_true) * U + 1e18 * 1e-5 * U
+    assert np.linalg.norm(x - xt) <= 20 * scale
+    B = np.column_stack([P.b, 2.0 * P.b, P.A @ P.x_true])
+    X = hh.qr_lstsq_tsqr(P.A, B, block_rows=200, workers=4)
+    for j in range(3):
+        assert np.linalg.norm(X[:, j] - hh.qr_lstsq_tsqr(P.A, B[:, j], block_rows=200)) <= 20 * scale * (1 + j)
+    # consistent right-hand side: forward error at the kappa u level
+    assert np.linalg.norm(X[:, 2] - P.x_true) <= 100 * 1e9 * U * np.linalg.norm(P.x_true)
