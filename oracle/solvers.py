@@ -29,6 +29,7 @@ rank-deficient sketch always falls back to the truncated SVD preconditioner (Alg
 from __future__ import annotations
 
 import math
+import time
 from dataclasses import dataclass, field
 from typing import Optional
 
@@ -212,6 +213,8 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
         z = np.zeros(n)
         return Result(x=z, iters=[0, 0], flags=0, normest=0.0, condest=0.0, rank=n, be_sk=0.0, x0=z)
 
+    # Wall-clock marks of the phases (reported in info["phase_s"]; no effect on the arithmetic).
+    marks = [("start", time.perf_counter())]
     # Alg 4: normalize columns.
     dcol = column_norms(A) if opts.column_scaling else np.ones(n)
     As = A / dcol
@@ -239,6 +242,7 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
     else:
         raise ValueError("precision must be 'fp64' or 'mixed'")
     SA, Sb = Y[:, :n], Y[:, n]
+    marks.append(("sketch", time.perf_counter()))
 
     # Factor the sketch.
     if opts.precond == "qr":
@@ -253,6 +257,7 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
         R = t = None
     else:
         raise ValueError("precond must be 'qr' or 'svd'")
+    marks.append(("factor", time.perf_counter()))
     normest = float(sig_full[0])
     condest = float(sig_full[0] / sig_full[-1]) if sig_full[-1] > 0 else math.inf
 
@@ -297,6 +302,7 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
     def apply_M(y):
         return pre.PT(As.T @ (As @ pre.P(y)))
 
+    marks.append(("x0", time.perf_counter()))
     x = x0.copy()
     iters, xs, cs = [], [], []
     be_sk = math.nan
@@ -387,12 +393,14 @@ def solve(A, b, method="fossils", opts: Optional[Options] = None) -> Result:
         iters.append(it)
         xs.append(x / dcol)
         converged_last = converged
+        marks.append((f"step{i}", time.perf_counter()))
     if opts.steps == 2 and opts.fixed_q == 0 and not converged_last:
         flags |= FLAG_NOT_CONVERGED
     return Result(x=x / dcol, iters=iters, flags=flags, normest=normest, condest=condest, rank=rank,
                   be_sk=float(be_sk), x0=x0 / dcol, xs=xs, cs=cs,
                   info={"alpha": alpha, "beta": beta, "eta": eta, "d": dsk, "theta": theta,
-                        "fro": fro, "dcol": dcol, "thr_first": thr_first})
+                        "fro": fro, "dcol": dcol, "thr_first": thr_first,
+                        "phase_s": {marks[k][0]: marks[k][1] - marks[k - 1][1] for k in range(1, len(marks))}})
 
 
 def fossils(A, b, opts: Optional[Options] = None) -> Result:
