@@ -14,10 +14,11 @@ Printed as one JSON line:
   loop_GBps      the same for the refinement loop alone (passes inside the two steps / their time);
   roofline       the fused A^T(A z) kernel timed live with HIP events on the library's stream,
                  against the 8 TB/s HBM peak;
-  cpu_baseline   the CPU oracle's heavy-ball iterations (oracle.solvers.polyak with the oracle's
-                 normal_pass and substitutions, numpy float64) on the same 1e6 x 1000 matrix, in GB/s
-                 of algorithmic bytes;
-  accuracy       relative backward error (Karlson-Walden, known SVD, long double) per problem;
+  cpu_baseline   the CPU oracle's own complete FOSSILS solve (oracle.solvers.fossils, Algorithm 4)
+                 on the same bytes as the first timed problem, on the host's cores, in GB/s of the
+                 same algorithmic bytes, with its phase times; plus its heavy-ball loop at one thread;
+  accuracy       relative backward error (Karlson-Walden, known SVD, long double) and forward error
+                 per problem, beside Householder QR's forward error on the same bytes (LAPACK TSQR);
   pass_autotune  fs_tune_pass at this shape (every admissible tile height and work-group count of
                  the fused pass timed, the fastest kept) against the built-in rule;
   multi_rhs, mixed, prony, serving
@@ -55,7 +56,7 @@ def parse():
     ap.add_argument("--precond", default="svd", choices=["qr", "svd"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-check", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=300)
+    ap.add_argument("--cpu-iters", type=int, default=5, help="heavy-ball iterations of the 1-thread CPU sample")
     ap.add_argument("--pass-repeats", type=int, default=20)
     ap.add_argument("--multi", type=int, default=64, help="right-hand sides of the multi-RHS line (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=2048, help="requests of the serving line (0: skip)")
@@ -63,6 +64,8 @@ def parse():
                     help="profiling mode: a 1 GiB device copy (counter calibration) then the fused pass "
                          "A^T(A z) at m=1e6, n=1000, --pass-repeats times; prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--slot-sweep", type=lambda v: [int(t) for t in v.split(",") if t], default=[1, 2, 4, 8, 16],
+                    help="slot counts of the saturated-throughput sweep (comma separated; empty: skip)")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-precision line")
     ap.add_argument("--no-prony", dest="prony", action="store_false", help="skip the complex (Prony) line")
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
@@ -135,6 +138,32 @@ def serve_bench(ctx, args, dev):
                    if mx and binding.batched_poll(srv, t)[2].flags & binding.FS_FLAG_FP64_SKETCH)
         print(f"# serving saturated: {R} requests in {sat_s:.2f}s = {thr:.1f} solves/s, errors {bad}, "
               f"mean service {service_ms:.2f} ms", file=sys.stderr, flush=True)
+        # the plain form on the same stream: one solve after another on the caller's context (the
+        # single-solve defaults, SVD beside the first step), no server
+        nplain = min(R, 512)
+        for (P, meth, mx), x in zip(reqs[:4], outs[:4]):
+            (binding.spir_solve if meth == 1 else binding.fossils_solve)(ctx, P.A, P.b, x,
+                                                                          opt_mixed[id(P)] if mx else None)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        plain_bad = 0
+        for (P, meth, mx), x in zip(reqs[:nplain], outs[:nplain]):
+            st_, _ = (binding.spir_solve if meth == 1 else binding.fossils_solve)(ctx, P.A, P.b, x,
+                                                                                  opt_mixed[id(P)] if mx else None)
+            plain_bad += int(st_ < 0)
+        plain_s = time.perf_counter() - tp
+        plain_thr = nplain / plain_s
+        plain_be = []
+        if not args.no_check:
+            from oracle import backward_error as be
+            for i in (0, nplain // 2 + 1):
+                P, _, _ = reqs[i]
+                A_h, b_h, x_h = P.A.cpu().numpy(), P.b.cpu().numpy(), outs[i].cpu().numpy()
+                fro = np.sqrt(np.sum(A_h * A_h))
+                plain_be.append(float(be.kw_known_svd(A_h, b_h, x_h, P.sigma, P.V, fro / np.linalg.norm(b_h)) / fro))
+        print(f"# plain (no server, one solve at a time): {nplain} requests in {plain_s:.2f}s = {plain_thr:.1f} solves/s, "
+              f"BE sample {plain_be}", file=sys.stderr, flush=True)
+
         def poisson(frac, nreq):
             """p50 / p99 latency (ms) of nreq requests arriving as a Poisson stream at frac x saturated."""
             lam_ = frac * thr
@@ -180,7 +209,29 @@ def serve_bench(ctx, args, dev):
             print(f"# serving accuracy sample: BE {bes}", file=sys.stderr, flush=True)
     finally:
         srv.close()
-    return {"requests": R, "slots": args.serve_slots, "pool": len(pool), "saturated_solves_per_s": round(thr, 1),
+    # saturated throughput against the slot count, on the first 512 requests of the same stream
+    slot_sweep = []
+    for ns in args.slot_sweep:
+        sv = binding.Server(ctx, hbm_budget=32 << 30, max_slots=ns)
+        try:
+            nreq = min(R, 512)
+            wt = [binding.batched_submit(sv, P.A, P.b, x, method=meth, opts=opt_mixed[id(P)] if mx else None)
+                  for (P, meth, mx), x in zip(reqs[:2 * ns], outs[:2 * ns])]
+            for t in wt:
+                binding.fs_server_wait(sv, t)
+            ts = time.perf_counter()
+            tks = [binding.batched_submit(sv, P.A, P.b, x, method=meth, opts=opt_mixed[id(P)] if mx else None)
+                   for (P, meth, mx), x in zip(reqs[:nreq], outs[:nreq])]
+            for t in tks:
+                binding.fs_server_wait(sv, t)
+            rate = nreq / (time.perf_counter() - ts)
+        finally:
+            sv.close()
+        slot_sweep.append({"slots": ns, "solves_per_s": round(rate, 1)})
+        print(f"# serving slot sweep: {ns} slots {rate:.1f} solves/s", file=sys.stderr, flush=True)
+    return {"requests": R, "slots": args.serve_slots, "plain_solves_per_s": round(plain_thr, 1),
+            "plain_requests": nplain, "plain_errors": plain_bad, "plain_be_sample": plain_be,
+            "served_over_plain": round(thr / plain_thr, 3), "slot_sweep": slot_sweep, "pool": len(pool), "saturated_solves_per_s": round(thr, 1),
             "saturated_GBps_of_A": round(gbytes / sat_s, 1), "mean_service_ms": round(service_ms, 2),
             "poisson_rate_per_s": round(lam, 1),
             "p50_ms": round(p50, 2), "p99_ms": round(p99, 2), "load_sweep": sweep, "errors": bad, "be_sample": bes,
@@ -337,6 +388,68 @@ def prony_bench(ctx, args, dev):
     return rec
 
 
+def cpu_baseline(args, P, Ah):
+    """The oracle's FOSSILS on the bytes of the first timed problem (1e6 x 1000, kappa 1e10, ||r|| 1e-10):
+    oracle.solvers.fossils with Algorithm 4's SVD preconditioner (the GPU default), every phase --
+    column scaling, sketch S [A_s b], SVD of S A_s, sketch-and-solve, both refinement steps -- on the
+    host's cores (numpy + OpenBLAS threads; the sparse sketch product is single-threaded scipy).
+    value = the same algorithmic bytes as the GPU line (passes over A x m n 8) / solve time.  Then
+    the oracle's heavy-ball loop (oracle.solvers.polyak over normal_pass and two substitutions) for
+    --cpu-iters iterations at one BLAS thread."""
+    import platform
+
+    import numpy as np
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import householder as hh
+    from oracle import solvers
+
+    bh = P.b.cpu().numpy()
+    blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+    threads = max((i["num_threads"] for i in blas), default=1)
+    model = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    t = time.perf_counter()
+    res = solvers.fossils(Ah, bh, solvers.Options(precond="svd"))
+    dt = time.perf_counter() - t
+    kw = (res.iters[1] - 1) // 5 + 1 if res.iters[1] > 0 else 0
+    passes = 1 + 2 + res.iters[0] + res.iters[1] + kw
+    gbps = passes * M * N * 8 / dt / 1e9
+    phases = {k: round(v, 2) for k, v in res.info["phase_s"].items()}
+    print(f"# cpu oracle FOSSILS: {dt:.1f} s, iters {res.iters}, {passes} passes, {gbps:.1f} GB/s, phases {phases}",
+          file=sys.stderr, flush=True)
+    # the loop at one thread
+    q = args.cpu_iters
+    rng = np.random.default_rng(0)
+    R = np.triu(rng.standard_normal((N, N))) + 4 * np.sqrt(N) * np.eye(N)  # stand-in triangle (cost only)
+    c = rng.standard_normal(N)
+
+    def apply_M(y):
+        return hh.forward_substitution_transposed(R, solvers.normal_pass(Ah, hh.back_substitution(R, y)))
+
+    with threadpool_limits(1):
+        t1 = time.perf_counter()
+        solvers.polyak(apply_M, c, 0.84, 0.083, q + 1)
+        dt1 = time.perf_counter() - t1
+    gbps1 = q * M * N * 8 / dt1 / 1e9
+    print(f"# cpu oracle loop at 1 thread: {q} iterations in {dt1:.1f} s = {gbps1:.2f} GB/s", file=sys.stderr,
+          flush=True)
+    return {"value": round(gbps, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"one complete oracle FOSSILS solve (oracle.solvers.fossils, Algorithm 4, SVD preconditioner) "
+                       f"on the first timed problem's bytes ({M}x{N}, kappa 1e10, ||r|| 1e-10): {dt:.1f} s, "
+                       f"iters {res.iters}, {passes} passes over A; GB/s = passes x m n 8 / solve time"),
+            "seconds": round(dt, 2), "phase_s": phases, "iters": list(res.iters), "passes": passes,
+            "cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "blas_threads": int(threads),
+            "one_thread_loop": {"iterations": q, "seconds": round(dt1, 2), "GBps": round(gbps1, 3),
+                                "sample": "oracle.solvers.polyak over normal_pass on the same matrix plus two "
+                                          "substitutions with a stand-in triangle, one BLAS thread"}}
+
+
 def main():
     args = parse()
     if args.pass_only:
@@ -469,6 +582,7 @@ def main():
         Ah = probs[0].A.cpu().numpy()  # (m, n) Fortran-ordered view of the device bytes
     if not args.no_check:
         from oracle import backward_error as be
+        from oracle import householder as hh
         accuracy = []
         solved = sorted({i for i, _, _ in infos})
         for i, P in enumerate(probs):
@@ -481,11 +595,15 @@ def main():
             fro = np.sqrt(np.sum(A_i * A_i))
             bek = be.kw_known_svd(A_i, b_i, x_i, P.sigma, P.V, theta) / fro
             fe = float(np.linalg.norm(x_i - P.x_true) / np.linalg.norm(P.x_true))
+            t_q = time.perf_counter()
+            xq = hh.qr_lstsq_tsqr(A_i, b_i)
+            t_q = time.perf_counter() - t_q
+            fe_qr = float(np.linalg.norm(xq - P.x_true) / np.linalg.norm(P.x_true))
             u = 2.0**-52
-            wedin = KAPPA * (1 + KAPPA * P.resid_norm / np.linalg.norm(x_i)) * u
-            accuracy.append({"resid_norm": P.resid_norm, "be": float(bek), "fe": fe, "wedin_scale": float(wedin)})
-            print(f"# accuracy problem {i}: BE {bek:.3e} FE {fe:.3e} (Wedin scale {wedin:.3e})", file=sys.stderr,
-                  flush=True)
+            accuracy.append({"resid_norm": P.resid_norm, "be": float(bek), "fe": fe, "fe_qr": fe_qr,
+                             "fe_ratio": fe / max(fe_qr, KAPPA * u), "qr_reference": "LAPACK TSQR of [A b]"})
+            print(f"# accuracy problem {i}: BE {bek:.3e} FE {fe:.3e} FE_QR {fe_qr:.3e} (TSQR {t_q:.1f} s)",
+                  file=sys.stderr, flush=True)
             del A_i
         if multi_check is not None:  # two columns of the multi-RHS solve, known-SVD KW
             PM, Bm, Xm = multi_check
@@ -501,29 +619,8 @@ def main():
             print(f"# multi-RHS accuracy (columns 0, k-1): BE {bes}", file=sys.stderr, flush=True)
             del A_m
 
-    # ---- CPU baseline: the oracle's heavy-ball iterations (Algorithm 5) on the same problem
-    cpu = None
-    if not args.no_cpu:
-        from oracle import householder as hh
-        from oracle import solvers
-        q = args.cpu_iters
-        rng = np.random.default_rng(0)
-        # timing stand-in for the sketch's R factor (values do not affect the cost of an iteration)
-        R = np.triu(rng.standard_normal((N, N))) + 4 * np.sqrt(N) * np.eye(N)
-        c = rng.standard_normal(N)
-
-        def apply_M(y):  # P^T A^T A P y with P = R^{-1}, exactly as in the oracle's refinement loop
-            return hh.forward_substitution_transposed(R, solvers.normal_pass(Ah, hh.back_substitution(R, y)))
-
-        threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-        t = time.perf_counter()
-        solvers.polyak(apply_M, c, 0.84, 0.083, q + 1)
-        dt = time.perf_counter() - t
-        cpu_gbps = q * bytes_per_pass / dt / 1e9
-        cpu = {"value": round(cpu_gbps, 3), "unit": "GB/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"{q} heavy-ball iterations (oracle.solvers.polyak: normal_pass on the full {M}x{N} "
-                         f"matrix + two substitutions with an {N}x{N} triangular R) in {dt:.1f} s; "
-                         f"GB/s = algorithmic bytes {q} x m n 8 / time", "seconds": round(dt, 2)}
+    # ---- CPU baseline: the oracle's own FOSSILS on the same bytes (host cores), then its loop at 1 thread
+    cpu = cpu_baseline(args, probs[0], Ah) if not args.no_cpu else None
 
     iters = [list(inf.iters) for _, _, inf in infos]
     out = {

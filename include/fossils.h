@@ -260,7 +260,11 @@ fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32
 /* A solve request.  A (m x n, lda >= m), b (m) and x (n) are device arrays owned by the caller;
  * they must stay valid (and A, b unchanged) until batched_poll reports the ticket done.  method:
  * FS_METHOD_FOSSILS, FS_METHOD_SPIR or FS_METHOD_SPIR_LSQR.  opts may be NULL (defaults); it is
- * copied at submission. */
+ * copied at submission (opts->precision = FS_MIXED gives the mixed-precision form with A rounded to
+ * FP32 as it is read).  stream: the HIP stream on which the caller produced A and b (NULL: the null
+ * stream); batched_submit records an event on it, and the solve's kernels wait for that event, so
+ * work the caller enqueued there before the submission is complete before the solve reads A or b.
+ * When the ticket is done, x has been written and the solve's stream has drained. */
 enum { FS_METHOD_FOSSILS = 0, FS_METHOD_SPIR = 1, FS_METHOD_SPIR_LSQR = 2 };
 typedef struct {
   int32_t method;
@@ -271,15 +275,22 @@ typedef struct {
   const double* b;
   double* x;
   const fs_options* opts;
+  void* stream;
 } fs_request;
 
-/* A server on the device of ctx: max_slots worker slots (1..16), each with its own stream and
- * workspace, take requests from one FIFO queue as they free up (continuous batching), so the
- * passes of different solves overlap on the GPU; the cooperative QR/SVD kernels of different slots
- * are serialized (a cooperative grid must be fully resident).  hbm_budget bounds the workspace:
- * each slot may use hbm_budget / max_slots bytes, and a request whose workspace footprint exceeds
- * that share is refused at submission with FS_ERR_TOO_LARGE.  With more than one slot the solves
- * run in the serial order (opts->overlap_svd is treated as 0): the slots already share the GPU. */
+/* A server on the device of ctx (continuous batching, the serving form of the solvers): max_slots
+ * worker slots (1..16), each a host thread with its own stream and workspace, take requests from
+ * one FIFO queue as they free up, so the passes of different solves overlap on the GPU; the
+ * cooperative QR/SVD grids of different slots reserve their work-groups from one device-wide
+ * budget (a cooperative grid must be fully resident).
+ * Admission is against a device-wide ledger of hbm_budget workspace bytes: it charges each slot the
+ * workspace it holds between requests plus, while a request runs, the further growth that
+ * request's footprint allows.  The head of the queue starts on a free slot once its growth fits
+ * the ledger; until then slots give their idle workspace back (fs_context_trim) and the request
+ * waits, so requests are admitted in arrival order as memory frees up.  A request whose footprint
+ * alone exceeds hbm_budget is refused at submission with FS_ERR_TOO_LARGE.  With more than one slot
+ * the solves run in the serial order (opts->overlap_svd is treated as 0): the slots already share
+ * the GPU. */
 fs_status fs_server_create(fs_context ctx, size_t hbm_budget, int32_t max_slots, fs_server* out);
 /* Finishes every queued request, then frees the slots. */
 fs_status fs_server_destroy(fs_server srv);
@@ -293,8 +304,19 @@ fs_status fs_server_wait(fs_server srv, uint64_t ticket);
 /* Seconds on the server's steady clock at submission, start on a slot and completion (-1 if not
  * yet reached). */
 fs_status fs_server_ticket_times(fs_server srv, uint64_t ticket, double* submit_s, double* start_s, double* finish_s);
-/* Workspace bytes one slot needs for an m x n solve with options opts (NULL: defaults). */
+/* Ledger of a server: bytes charged now, the most charged at any time, and hbm_budget (each
+ * pointer may be NULL).  The charge never exceeds hbm_budget. */
+fs_status fs_server_memory(fs_server srv, size_t* used, size_t* peak, size_t* budget);
+/* Footprint the server charges for an m x n request with options opts (NULL: defaults). */
+fs_status fs_server_request_footprint(fs_server srv, int64_t m, int32_t n, const fs_options* opts, size_t* bytes);
+/* Upper bound of the workspace bytes one single-right-hand-side solve (fossils_solve, spir_solve,
+ * spir_lsqr_solve, fossils_solve_mixed) of an m x n problem with options opts (NULL: defaults)
+ * grows a context to, on a GPU with 256 compute units. */
 size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts);
+/* Device bytes of workspace a context holds now (it grows to the largest problem seen). */
+fs_status fs_context_workspace(fs_context ctx, size_t* bytes);
+/* Frees a context's workspace (after draining its stream); the next solve allocates again. */
+fs_status fs_context_trim(fs_context ctx);
 
 #ifdef __cplusplus
 }

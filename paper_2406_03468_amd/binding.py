@@ -69,7 +69,7 @@ class FsInfo(ctypes.Structure):
 
 class FsRequest(ctypes.Structure):
     _fields_ = [("method", c_int32), ("m", c_int64), ("n", c_int32), ("A", c_vp), ("lda", c_int64), ("b", c_vp),
-                ("x", c_vp), ("opts", ctypes.POINTER(FsOptions))]
+                ("x", c_vp), ("opts", ctypes.POINTER(FsOptions)), ("stream", c_vp)]
 
 
 FS_METHOD_FOSSILS = 0
@@ -116,6 +116,12 @@ _SIGS = [
     ("fs_server_ticket_times", c_int32, [c_vp, c_uint64, ctypes.POINTER(c_double), ctypes.POINTER(c_double),
                                          ctypes.POINTER(c_double)]),
     ("fs_solve_footprint", ctypes.c_size_t, [c_int64, c_int32, ctypes.POINTER(FsOptions)]),
+    ("fs_server_memory", c_int32, [c_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t)]),
+    ("fs_server_request_footprint", c_int32, [c_vp, c_int64, c_int32, ctypes.POINTER(FsOptions),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    ("fs_context_workspace", c_int32, [c_vp, ctypes.POINTER(ctypes.c_size_t)]),
+    ("fs_context_trim", c_int32, [c_vp]),
     ("sketch_create", c_int32, [c_vp, c_int64, c_int32, c_int32, c_uint64, ctypes.POINTER(c_vp)]),
     ("sketch_destroy", c_int32, [c_vp]),
     ("sketch_indices", c_int32, [c_vp, c_int64, c_int64, c_vp, c_vp]),
@@ -322,10 +328,17 @@ class Server:
             pass
 
 
-def batched_submit(srv: Server, A, b, x, method: int = FS_METHOD_FOSSILS, opts: Optional[FsOptions] = None) -> int:
+def batched_submit(srv: Server, A, b, x, method: int = FS_METHOD_FOSSILS, opts: Optional[FsOptions] = None,
+                   stream=None) -> int:
+    """Enqueue a solve; it starts after the work already enqueued on `stream` (default: torch's
+    current stream on A's device), which is where A and b were produced."""
     m, n = A.shape
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream(A.device)
+    sh = stream if isinstance(stream, int) else stream.cuda_stream
     req = FsRequest(int(method), int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(x)),
-                    ctypes.pointer(opts) if opts is not None else None)
+                    ctypes.pointer(opts) if opts is not None else None, c_vp(sh or None))
     t = c_uint64(0)
     _check(load().batched_submit(srv.h, ctypes.byref(req), ctypes.byref(t)))
     srv._keep[t.value] = (A, b, x, opts)
@@ -354,6 +367,30 @@ def fs_server_ticket_times(srv: Server, ticket: int):
 
 def fs_solve_footprint(m: int, n: int, opts: Optional[FsOptions] = None) -> int:
     return int(load().fs_solve_footprint(int(m), int(n), ctypes.byref(opts) if opts is not None else None))
+
+
+def fs_server_memory(srv: Server):
+    """(used, peak, budget) bytes of the server's workspace ledger."""
+    u, p, b_ = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().fs_server_memory(srv.h, ctypes.byref(u), ctypes.byref(p), ctypes.byref(b_)))
+    return u.value, p.value, b_.value
+
+
+def fs_server_request_footprint(srv: Server, m: int, n: int, opts: Optional[FsOptions] = None) -> int:
+    out = ctypes.c_size_t()
+    _check(load().fs_server_request_footprint(srv.h, int(m), int(n), ctypes.byref(opts) if opts is not None else None,
+                                              ctypes.byref(out)))
+    return out.value
+
+
+def fs_context_workspace(ctx: Context) -> int:
+    out = ctypes.c_size_t()
+    _check(load().fs_context_workspace(ctx.h, ctypes.byref(out)))
+    return out.value
+
+
+def fs_context_trim(ctx: Context):
+    _check(load().fs_context_trim(ctx.h))
 
 
 class Sketch:

@@ -17,10 +17,13 @@ constexpr double FS_U_ROUND = 2.220446049250313e-16;
 // Mixed precision: the sketch of the FP32 copy is accepted while u32 condest <= 2 (condest <= ~3.4e7).
 constexpr double FS_MIXED_COND_FACTOR = 5.9604644775390625e-08;
 constexpr double FS_MIXED_DISTORTION = 2.0;
+// Size of the device array behind fossils_solve_noalloc (per GPU, for the life of the process).
+constexpr size_t FS_NOALLOC_SCRATCH_BYTES = size_t(256) << 20;
 
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool fixed = false;  // a slice of caller-provided memory: never reallocated or freed by the library
 };
 
 struct Workspace {
@@ -101,6 +104,18 @@ struct fs_sketch_s {
 // Grow-only device buffer (the caller synchronizes the stream before growing).
 fs_status fs_grow(DevBuf& b, size_t bytes);
 void fs_free_buf(DevBuf& b);
+size_t fs_workspace_bytes(Workspace& w);  // device bytes the workspace holds
+void fs_workspace_free(Workspace& w);     // frees every buffer (nothing in flight may use them)
+size_t fs_solve_footprint_cu(int64_t m, int32_t n, const fs_options& o, int num_cu);
+// Bytes of the fixed workspace a FOSSILS solve in the serial order (overlap_svd 0, graph_sweeps 0)
+// needs; with base != nullptr, also points the buffers of w at consecutive 256-byte aligned slices
+// of [base, base + the returned size) (marked fixed).
+size_t fs_carve_workspace(Workspace& w, unsigned char* base, int64_t m, int32_t n, const fs_options& o, int num_cu);
+// fossils_solve on a workspace of fixed slices (fs_carve_workspace) of caller-provided device memory:
+// nothing is allocated; opts must have overlap_svd = 0 and graph_sweeps = 0.
+fs_status fs_fossils_solve_fixed(fs_context ctx, unsigned char* base, size_t cap, int64_t m, int32_t n,
+                                 const double* A, int64_t lda, const double* b, double* x, const fs_options& opts,
+                                 fs_info* info);
 fs_status fs_validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x);
 fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o);
 inline bool fs_idx16_ok(int d) { return d <= 32767; }

@@ -50,6 +50,7 @@ fs_status validate_options(int64_t m, int32_t n, const fs_options& o) { return f
 fs_status fs_grow(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return FS_OK;
+  if (b.fixed) return FS_ERR_TOO_LARGE;  // a fixed slice is never reallocated
   if (b.p) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
@@ -64,9 +65,26 @@ fs_status fs_grow(DevBuf& b, size_t bytes) {
 }
 
 void fs_free_buf(DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+  if (b.p && !b.fixed) (void)hipFree(b.p);
   b.p = nullptr;
   b.bytes = 0;
+  b.fixed = false;
+}
+
+std::vector<DevBuf*> fs_workspace_buffers(Workspace& w) {
+  return {&w.idx, &w.Y,       &w.colnorm2, &w.dinv,  &w.qrwork, &w.svdwork, &w.sigma, &w.V,    &w.UR,
+          &w.partial, &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate,
+          &w.lsqr, &w.hist, &w.cplx};
+}
+
+size_t fs_workspace_bytes(Workspace& w) {
+  size_t t = 0;
+  for (DevBuf* b : fs_workspace_buffers(w)) t += b->bytes;
+  return t;
+}
+
+void fs_workspace_free(Workspace& w) {
+  for (DevBuf* b : fs_workspace_buffers(w)) fs_free_buf(*b);
 }
 
 fs_status fs_validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x) {
@@ -91,6 +109,55 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   if (o.overlap_svd != 0 && o.overlap_svd != 1) return FS_ERR_INVALID_ARG;
   (void)m;
   return FS_OK;
+}
+
+// Upper bound of the workspace one single-right-hand-side solve (FOSSILS, SPIR, LSQR; FP64 or mixed)
+// grows to on a GPU with num_cu compute units: every buffer solve() sizes, at its largest.
+size_t fs_solve_footprint_cu(int64_t m, int32_t n, const fs_options& o, int num_cu) {
+  if (n < 1 || m < n || o.d < n || o.zeta < 1) return 0;
+  const size_t d = (size_t)o.d, k = (size_t)n + 1, N = (size_t)n;
+  size_t b = (size_t)m * o.zeta * (fs_idx16_ok(o.d) ? 2 : 4);  // index stream
+  b += 8 * d * k;                                                // sketch Y
+  b += fs_qr_work_bytes(o.d, (int)k, num_cu) + fs_svd_work_bytes(n);
+  b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 16 * N);  // V, U_R, vectors
+  const size_t gmax = std::max<size_t>(2 * (size_t)num_cu, 512);    // fused-pass partials (tuned: up to 2 per CU)
+  b += 8 * (gmax * N + gmax + 64) + sizeof(DevState) + 64;
+  b += 8 * (size_t)m;   // the unfused pass's row scratch (a leading dimension too large for 32-bit offsets)
+  b += 16 * (size_t)m;  // the LSQR form's two m-vectors (counted for every method)
+  if (o.overlap_svd) b += 8 * ((size_t)o.max_inner * N + (size_t)o.max_inner + 8);  // first-step history
+  return b;
+}
+
+size_t fs_carve_workspace(Workspace& w, unsigned char* base, int64_t m, int32_t n, const fs_options& o, int num_cu) {
+  const size_t d = (size_t)o.d, k = (size_t)n + 1, N = (size_t)n;
+  const size_t gmax = std::max<size_t>(2 * (size_t)num_cu, 512);
+  size_t off = 0;
+  auto slice = [&](DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (base) {
+      b.p = base + off;
+      b.bytes = bytes;
+      b.fixed = true;
+    }
+    off += (bytes + 255) / 256 * 256;
+  };
+  // every buffer solve() sizes for FOSSILS in the serial order, at the size it asks for
+  slice(w.idx, (size_t)m * o.zeta * (fs_idx16_ok(o.d) ? 2 : 4));
+  slice(w.Y, 8 * d * k);
+  slice(w.colnorm2, 8 * (N + 1));
+  slice(w.dinv, 8 * N);
+  slice(w.qrwork, fs_qr_work_bytes(o.d, (int)k, num_cu));
+  slice(w.svdwork, fs_svd_work_bytes(n));
+  slice(w.sigma, 8 * N);
+  slice(w.V, 8 * N * N);
+  slice(w.UR, 8 * N * N);
+  slice(w.gemvpart, 8 * N * ((N + 63) / 64 + 1));
+  slice(w.vecs, 8 * 16 * N);
+  slice(w.state, sizeof(DevState) + 64);
+  slice(w.partial, 8 * gmax * N);
+  slice(w.pr2, 8 * gmax + 64);
+  slice(w.wscratch, 8 * (size_t)m);
+  return off;
 }
 
 extern "C" {
@@ -173,11 +240,7 @@ fs_status fs_context_destroy(fs_context c) {
   if (!c) return FS_ERR_INVALID_ARG;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  Workspace& w = c->ws;
-  for (DevBuf* b : {&w.idx, &w.Y, &w.colnorm2, &w.dinv, &w.qrwork, &w.svdwork, &w.sigma, &w.V, &w.UR, &w.partial,
-                    &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate, &w.lsqr,
-                    &w.hist, &w.cplx})
-    free_buf(*b);
+  fs_workspace_free(c->ws);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->aux_stream) {
     (void)hipStreamSynchronize(c->aux_stream);
@@ -485,18 +548,22 @@ size_t fs_solve_footprint(int64_t m, int32_t n, const fs_options* opts) {
   fs_options o;
   if (opts) o = *opts;
   else if (fs_options_default(m, n, &o) != FS_OK) return 0;
-  if (n < 1 || m < n || o.d < n) return 0;
-  const size_t d = (size_t)o.d, k = (size_t)n + 1, N = (size_t)n;
-  const PassConfig cfg = fs_pass_config(m, n, 256);
-  size_t b = (size_t)m * o.zeta * (fs_idx16_ok(o.d) ? 2 : 4);  // index stream
-  b += 8 * d * k;                                                // sketch Y
-  b += fs_qr_work_bytes(o.d, (int)k, 256) + fs_svd_work_bytes(n);
-  b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 16 * N);  // V, U_R, vectors
-  const size_t gmax = std::max<size_t>((size_t)cfg.G, 512);  // (a tuned pass: up to 2 x 256 work-groups)
-  b += 8 * (gmax * N + gmax + 64) + sizeof(DevState) + 64;
-  if (!cfg.H) b += 8 * (size_t)m;
-  b += 16 * (size_t)m;  // the LSQR form's two m-vectors (counted for every method)
-  return b;
+  return fs_solve_footprint_cu(m, n, o, 256);
+}
+
+fs_status fs_context_workspace(fs_context ctx, size_t* bytes) {
+  if (!ctx || !bytes) return FS_ERR_INVALID_ARG;
+  *bytes = fs_workspace_bytes(ctx->ws);
+  return FS_OK;
+}
+
+fs_status fs_context_trim(fs_context ctx) {
+  if (!ctx) return FS_ERR_INVALID_ARG;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->aux_stream) FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+  fs_workspace_free(ctx->ws);
+  return FS_OK;
 }
 
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
@@ -1051,6 +1118,31 @@ fs_status spir_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int6
                      const fs_options* opts, fs_info* info) {
   return solve(ctx, M_SPIR, m, n, A, lda, b, x, opts, info);
 }
+
+}  // extern "C"
+
+fs_status fs_fossils_solve_fixed(fs_context ctx, unsigned char* base, size_t cap, int64_t m, int32_t n,
+                                 const double* A, int64_t lda, const double* b, double* x, const fs_options& o,
+                                 fs_info* info) {
+  if (!ctx || !base) return FS_ERR_INVALID_ARG;
+  if (o.overlap_svd != 0 || o.graph_sweeps != 0) return FS_ERR_INVALID_ARG;
+  FS_TRY(validate_problem(m, n, A, lda, b, x));
+  FS_TRY(validate_options(m, n, o));
+  if (fs_carve_workspace(ctx->ws, nullptr, m, n, o, ctx->num_cu) > cap) return FS_ERR_TOO_LARGE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  // the context's own buffers are set aside for this call and put back on every exit path
+  struct Swap {
+    fs_context c;
+    Workspace saved;
+    ~Swap() { c->ws = saved; }
+  } swap{ctx, ctx->ws};
+  ctx->ws = Workspace{};
+  (void)fs_carve_workspace(ctx->ws, base, m, n, o, ctx->num_cu);
+  return solve(ctx, M_FOSSILS, m, n, A, lda, b, x, &o, info);
+}
+
+extern "C" {
 
 fs_status spir_lsqr_solve(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
                           double* x, const fs_options* opts, fs_info* info) {

@@ -139,3 +139,34 @@ def test_mixed_rejects_bad_ld(ctx):
     A32 = torch.zeros((20, 400), dtype=torch.float32, device="cuda").t()  # ld 400 < m
     with pytest.raises(Exception):
         binding.fossils_solve_mixed(ctx, A, b, x, A32)
+
+
+def test_mixed_full_size_kappa_1e6(ctx):
+    """The mixed form at 1e6 x 1000 where the FP32 sketch is kept (kappa 1e6, ||r|| 1e-4, made on
+    the device): no FP64 fallback, known-SVD KW backward error <= 1e-14, forward error within 10x of
+    Householder QR's (LAPACK TSQR on the same bytes), and iteration counts near the FP64 solve's."""
+    import torch
+    from paper_2406_03468_amd import binding
+    from synth import make_problem_torch
+    m, n, kappa = 1_000_000, 1000, 1e6
+    P = make_problem_torch(m, n, kappa, 1e-4, seed=4)
+    A32 = torch.empty((n, m), dtype=torch.float32, device="cuda").t()
+    binding.fs_to_fp32(ctx, P.A, A32)
+    xm = torch.zeros(n, dtype=torch.float64, device="cuda")
+    x64 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st, im = binding.fossils_solve_mixed(ctx, P.A, P.b, xm, A32)
+    st64, i64 = binding.fossils_solve(ctx, P.A, P.b, x64)
+    del A32
+    assert st == 0 and st64 == 0, (im.to_dict(), i64.to_dict())
+    assert not (im.flags & binding.FS_FLAG_FP64_SKETCH), im.to_dict()
+    Ah = P.A.cpu().numpy()
+    bh = P.b.cpu().numpy()
+    fro = np.sqrt(np.sum(Ah * Ah))
+    xq = hh.qr_lstsq_tsqr(Ah, bh)
+    fq = _fe(xq, P)
+    for name, x in (("mixed", host(xm)), ("fp64", host(x64))):
+        bek = be.kw_known_svd(Ah, bh, x, P.sigma, P.V, fro / np.linalg.norm(bh)) / fro
+        print("C4", name, "BE", bek, "FE", _fe(x, P), "FE_QR", fq)
+        assert bek <= 1e-14, (name, bek)
+        assert _fe(x, P) <= 10 * max(fq, kappa * U), (name, _fe(x, P), fq)
+    assert abs(im.iters[0] - i64.iters[0]) <= 3 and abs(im.iters[1] - i64.iters[1]) <= 6, (im.iters, i64.iters)

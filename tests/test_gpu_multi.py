@@ -107,3 +107,34 @@ def test_multi_zero_column_and_edge_cases(ctx):
     with pytest.raises(binding.FossilsError) as e:
         _multi(ctx, P.A, B)
     assert e.value.status == binding.FS_ERR_NONFINITE
+
+
+def test_multi_rhs_full_size(ctx):
+    """The measured 64-right-hand-side configuration: 1e6 x 1000, kappa 1e10, residual norms cycling
+    through 1e-10, 1e-4, 1 (made on the device).  A sample of columns covering every residual class
+    (two of each): known-SVD KW backward error <= 1e-14, forward error within 10x of Householder
+    QR's on the same bytes (LAPACK TSQR of [A B_sample])."""
+    import torch
+    from paper_2406_03468_amd import binding
+    from synth import make_problem_torch
+    m, n, k, kappa = 1_000_000, 1000, 64, 1e10
+    norms = [1e-10, 1e-4, 1.0]
+    P = make_problem_torch(m, n, kappa, norms[1], seed=1, nrhs=k, rhs_resid_norms=norms)
+    B = P.meta["B"]
+    X = torch.zeros((k, n), dtype=torch.float64, device="cuda").t()
+    status, infos = binding.fossils_solve_multi(ctx, P.A, B, X, binding.fs_options_default(m, n))
+    assert status == 0, [f.to_dict() for f in infos if f.flags]
+    cols = [0, 1, 2, 33, 34, 63]  # residual classes j % 3 = 0, 1, 2, 0, 1, 0
+    assert {j % 3 for j in cols} == {0, 1, 2}
+    Ah = P.A.cpu().numpy()
+    Bh = B[:, cols].cpu().numpy()
+    Xh = host(X)[:, cols]
+    Xt = P.meta["X_true"][:, cols]
+    fro = np.sqrt(np.sum(Ah * Ah))
+    Xq = hh.qr_lstsq_tsqr(Ah, Bh)
+    for i, j in enumerate(cols):
+        bek = be.kw_known_svd(Ah, Bh[:, i], Xh[:, i], P.sigma, P.V, fro / np.linalg.norm(Bh[:, i])) / fro
+        fe, fq = _fe(Xh[:, i], Xt[:, i]), _fe(Xq[:, i], Xt[:, i])
+        print("multi C3 column", j, norms[j % 3], list(infos[j].iters), "BE", bek, "FE", fe, "FE_QR", fq)
+        assert bek <= 1e-14, (j, bek)
+        assert fe <= 10 * max(fq, kappa * U), (j, fe, fq)
