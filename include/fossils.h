@@ -43,9 +43,14 @@ typedef enum fs_status {
   FS_ERR_NOMEM = -3,           /* device allocation failed */
   FS_ERR_DEVICE = -4,          /* a HIP call failed (see fs_last_error_detail) */
   FS_ERR_NONFINITE = -5,       /* A or b holds NaN or Inf */
-  FS_ERR_TOO_LARGE = -6,       /* size beyond what the library supports (n > 15000, d > 65536) */
+  FS_ERR_TOO_LARGE = -6,       /* size beyond what the library supports (n > 15000, d > 65536, a server's
+                                  budget, the no-alloc array), or finite entries of A or b so large that
+                                  their column norms overflow FP64 (column scaling impossible) */
   FS_ERR_UNKNOWN_TICKET = -7,  /* batched_poll / fs_server_ticket_times: no such ticket */
-  FS_ERR_UNSUPPORTED = -8
+  FS_ERR_UNSUPPORTED = -8,
+  /* not statuses: they make every 32-bit value a valid fs_status (fs_status_string of any int) */
+  FS_STATUS_RANGE_MIN_ = -2147483647 - 1,
+  FS_STATUS_RANGE_MAX_ = 2147483647
 } fs_status;
 
 typedef struct fs_context_s* fs_context;
@@ -56,7 +61,14 @@ enum { FS_PRECOND_QR = 0, FS_PRECOND_SVD = 1 };
 enum { FS_FP64 = 0, FS_MIXED = 1 };
 enum { FS_INIT_SKETCH = 0, FS_INIT_ZERO = 1 };
 /* bits of fs_info.flags */
-enum { FS_FLAG_RANK_DEFICIENT = 1, FS_FLAG_NOT_CONVERGED = 2, FS_FLAG_FP64_SKETCH = 4 };
+enum {
+  FS_FLAG_RANK_DEFICIENT = 1,
+  FS_FLAG_NOT_CONVERGED = 2,
+  FS_FLAG_FP64_SKETCH = 4,        /* mixed form: the sketch was redone in FP64 */
+  FS_FLAG_EARLY_SECOND_STEP = 8,  /* overlap_svd: the second step started before the SVD of R finished */
+  FS_FLAG_SVD_ABANDONED = 16      /* ... and met its rule through ||R^{-T} g|| before the SVD was needed:
+                                     the SVD was stopped, normest and condest are lower bounds */
+};
 
 /* Solver options (Section 4.2 and Algorithm 4).  Fill with fs_options_default. */
 typedef struct fs_options {
@@ -78,14 +90,20 @@ typedef struct fs_options {
   int32_t max_sweeps;     /* Jacobi sweep cap of the SVD of R */
   int32_t init;           /* FS_INIT_SKETCH: x_0 = sketch-and-solve (Alg 4); FS_INIT_ZERO: x_0 = 0 (the
                              zero start of plain sketch-and-precondition, for the Section 5.1 comparisons) */
-  int32_t overlap_svd;    /* 1 (P = V Sigma^{-1}, adaptive FOSSILS or CG-SPIR, FP64): the SVD of R runs on
-                             a second stream while the first refinement step iterates with P = R^{-1}
-                             (the same preconditioned system up to an orthogonal change of variables);
-                             its iterates are recorded and, once normest and condest are known, the step
-                             is cut back to the iteration where the first-step rule stops.  Falls back to
-                             the serial order when R turns out numerically rank deficient; not used when
-                             the SVD's work-groups would hold more than half of the compute units
-                             (n above ~1500 on 256 compute units). */
+  int32_t overlap_svd;    /* 1 (P = V Sigma^{-1}, adaptive FOSSILS or CG-SPIR): the SVD of R runs on a
+                             second stream while the refinement iterates with P = R^{-1} (the same
+                             preconditioned system up to an orthogonal change of variables).  Until the
+                             SVD is done the first-step rule uses lower bounds of normest and condest
+                             (diag(R), power and inverse iteration): if the SVD arrives first, the step is
+                             cut back to the iteration where the true rule stops; if the step stops on
+                             the bounds first, the second step starts at once with P = R^{-1}, its KW
+                             checkpoints recorded and evaluated in order once Sigma and V exist (flag
+                             FS_FLAG_EARLY_SECOND_STEP); a checkpoint where even the upper bound
+                             theta ||R^{-T} g|| / sqrt(1 + theta^2 ||x||^2) of the sketched KW estimate
+                             meets the rule (times 1.25, where n u condest <= 0.1) ends the step at once
+                             and stops the SVD (FS_FLAG_SVD_ABANDONED).  Falls back to the serial order when R turns out
+                             numerically rank deficient; not used when the SVD's work-groups would hold
+                             more than half of the compute units (n above ~1500 on 256 compute units). */
   int32_t graph_sweeps;   /* 1: the inner iterations run as a captured HIP graph of kw_every iterations,
                              replayed until the device-side stop flag is set (one launch and one
                              host poll per kw_every iterations); 0: kernel-by-kernel launches */
@@ -98,7 +116,8 @@ typedef struct fs_options {
 /* Per-solve report. */
 typedef struct fs_info {
   int32_t iters[2];       /* inner iterations of the two refinement steps */
-  int32_t flags;          /* bit 0: rank deficient, bit 1: not converged */
+  int32_t flags;          /* FS_FLAG_*: rank deficient, not converged, FP64 sketch (mixed form), early
+                             second step (overlap_svd) */
   int32_t rank;           /* rank of the preconditioner (n unless truncated) */
   double be_sk;           /* last sketched KW estimate of the scaled problem (absolute) */
   double normest;         /* sigma_max of the sketch */

@@ -37,6 +37,8 @@ FS_INIT_ZERO = 1
 FS_FLAG_RANK_DEFICIENT = 1
 FS_FLAG_NOT_CONVERGED = 2
 FS_FLAG_FP64_SKETCH = 4
+FS_FLAG_EARLY_SECOND_STEP = 8
+FS_FLAG_SVD_ABANDONED = 16
 
 c_int32, c_int64, c_uint64, c_double, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double, ctypes.c_void_p
 

@@ -32,6 +32,7 @@ struct Workspace {
   DevBuf lsqr;                  // LSQR form of SPIR: the residual r and ubar = alpha u (2 m-vectors)
   DevBuf hist;                  // first step beside the SVD: iterates and ||Delta||^2 per iteration
   DevBuf cplx;                  // complex problems: the realified A (2m x 2n), b and x
+  DevBuf trsv;                  // triangular solves across work-groups: published x and block flags
 };
 
 struct fs_context_s {

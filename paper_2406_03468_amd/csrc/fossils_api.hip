@@ -74,7 +74,7 @@ void fs_free_buf(DevBuf& b) {
 std::vector<DevBuf*> fs_workspace_buffers(Workspace& w) {
   return {&w.idx, &w.Y,       &w.colnorm2, &w.dinv,  &w.qrwork, &w.svdwork, &w.sigma, &w.V,    &w.UR,
           &w.partial, &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate,
-          &w.lsqr, &w.hist, &w.cplx};
+          &w.lsqr, &w.hist, &w.cplx, &w.trsv};
 }
 
 size_t fs_workspace_bytes(Workspace& w) {
@@ -111,6 +111,15 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
   return FS_OK;
 }
 
+// History of the solve beside the SVD of R: the first step's iterates and ||Delta||^2 per iteration,
+// then the second step's KW checkpoints recorded before Sigma and V exist (dy, g and V^T g per
+// checkpoint, and four scalars each).
+static int fs_kw_slots(const fs_options& o) { return o.max_inner / o.kw_every + 2; }
+size_t fs_hist_bytes(int n, const fs_options& o) {
+  const size_t N = (size_t)n, C = (size_t)fs_kw_slots(o);
+  return 8 * ((size_t)o.max_inner * N + (size_t)o.max_inner + 8 + 3 * C * N + 4 * C);
+}
+
 // Upper bound of the workspace one single-right-hand-side solve (FOSSILS, SPIR, LSQR; FP64 or mixed)
 // grows to on a GPU with num_cu compute units: every buffer solve() sizes, at its largest.
 size_t fs_solve_footprint_cu(int64_t m, int32_t n, const fs_options& o, int num_cu) {
@@ -119,12 +128,13 @@ size_t fs_solve_footprint_cu(int64_t m, int32_t n, const fs_options& o, int num_
   size_t b = (size_t)m * o.zeta * (fs_idx16_ok(o.d) ? 2 : 4);  // index stream
   b += 8 * d * k;                                                // sketch Y
   b += fs_qr_work_bytes(o.d, (int)k, num_cu) + fs_svd_work_bytes(n);
-  b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 16 * N);  // V, U_R, vectors
+  b += 8 * (2 * N * N + 4 * N + N * ((N + 63) / 64 + 1) + 22 * N);  // V, U_R, vectors
   const size_t gmax = std::max<size_t>(2 * (size_t)num_cu, 512);    // fused-pass partials (tuned: up to 2 per CU)
   b += 8 * (gmax * N + gmax + 64) + sizeof(DevState) + 64;
   b += 8 * (size_t)m;   // the unfused pass's row scratch (a leading dimension too large for 32-bit offsets)
   b += 16 * (size_t)m;  // the LSQR form's two m-vectors (counted for every method)
-  if (o.overlap_svd) b += 8 * ((size_t)o.max_inner * N + (size_t)o.max_inner + 8);  // first-step history
+  if (o.overlap_svd) b += fs_hist_bytes(n, o);  // first-step history and deferred KW checkpoints
+  b += fs_trsv_flow_bytes(n);
   return b;
 }
 
@@ -152,11 +162,12 @@ size_t fs_carve_workspace(Workspace& w, unsigned char* base, int64_t m, int32_t 
   slice(w.V, 8 * N * N);
   slice(w.UR, 8 * N * N);
   slice(w.gemvpart, 8 * N * ((N + 63) / 64 + 1));
-  slice(w.vecs, 8 * 16 * N);
+  slice(w.vecs, 8 * 22 * N);
   slice(w.state, sizeof(DevState) + 64);
   slice(w.partial, 8 * gmax * N);
   slice(w.pr2, 8 * gmax + 64);
   slice(w.wscratch, 8 * (size_t)m);
+  slice(w.trsv, fs_trsv_flow_bytes(n));
   return off;
 }
 
@@ -175,6 +186,7 @@ const char* fs_status_string(fs_status s) {
     case FS_ERR_TOO_LARGE: return "FS_ERR_TOO_LARGE";
     case FS_ERR_UNKNOWN_TICKET: return "FS_ERR_UNKNOWN_TICKET";
     case FS_ERR_UNSUPPORTED: return "FS_ERR_UNSUPPORTED";
+    default: break;
   }
   return "FS_UNKNOWN_STATUS";
 }
@@ -572,8 +584,18 @@ fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32
   if (n < 1 || ldr < n) return FS_ERR_SHAPE;
   if (n > 15000) return FS_ERR_TOO_LARGE;
   FS_HIP(hipSetDevice(ctx->device));
-  FS_K(fs_launch_trsv(R, ldr, n, transpose != 0, y, x, nullptr, nullptr, nullptr, ctx->stream));
   FS_HIP(hipStreamSynchronize(ctx->stream));
+  FS_TRY(grow(ctx->ws.trsv, fs_trsv_flow_bytes(n)));
+  FS_K(fs_trsv_flow_reset(n, ctx->ws.trsv.p, ctx->stream));
+  FS_K(fs_launch_trsv_flow(R, ldr, n, transpose != 0, y, x, nullptr, nullptr, nullptr, ctx->ws.trsv.p, ctx->stream));
+  int err = 0;
+  FS_HIP(hipMemcpyAsync(&err, fs_trsv_flow_err_word(n, ctx->ws.trsv.p), sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  if (err) {
+    fs_set_last_hip_error(hipErrorLaunchTimeOut, "triangular solve gave up waiting for a block", __FILE__, __LINE__);
+    return FS_ERR_DEVICE;
+  }
   return FS_OK;
 }
 
@@ -669,17 +691,23 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_TRY(grow(W.V, sizeof(double) * (size_t)n * n));
   FS_TRY(grow(W.UR, sizeof(double) * (size_t)n * n));
   FS_TRY(grow(W.gemvpart, sizeof(double) * (size_t)n * ((n + 63) / 64 + 1)));
-  const int NV = 16;
+  const int NV = 22;  // 16 vectors of the iteration, 6 of the spectral bounds
   FS_TRY(grow(W.vecs, sizeof(double) * (size_t)NV * n));
   FS_TRY(grow(W.state, sizeof(DevState) + 64));
+  FS_TRY(grow(W.trsv, fs_trsv_flow_bytes(n)));
   FS_TRY(ensure_pass_ws(ctx, m, n, lda));
   if (defer_fp64) {  // (also for a mixed solve, which may fall back to an FP64 sketch and overlap)
-    FS_TRY(grow(W.hist, sizeof(double) * ((size_t)o.max_inner * n + o.max_inner + 8)));
+    FS_TRY(grow(W.hist, fs_hist_bytes(n, o)));
     if (!ctx->aux_stream) FS_HIP(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
     if (!ctx->ev_aux) FS_HIP(hipEventCreateWithFlags(&ctx->ev_aux, hipEventDisableTiming));
   }
   double* hist_dy = defer_fp64 ? (double*)W.hist.p : nullptr;
   double* hist_dn = defer_fp64 ? hist_dy + (size_t)o.max_inner * n : nullptr;
+  const int kw_slots = fs_kw_slots(o);
+  double* kw_dy = defer_fp64 ? hist_dn + o.max_inner + 8 : nullptr;  // deferred KW checkpoints
+  double* kw_g = defer_fp64 ? kw_dy + (size_t)kw_slots * n : nullptr;
+  double* kw_w = defer_fp64 ? kw_g + (size_t)kw_slots * n : nullptr;
+  double* kw_s = defer_fp64 ? kw_w + (size_t)kw_slots * n : nullptr;
   const bool lsqr = (method == M_SPIR_LSQR);
   if (lsqr) FS_TRY(grow(W.lsqr, sizeof(double) * 2 * (size_t)m));
   double* rbuf = lsqr ? (double*)W.lsqr.p : nullptr;  // r of the last LSQR pass (m)
@@ -705,6 +733,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   const double eta = ((o.eta > 0) ? o.eta : sqrt((double)n / d)) * o.eta_factor;
   const double beta0 = eta * eta;                            // eq:optimal-coeffs
   FS_K(fs_vec_state_init(st, (1.0 - beta0) * (1.0 - beta0), beta0, o.max_inner, s));
+  FS_K(fs_trsv_flow_reset(n, W.trsv.p, s));
 
   hipEvent_t* ev = ctx->ev;
   FS_HIP(hipEventRecord(ev[0], s));
@@ -714,7 +743,6 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   // Sketch (Alg 1 first statement; Alg 4 column scaling in the same read of A), QR of the sketch,
   // SVD of R (Alg 4: Sigma, V for normest, condest, truncation and the KW estimate), then a read-back
   // of the statistics.  fp32: the mixed-precision form's sketch (FP32 accumulation, from A32 if given).
-  std::vector<double> rdiag(n);
   bool early_fallback = false;
   auto factor = [&](bool fp32, bool defer_svd) -> fs_status {
     if (fp32)
@@ -730,28 +758,33 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
                                     : std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false)));
     FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
     FS_HIP(hipEventRecord(ev[2], s));
+    bool bounds_done = false;
     if (fp32) {
-      // max |r_ii| / min |r_ii| <= cond(R): when it alone passes the threshold, the FP32-copy sketch is
-      // dropped before its SVD (the costlier half of the factorization)
-      FS_HIP(hipMemcpy2DAsync(rdiag.data(), sizeof(double), R, sizeof(double) * (ldr + 1), sizeof(double), n,
-                              hipMemcpyDeviceToHost, s));
+      // A lower bound of cond(R) (diag(R), then power and inverse iteration, about 0.5 ms at n = 1000)
+      // decides before the SVD whether the FP32-copy sketch can be kept: a bound that already passes
+      // u32 condest > 2 drops it at once (the SVD would only confirm); otherwise the SVD's condest
+      // decides later.
+      FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
+      FS_K(fs_vec_spectral_bounds(n, R, ldr, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st, s));
+      FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
       FS_HIP(hipStreamSynchronize(s));
-      double dmax = 0.0, dmin = INFINITY;
-      for (int j = 0; j < n; ++j) {
-        dmax = std::max(dmax, fabs(rdiag[j]));
-        dmin = std::min(dmin, fabs(rdiag[j]));
-      }
-      if (!(dmax * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION * dmin)) {
+      bounds_done = true;
+      if (!(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
         early_fallback = true;
         return FS_OK;
       }
     }
     if (defer_svd) {
-      // the SVD is launched by the caller on the second stream; until it fills in normest and
-      // condest they hold lower bounds from diag(R), so the first step can stop on its own no later
-      // than the true rule would (its threshold is recomputed and the step cut back once known)
-      FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
+      // the SVD is launched by the caller on the second stream (after this event); until it fills in
+      // normest and condest they hold lower bounds -- from diag(R), sharpened by a few steps of power
+      // and inverse iteration on the main stream beside the SVD -- so the first step stops on its own
+      // no earlier than the true rule would (its threshold is recomputed and the step cut back if the
+      // SVD arrives first)
       FS_HIP(hipEventRecord(ctx->ev_aux, s));
+      if (!bounds_done) {
+        FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
+        FS_K(fs_vec_spectral_bounds(n, R, ldr, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st, s));
+      }
     } else {
       FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
                               svd_sweeps_dev, s));
@@ -773,8 +806,12 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
                             __LINE__);
       return FS_ERR_DEVICE;
     }
+    // the sketch marks a column holding NaN or Inf with a NaN norm; an infinite norm of finite data
+    // means its squares overflow FP64 (entries beyond ~1e154): too large for the column scaling
     for (int j = 0; j <= n; ++j)
-      if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
+      if (std::isnan(cnh[j])) return FS_ERR_NONFINITE;
+    for (int j = 0; j <= n; ++j)
+      if (!std::isfinite(cnh[j])) return FS_ERR_TOO_LARGE;
     return FS_OK;
   };
   const bool mixed = (o.precision == FS_MIXED);
@@ -815,8 +852,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     aux_drain.a = a;
     FS_HIP(hipStreamWaitEvent(a, ctx->ev_aux, 0));
     svd_coop = std::make_unique<CoopSection>(ctx, fs_svd_grid_size(n, ctx->num_cu, false), a);
-    FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
-                            svd_sweeps_dev, a));
+    FS_K(fs_launch_svd_abortable(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
+                                 svd_sweeps_dev, &st->svd_abort, a));
     FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, a));
     FS_HIP(hipEventRecord(ev[3], a));
     return FS_OK;
@@ -857,7 +894,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     if (use_svd) {
       FS_K(fs_vec_gemv_v(V, n, n, nr, y, sigma, oscale, addv, out, gpart, stp, s));
     } else {
-      FS_K(fs_launch_trsv(R, ldr, n, false, y, out, nullptr, oscale, stp, s));
+      FS_K(fs_launch_trsv_flow(R, ldr, n, false, y, out, nullptr, oscale, stp, W.trsv.p, s));
       if (addv) FS_K(fs_vec_add_norm(n, addv, out, out, nullptr, stp, s));
     }
     return FS_OK;
@@ -866,7 +903,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     if (use_svd) {
       FS_K(fs_vec_gemv_vt(V, n, n, nr, vin, sigma, out, stp, s));
     } else {
-      FS_K(fs_launch_trsv(R, ldr, n, true, vin, out, nullptr, nullptr, stp, s));
+      FS_K(fs_launch_trsv_flow(R, ldr, n, true, vin, out, nullptr, nullptr, stp, W.trsv.p, s));
     }
     return FS_OK;
   };
@@ -878,7 +915,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));
       FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
     } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
-      FS_K(fs_launch_trsv(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, s));
+      FS_K(fs_launch_trsv_flow(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, W.trsv.p, s));
     }
     if (o.init == FS_INIT_ZERO) FS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));  // (not captured)
     FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));
@@ -915,13 +952,67 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     fs_context c;
     ~PassCapReset() { c->pass_group_cap = 0; }
   } pass_cap_reset{ctx};
+  // Join the SVD running beside the refinement: statistics and barrier status.  Returns 1 when the
+  // solve restarts (a kept FP32 sketch fails its condest, or R is numerically rank deficient).
+  auto join_svd = [&](int& restarted) -> fs_status {
+    restarted = 0;
+    FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+    svd_coop.reset();
+    int bar_err = 0;
+    FS_HIP(hipMemcpyAsync(&bar_err, fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    FS_HIP(hipStreamSynchronize(s));
+    if (bar_err) {
+      fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the SVD kernel gave up waiting", __FILE__,
+                            __LINE__);
+      return FS_ERR_DEVICE;
+    }
+    hs.normest = ctx->st_host->normest;
+    hs.condest = ctx->st_host->condest;
+    hs.rank_trunc = ctx->st_host->rank_trunc;
+    inf.normest = hs.normest;
+    inf.condest = hs.condest;
+    inf.svd_sweeps = svd_sweeps;
+    defer = false;
+    if (mixed && !(flags & FS_FLAG_FP64_SKETCH) && !(hs.condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
+      // the FP32 sketch kept on diag(R)'s evidence fails on its SVD's condest: discard the
+      // overlapped steps and restart from an FP64 sketch, its SVD again beside the first step
+      flags |= FS_FLAG_FP64_SKETCH;
+      FS_TRY(factor(false, true));
+      FS_TRY(launch_aux_svd());
+      defer = true;
+      hs = *ctx->st_host;
+      FS_K(fs_vec_set_double(&st->theta2, hs.fro2 / b2, s));  // ||A_s||_F of the FP64 column scaling
+      use_svd = false;
+      nr = n;
+      FS_TRY(start_x0());
+      restarted = 1;
+      return FS_OK;
+    }
+    if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {
+      // numerically rank deficient after all: start over in the serial order with the truncated
+      // preconditioner (the overlapped steps are discarded)
+      FS_TRY(set_rank_deficient());
+      inf.rank = rk;
+      nr = rk;
+      FS_TRY(start_x0());
+      restarted = 1;
+    }
+    return FS_OK;
+  };
+  bool early = false;  // the second step runs with P = R^{-1} while the SVD is still running
+  bool svd_abandoned = false;  // that step met its rule through the bound ||R^{-T} g||: no SVD needed
+  // The bound certifies the rule only where the substitution R^{-T} g is accurate to a few percent
+  // (n u condest <= 0.1, condest from its lower bound) and, in the mixed form, once the sketch is FP64.
+  const bool kw_bound_ok = !(mixed && !(flags & FS_FLAG_FP64_SKETCH)) && hs.condest * n * U_ROUND <= 0.1;
   for (int step = 0; step < o.steps; ++step) {
     const bool dstep = defer && step == 0;  // first step beside the SVD (P = R^{-1}, iterates recorded)
     bool thr_known = !dstep;
     // beside the SVD the passes take only the compute units its work-groups leave free (at least
     // half of them here): a pass with more work-groups than free units runs a second, partial wave
     int group_cap = 0;
-    if (dstep) {
+    if (dstep || early) {
       const int free_cu = ctx->num_cu - fs_svd_grid_size(n, ctx->num_cu, false);
       group_cap = (o.overlap_pass_groups > 0) ? o.overlap_pass_groups : free_cu / 8 * 8;
     }
@@ -946,6 +1037,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     if (fixed) FS_K(fs_vec_set_int(&st->max_inner, cap, s));
     const bool first = (step == 0) && !fixed;
     bool stopped = false;
+    bool kw_deferred = early && step == 1;  // KW checkpoints recorded until Sigma and V exist
+    int kw_recorded = 0;
     // one inner iteration (every kernel returns at once after the device-side stop flag is set)
     auto iteration = [&](int j) -> fs_status {
       const double* dir = (method == M_FOSSILS) ? v.dy : v.p;
@@ -969,8 +1062,22 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
         FS_K(fs_vec_add_norm(n, v.xh, nullptr, v.xh, &st->x2, stop, s));
         FS_K(fs_vec_mul(n, v.xh, dinv, v.zs, stop, s));
         FS_TRY(run_pass(ctx, m, n, A, lda, v.zs, b, v.g, dinv, &st->r2, stop));
-        FS_K(fs_vec_gemv_vt(V, n, n, n, v.g, nullptr, v.w, stop, s));
-        FS_K(fs_vec_kw(n, v.w, sigma, st, s));
+        if (kw_deferred) {
+          if (kw_recorded < kw_slots) {
+            FS_K(fs_vec_kw_record(kw_recorded, j, n, v.dy, v.g, kw_dy, kw_g, kw_s, st, s));
+            ++kw_recorded;
+          }
+          // the rule through ||R^{-T} g|| >= the sketched KW estimate: when even the bound meets it,
+          // the step stops here without Sigma and V (the first checkpoint where it holds; the exact
+          // rule might have stopped at an earlier one)
+          if (kw_bound_ok) {
+            FS_K(fs_launch_trsv_flow(R, ldr, n, true, v.g, v.w, nullptr, nullptr, stop, W.trsv.p, s));
+            FS_K(fs_vec_kw_upper(n, v.w, 1.25, st, s));
+          }
+        } else {
+          FS_K(fs_vec_gemv_vt(V, n, n, n, v.g, nullptr, v.w, stop, s));
+          FS_K(fs_vec_kw(n, v.w, sigma, st, s));
+        }
       }
       return FS_OK;
     };
@@ -989,6 +1096,19 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       thr_known = true;
       return FS_OK;
     };
+    // the second step beside the SVD: once Sigma and V exist, the recorded KW checkpoints are
+    // evaluated in order (the step may end at one of them) and later checks are evaluated at once
+    int restarted = 0;
+    auto finish_deferred = [&]() -> fs_status {
+      FS_TRY(join_svd(restarted));
+      if (restarted) return FS_OK;
+      ctx->pass_group_cap = 0;  // the whole GPU for the rest of the step
+      for (int c = 0; c < kw_recorded; ++c)
+        FS_K(fs_vec_gemv_vt(V, n, n, n, kw_g + (size_t)c * n, nullptr, kw_w + (size_t)c * n, nullptr, s));
+      FS_K(fs_vec_kw_replay(n, kw_recorded, kw_w, sigma, kw_dy, kw_s, v.dy, st, s));
+      kw_deferred = false;
+      return FS_OK;
+    };
     const int sweep = o.kw_every;
     if (dstep) {
       for (int j = 0; j < cap && !stopped; ++j) {
@@ -1004,8 +1124,18 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
             stopped = true;
         }
       }
-      if (!thr_known) FS_TRY(apply_threshold());
-    } else if (o.graph_sweeps && !fixed && cap % sweep == 0) {
+      // The step stopped on the diag(R) lower bounds before the SVD finished: the threshold it used
+      // is at most the true one (the step ran at least as long as the first-step rule asks), and the
+      // second step starts now with P = R^{-1}.  Otherwise the cut back to the true rule.
+      // (only where substitution with R is accurate to a few percent, n u condest <= 0.1 with condest
+      // from its lower bound: for a worse conditioned R the second step's KW estimate, taken at
+      // x + R^{-1} dy, does not reach the rule's floor, and that step waits for P = V Sigma^{-1})
+      early = !thr_known && o.steps == 2 && !fixed && !o.graph_sweeps && ctx->st_host->converged != 0 &&
+              ctx->st_host->condest * n * U_ROUND <= 0.1;
+      if (!thr_known && !early) FS_TRY(apply_threshold());
+      if (early) flags |= FS_FLAG_EARLY_SECOND_STEP;
+      else flags &= ~FS_FLAG_EARLY_SECOND_STEP;
+    } else if (o.graph_sweeps && !fixed && !kw_deferred && cap % sweep == 0) {
       // kw_every iterations (the KW check, when due, is the first of them) captured once as a graph
       // and replayed; the host polls the stop flag after each replay, as the launch-by-launch loop does
       FS_TRY(sweep_graph_run(ctx, s, sweep, cap / sweep, iteration, poll_stop, stopped));
@@ -1013,8 +1143,29 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       for (int j = 0; j < cap && !stopped; ++j) {
         FS_TRY(iteration(j));
         const bool poll = ((j + 1) % sweep) == 0 || j == cap - 1;
-        if (poll && !fixed) FS_TRY(poll_stop());
+        if (poll && !fixed) {
+          FS_TRY(poll_stop());
+          if (kw_deferred && ctx->st_host->svd_abort) {
+            kw_deferred = false;  // stopped on the bound; the SVD winds down unused
+            svd_abandoned = true;
+          } else if (kw_deferred && (stopped || hipEventQuery(ev[3]) == hipSuccess)) {
+            FS_TRY(finish_deferred());
+            if (restarted) break;
+            FS_TRY(poll_stop());
+          }
+        }
       }
+      if (kw_deferred && !restarted) {  // (the loop ended at the cap)
+        FS_TRY(poll_stop());
+        if (ctx->st_host->svd_abort) svd_abandoned = true;
+        else FS_TRY(finish_deferred());
+      }
+    }
+    if (restarted) {
+      early = false;
+      iters[0] = 0;
+      step = -1;
+      continue;
     }
     // x <- x + P dy
     FS_TRY(applyP(v.dy, v.z, nullptr, v.x, nullptr));
@@ -1026,50 +1177,10 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     cnorm[step] = sqrt(ctx->st_host->cnorm2);
     conv_last = ctx->st_host->converged != 0 || fixed;
     if (fixed) FS_K(fs_vec_set_int(&st->max_inner, o.max_inner, s));  // restore the cap
-    if (dstep) {
+    if (dstep && !early) {
       // join the SVD: statistics, barrier status; then the second step with P = V Sigma^{-1}
-      FS_HIP(hipStreamSynchronize(ctx->aux_stream));
-      svd_coop.reset();
-      int bar_err = 0;
-      FS_HIP(hipMemcpyAsync(&bar_err, fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
-      FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-      FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-      FS_HIP(hipStreamSynchronize(s));
-      if (bar_err) {
-        fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the SVD kernel gave up waiting", __FILE__,
-                              __LINE__);
-        return FS_ERR_DEVICE;
-      }
-      hs.normest = ctx->st_host->normest;
-      hs.condest = ctx->st_host->condest;
-      hs.rank_trunc = ctx->st_host->rank_trunc;
-      inf.normest = hs.normest;
-      inf.condest = hs.condest;
-      inf.svd_sweeps = svd_sweeps;
-      defer = false;
-      if (mixed && !(flags & FS_FLAG_FP64_SKETCH) && !(hs.condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
-        // the FP32 sketch kept on diag(R)'s evidence fails on its SVD's condest: discard the
-        // overlapped first step and restart from an FP64 sketch, its SVD again beside the first step
-        flags |= FS_FLAG_FP64_SKETCH;
-        FS_TRY(factor(false, true));
-        FS_TRY(launch_aux_svd());
-        defer = true;
-        hs = *ctx->st_host;
-        FS_K(fs_vec_set_double(&st->theta2, hs.fro2 / b2, s));  // ||A_s||_F of the FP64 column scaling
-        use_svd = false;
-        nr = n;
-        FS_TRY(start_x0());
-        iters[0] = 0;
-        step = -1;
-        continue;
-      }
-      if (!(hs.condest <= 1.0 / (o.tau_factor * U_ROUND))) {
-        // numerically rank deficient after all: start over in the serial order with the truncated
-        // preconditioner (the overlapped first step is discarded)
-        FS_TRY(set_rank_deficient());
-        inf.rank = rk;
-        nr = rk;
-        FS_TRY(start_x0());
+      FS_TRY(join_svd(restarted));
+      if (restarted) {
         iters[0] = 0;
         step = -1;
         continue;
@@ -1077,10 +1188,24 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       use_svd = true;  // P = V Sigma^{-1} for the second step (full rank: nr = n)
     }
   }
+  if (svd_abandoned) {
+    // the SVD stops at its next sweep boundary; normest and condest stay the lower bounds
+    FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+    svd_coop.reset();
+    FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    inf.svd_sweeps = svd_sweeps;
+    flags |= FS_FLAG_SVD_ABANDONED;
+  }
   // x_out = D^{-1} x
   FS_K(fs_vec_mul(n, v.x, dinv, x_out, nullptr, s));
   FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+  int trsv_err = 0;
+  FS_HIP(hipMemcpyAsync(&trsv_err, fs_trsv_flow_err_word(n, W.trsv.p), sizeof(int), hipMemcpyDeviceToHost, s));
   FS_HIP(hipStreamSynchronize(s));
+  if (trsv_err) {
+    fs_set_last_hip_error(hipErrorLaunchTimeOut, "triangular solve gave up waiting for a block", __FILE__, __LINE__);
+    return FS_ERR_DEVICE;
+  }
   if (o.steps == 2 && o.fixed_q == 0 && !conv_last) flags |= 2;
   inf.iters[0] = iters[0];
   inf.iters[1] = iters[1];

@@ -120,8 +120,11 @@ extern "C" fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, c
                           __LINE__);
     return FS_ERR_DEVICE;
   }
+  // NaN norm: the column holds NaN or Inf; +Inf: finite entries whose squares overflow FP64
   for (int j = 0; j < kc; ++j)
-    if (!std::isfinite(cnh[j])) return FS_ERR_NONFINITE;
+    if (std::isnan(cnh[j])) return FS_ERR_NONFINITE;
+  for (int j = 0; j < kc; ++j)
+    if (!std::isfinite(cnh[j])) return FS_ERR_TOO_LARGE;
   const DevState hs = *ctx->st_host;
   const double fro2 = hs.fro2, fro_u = sqrt(hs.fro2) * FS_U_ROUND;
   // per-column ||b_j||^2; b_j = 0 columns are never iterated (x_j = 0)

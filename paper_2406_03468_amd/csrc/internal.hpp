@@ -65,6 +65,13 @@ hipError_t fs_launch_qr(double* Y, int64_t ldy, int d, int k, void* work, int nu
 // x = R^{-1} y (upper, back substitution) or x = R^{-T} y (forward substitution); in place on x.
 hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
                           const double* yscale, const double* xscale, const int* stop, hipStream_t s);
+// Triangular solves across work-groups (one per 64-row block, dependency flags); ws holds
+// fs_trsv_flow_bytes(n) bytes, cleared once by fs_trsv_flow_reset before the first launch on it.
+size_t fs_trsv_flow_bytes(int n);
+hipError_t fs_trsv_flow_reset(int n, void* ws, hipStream_t s);
+int* fs_trsv_flow_err_word(int n, void* ws);
+hipError_t fs_launch_trsv_flow(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
+                               const double* yscale, const double* xscale, const int* stop, void* ws, hipStream_t s);
 // nrhs independent solves (one work-group each): Xb[:, r] = R^{-1} Yb[:, r] (or R^{-T}).
 hipError_t fs_launch_trsv_batched(const double* R, int64_t ldr, int n, bool transpose, const double* Yb, int64_t ldy,
                                   double* Xb, int64_t ldx, int nrhs, hipStream_t s);
@@ -75,6 +82,11 @@ size_t fs_svd_work_bytes(int n);
 hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
                               double* Uout, int64_t ldu, void* work, int num_cu, int max_sweeps,
                               int* sweeps_out_dev, hipStream_t s);
+// The same; the block-Jacobi sweeps stop early once *abort_flag (device, may be null) is set by another
+// stream (the results are then not used).
+hipError_t fs_launch_svd_abortable(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
+                                   double* Uout, int64_t ldu, void* work, int num_cu, int max_sweeps,
+                                   int* sweeps_out_dev, const int* abort_flag, hipStream_t s);
 hipError_t fs_launch_svd(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
                          void* work, int num_cu, int max_sweeps, int* sweeps_out_dev, hipStream_t s);
 

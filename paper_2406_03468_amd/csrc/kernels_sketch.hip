@@ -118,6 +118,7 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
   const TA* colA[PW];
   const double* colB[PW];
   double ss[PW];
+  int bad = 0;  // a NaN or Inf entry in one of the panel's columns (marked as a NaN norm below)
 #pragma unroll
   for (int p = 0; p < PW; ++p) {
     const int col = c0 + p;
@@ -153,7 +154,10 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
       const int64_t i = i0 + (int64_t)u * NT;
       if (i >= m) break;
 #pragma unroll
-      for (int p = 0; p < PW; ++p) ss[p] = fma(a[u][p], a[u][p], ss[p]);
+      for (int p = 0; p < PW; ++p) {
+        ss[p] = fma(a[u][p], a[u][p], ss[p]);
+        bad |= (int)(!isfinite(a[u][p])) << p;
+      }
       if (Z8) {
         const uint32_t w4[4] = {e8[u].x, e8[u].y, e8[u].z, e8[u].w};
 #pragma unroll
@@ -174,8 +178,10 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
     if (p >= np) continue;  // np is uniform across the work-group
     const int col = c0 + p;
     const double nrm2 = block_sum<NT>(ss[p], sred);
+    // non-finite data gives a NaN norm; finite data whose squares overflow gives +Inf
+    const bool nonfinite = block_sum<NT>((double)((bad >> p) & 1), sred) > 0.0;
     double f = inv_sqrt_zeta;
-    if (chk == 0 && tid == 0 && (col < n || write_bnorm)) colnorm2[col] = nrm2;
+    if (chk == 0 && tid == 0 && (col < n || write_bnorm)) colnorm2[col] = nonfinite ? NAN : nrm2;
     if (col < n) {
       if (scale_by_norm && nrm2 > 0.0) f = inv_sqrt_zeta / sqrt(nrm2);
     }

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
                                                       double tol, double* __restrict__ mbox, unsigned* __restrict__ flags,
                                                       int* __restrict__ rotcount, int* __restrict__ sweeps_out,
                                                       GridBarrier bar, unsigned long long* __restrict__ maxcos2,
-                                                      double stop_cos2) {
+                                                      double stop_cos2, const int* __restrict__ abort_flag) {
   extern __shared__ double lds[];  // [2][b][n]
   const int P = gridDim.x, p = blockIdx.x, tid = threadIdx.x;
   const int gl = tid % LP, grp = tid / LP, ngrp = blockDim.x / LP;  // pair groups (rows or waves)
@@ -547,6 +547,11 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
         c2 = fmax(c2, s_c2[w]);
       }
       if (t) __hip_atomic_fetch_add(&rotcount[sweep], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // a caller that no longer needs the SVD raises abort_flag; any work-group that has seen it by
+      // now marks the sweep (bit 30 of its count, far above any rotation count), so all agree after
+      // the barrier and stop together
+      if (abort_flag && __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+        __hip_atomic_fetch_or(&rotcount[sweep], 1 << 30, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_max(&maxcos2[sweep], (unsigned long long)__double_as_longlong(c2), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -557,6 +562,10 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
     // Converged, or in the quadratic phase: a sweep whose largest cosine was <= sqrt(stop_cos2)
     // leaves cosines of order n stop_cos2, which the orthogonality correction of V removes; the
     // sweep that would only confirm convergence is skipped.
+    if (tot & (1 << 30)) {  // abandoned: the results are not used
+      ++sweep;
+      break;
+    }
     if (tot == 0 || c2s <= stop_cos2) {
       ++sweep;
       break;
@@ -587,7 +596,8 @@ __global__ void k_fill_int(int* __restrict__ p, int n, int v) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
-__global__ void k_svd_norms(const double* __restrict__ Gm, int n, double* __restrict__ norms) {
+__global__ void k_svd_norms(const double* __restrict__ Gm, int n, double* __restrict__ norms, const int* __restrict__ skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const int i = blockIdx.x;
   __shared__ double sh[4];
   const double* gi = Gm + (int64_t)i * n;
@@ -599,7 +609,8 @@ __global__ void k_svd_norms(const double* __restrict__ Gm, int n, double* __rest
 
 __global__ void k_svd_sort_write(const double* __restrict__ Gm, const double* __restrict__ U, int n,
                                  const double* __restrict__ norms, double* __restrict__ sigma, double* __restrict__ V,
-                                 int64_t ldv, double* __restrict__ Uout, int64_t ldu) {
+                                 int64_t ldv, double* __restrict__ Uout, int64_t ldu, const int* __restrict__ skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const int i = blockIdx.x;
   __shared__ int srank;
   const double si = norms[i];
@@ -639,7 +650,8 @@ constexpr int OC_T = 64;
 // Tc[i, j] (ld n) = v_i^T v_j for i < j, (v_i^T v_i - 1) / 2 on the diagonal, 0 below (tiles on or
 // above the diagonal only; tiles wholly below it are never read).
 __global__ __launch_bounds__(256) void k_v_gram_upper(const double* __restrict__ V, int64_t ldv, int n,
-                                                      double* __restrict__ Tc) {
+                                                      double* __restrict__ Tc, const int* __restrict__ skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const int I = blockIdx.y, J = blockIdx.x;
   if (I > J) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -683,7 +695,8 @@ __global__ __launch_bounds__(256) void k_v_gram_upper(const double* __restrict__
 
 // Vout[:, j] (ld n) = V[:, j] - sum_{i <= j} V[:, i] Tc[i, j].
 __global__ __launch_bounds__(256) void k_v_correct(const double* __restrict__ V, int64_t ldv, int n,
-                                                   const double* __restrict__ Tc, double* __restrict__ Vout) {
+                                                   const double* __restrict__ Tc, double* __restrict__ Vout, const int* __restrict__ skip) {
+  if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   const int I = blockIdx.y, J = blockIdx.x;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int r0 = I * OC_T + (w >> 1) * 32, j0 = J * OC_T + (w & 1) * 32;
@@ -780,9 +793,9 @@ size_t fs_svd_work_bytes(int n) {
 }
 
 // work layout: Gm (n*n) | Uacc (n*n) | norms (n) | rotcount (64 ints) | sweeps (int)
-hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, double* Uout,
-                              int64_t ldu, void* work, int num_cu, int max_sweeps, int* sweeps_out_dev,
-                              hipStream_t s) {
+hipError_t fs_launch_svd_abortable(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv,
+                                   double* Uout, int64_t ldu, void* work, int num_cu, int max_sweeps,
+                                   int* sweeps_out_dev, const int* abort_flag, hipStream_t s) {
   if (max_sweeps > 64) max_sweeps = 64;
   double* Gm = (double*)work;
   double* Uacc = Gm + (size_t)n * n;
@@ -826,7 +839,7 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     unsigned long long* mc2 = (unsigned long long*)(rot + SVD_MC_INT);
     double stop_cos2 = 1e-10;  // a sweep whose cosines all stayed <= 1e-5 ends the iteration
     void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co, &mc2,
-                    &stop_cos2};
+                    &stop_cos2, &abort_flag};
     e = fs_launch_resident(kfn, dim3(P), dim3(SVD_BLOCK_NT), args, shmem, s);
     if (e != hipSuccess) return e;
   } else {
@@ -837,22 +850,30 @@ hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma
     e = fs_launch_resident((const void*)k_jacobi_coop, dim3(G), dim3(SVD_NT), args, 0, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_svd_norms, dim3(n), dim3(256), 0, s, Gm, n, norms);
-  hipLaunchKernelGGL(k_svd_sort_write, dim3(n), dim3(256), 0, s, Gm, Uarg, n, norms, sigma, V, ldv, Uout, ldu);
+  hipLaunchKernelGGL(k_svd_norms, dim3(n), dim3(256), 0, s, Gm, n, norms, abort_flag);
+  hipLaunchKernelGGL(k_svd_sort_write, dim3(n), dim3(256), 0, s, Gm, Uarg, n, norms, sigma, V, ldv, Uout, ldu,
+                     abort_flag);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // orthogonality correction of V (Gm and Uacc are free once sorted and written): Tc in Gm, the
   // corrected V in Uacc, copied back to V
   // Two passes: the Jacobi stop leaves cosines up to ~n 1e-10; each pass squares the remainder.
   const unsigned T = (unsigned)((n + OC_T - 1) / OC_T);
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(k_v_gram_upper, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm);
-    hipLaunchKernelGGL(k_v_correct, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm, Uacc);
+    hipLaunchKernelGGL(k_v_gram_upper, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm, abort_flag);
+    hipLaunchKernelGGL(k_v_correct, dim3(T, T), dim3(256), 0, s, V, ldv, n, Gm, Uacc, abort_flag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     e = hipMemcpy2DAsync(V, sizeof(double) * ldv, Uacc, sizeof(double) * n, sizeof(double) * n, n,
                          hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t fs_launch_svd_full(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, double* Uout,
+                              int64_t ldu, void* work, int num_cu, int max_sweeps, int* sweeps_out_dev,
+                              hipStream_t s) {
+  return fs_launch_svd_abortable(R, ldr, n, sigma, V, ldv, Uout, ldu, work, num_cu, max_sweeps, sweeps_out_dev,
+                                 nullptr, s);
 }
 
 hipError_t fs_launch_svd(const double* R, int64_t ldr, int n, double* sigma, double* V, int64_t ldv, void* work,

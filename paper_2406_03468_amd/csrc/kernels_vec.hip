@@ -103,6 +103,141 @@ __global__ __launch_bounds__(VNT) void k_trsv(const double* __restrict__ R, int6
   for (int i = tid; i < n; i += VNT) x[i] = xscale ? xs[i] * xscale[i] : xs[i];
 }
 
+// ---------------------------------------------------------------- triangular solves across work-groups
+// Back substitution R x = y (or forward substitution R^T x = y) with one work-group per block of 64
+// rows.  Block I needs the solution of the blocks it depends on (J > I for R, J < I for R^T): it
+// accumulates R_IJ x_J (R_JI^T x_J) as each x_J is published, then solves its 64 x 64 diagonal block
+// with one wave (row by row, as the single-work-group solve does) and publishes x_I.  Publication:
+// x_I goes to xbuf with device-coherent stores; after they complete, flag[I] is set to the launch's
+// epoch.  Readers poll the flag, then load x_J with device-coherent loads.  The work-group of the
+// block without dependencies gets blockIdx 0 and each block waits only for blocks with smaller
+// blockIdx, which the GPU dispatches first, so the wait needs no co-residency.  The epoch is a device
+// word: each launch targets its value + 1 and the last block (the one depending on all others, so
+// every work-group has read it) advances it, which keeps captured graphs correct on replay.  Waits
+// are bounded: on expiry the error word is set and the work-group proceeds.  The divisions by r_ii
+// are multiplications by the reciprocal formed once per block (one rounding more per row).
+constexpr int TF_NT = 512;
+constexpr int TF_B = 64;
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// flags layout (ints): [0, nb) block flags | nb: epoch | nb + 1: error word
+__global__ __launch_bounds__(TF_NT) void k_trsv_flow(const double* __restrict__ R, int64_t ldr, int n, int transpose,
+                                                     const double* y, double* x, const double* __restrict__ yscale,
+                                                     const double* __restrict__ xscale, const int* __restrict__ stop,
+                                                     double* __restrict__ xbuf, int* __restrict__ flags) {
+  if (fs_stopped(stop)) return;
+  const int nb = (n + TF_B - 1) / TF_B;
+  const int I = transpose ? (int)blockIdx.x : nb - 1 - (int)blockIdx.x;
+  const int r0 = I * TF_B;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;  // 8 waves
+  __shared__ double dblk[TF_B][TF_B + 1];
+  __shared__ double red[TF_NT / 64][TF_B];
+  int* epoch_w = flags + nb;
+  int* err_w = flags + nb + 1;
+  const int target = __hip_atomic_load(epoch_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  // the diagonal block (rows past n: identity, so their x is 0) and the right-hand side
+  for (int q = tid; q < TF_B * TF_B; q += TF_NT) {
+    const int r = q & 63, c = q >> 6;
+    const bool in = r0 + r < n && r0 + c < n;
+    double v = 0.0;
+    if (!transpose) {
+      if (in && r <= c) v = R[(int64_t)(r0 + c) * ldr + r0 + r];
+    } else {
+      if (in && c <= r) v = R[(int64_t)(r0 + r) * ldr + r0 + c];  // (R^T)[r][c] = R[c][r]
+    }
+    if (r == c && !in) v = 1.0;
+    dblk[r][c] = v;
+  }
+  double t = 0.0;
+  if (wv == 0 && r0 + lane < n) t = yscale ? y[r0 + lane] * yscale[r0 + lane] : y[r0 + lane];
+  // off-diagonal blocks in dependency order: thread (row lane, column group wv) sums 8 columns
+  const int nj = transpose ? I : nb - 1 - I;  // number of blocks this one depends on
+  double acc = 0.0;
+  auto tile_ptr = [&](int J, int u) -> double {
+    const int c = J * TF_B + wv * 8 + u;  // source index of x_J
+    if (!transpose) {
+      if (r0 + lane >= n || c >= n) return 0.0;
+      return R[(int64_t)c * ldr + r0 + lane];  // R[r0 + lane][c]
+    }
+    if (r0 + lane >= n || c >= n) return 0.0;
+    return R[(int64_t)(r0 + lane) * ldr + c];  // (R^T)[r0 + lane][c] = R[c][r0 + lane]
+  };
+  const __amdgpu_buffer_rsrc_t xr = co_rsrc(xbuf, (size_t)n * sizeof(double));  // reads past n give 0
+  double cur[8];
+  if (nj > 0) {
+    const int J0 = transpose ? 0 : nb - 1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cur[u] = tile_ptr(J0, u);
+  }
+  for (int q = 0; q < nj; ++q) {
+    const int J = transpose ? q : nb - 1 - q;
+    double nxt[8];
+    if (q + 1 < nj) {
+      const int Jn = transpose ? q + 1 : nb - 2 - q;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) nxt[u] = tile_ptr(Jn, u);
+    }
+    if (tid == 0) {
+      unsigned long long spins = 0;
+      while (__hip_atomic_load(flags + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ull << 24)) {
+          __hip_atomic_store(err_w, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    double xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) xv[u] = ld_cob(xr, (size_t)(J * TF_B + wv * 8 + u) * sizeof(double));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(cur[u], xv[u], acc);
+    if (q + 1 < nj) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cur[u] = nxt[u];
+    }
+  }
+  red[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0) {
+    double sred = 0.0;
+#pragma unroll
+    for (int g = 0; g < TF_NT / 64; ++g) sred += red[g][lane];
+    t -= sred;
+    const double rinv = 1.0 / dblk[lane][lane];
+    double xl = 0.0;
+    if (!transpose) {
+#pragma unroll 8
+      for (int i = TF_B - 1; i >= 0; --i) {
+        const double xi = readlane_d(t, i) * readlane_d(rinv, i);
+        if (lane == i) xl = xi;
+        if (lane < i) t = fma(-dblk[lane][i], xi, t);
+      }
+    } else {
+#pragma unroll 8
+      for (int i = 0; i < TF_B; ++i) {
+        const double xi = readlane_d(t, i) * readlane_d(rinv, i);
+        if (lane == i) xl = xi;
+        if (lane > i) t = fma(-dblk[lane][i], xi, t);
+      }
+    }
+    if (r0 + lane < n) {
+      st_co(xbuf + r0 + lane, xl);
+      x[r0 + lane] = xscale ? xl * xscale[r0 + lane] : xl;
+    }
+    stores_complete();
+    if (lane == 0) {
+      __hip_atomic_store(flags + I, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (nj == nb - 1) __hip_atomic_store(epoch_w, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- dense products with V (n x k, ld)
 // out[i] = oscale[i] * sum_j V[i, j] (y[j] * yscale[j])  -- partial over column slices
 __global__ __launch_bounds__(256) void k_gemv_v_part(const double* __restrict__ V, int64_t ldv, int n, int k,
@@ -152,6 +287,17 @@ __global__ __launch_bounds__(256) void k_trmv_t(const double* __restrict__ R, in
   for (int i = threadIdx.x; i <= j; i += 256) s = fma(R[(int64_t)j * ldr + i], t[i], s);
   s = block_sum<256>(s, sh);
   if (threadIdx.x == 0) out[j] = s;
+}
+
+// out partials: part[slice][i] = sum_{j in slice, j >= i} R[i, j] v[j]  (R v for upper-triangular R)
+__global__ __launch_bounds__(256) void k_trmv_part(const double* __restrict__ R, int64_t ldr, int n,
+                                                   const double* __restrict__ v, double* __restrict__ part, int cs) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * cs, j1 = min(n, j0 + cs);
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = max(i, j0); j < j1; ++j) acc = fma(R[(int64_t)j * ldr + i], v[j], acc);
+  part[(int64_t)blockIdx.y * n + i] = acc;
 }
 
 // ---------------------------------------------------------------- small vector kernels (one work-group)
@@ -358,6 +504,52 @@ __global__ __launch_bounds__(VNT) void k_diag_bounds(int n, const double* __rest
     mn = fmin(mn, smin[0]);
     st->normest = mx;
     st->condest = (mn > 0.0) ? mx / mn : 0.0;  // a zero diagonal: no usable bound
+    st->smin_ub = mn;
+  }
+}
+
+// One step of each bound iteration (one work-group).  Power iteration: est = ||R v|| / ||v|| <= sigma_max
+// (the running maximum goes to normest); v <- R^T R v / ||.||.  Inverse iteration: with w = R^{-T} x
+// and y = R^{-1} w, x_new = y / ||y|| is a unit vector with ||R x_new|| = ||w|| / ||y|| >= sigma_min
+// (the running minimum goes to smin_ub); condest = normest / smin_ub is then a lower bound.
+__global__ __launch_bounds__(VNT) void k_bound_step(int n, const double* __restrict__ p, const double* v,
+                                                    const double* __restrict__ q, const double* __restrict__ w,
+                                                    const double* __restrict__ y, double* v_out, double* x_out,
+                                                    DevState* __restrict__ st) {
+  __shared__ double sh[VNT / 64];
+  double p2 = 0.0, v2 = 0.0, q2 = 0.0, w2 = 0.0, y2 = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    p2 = fma(p[i], p[i], p2);
+    v2 = fma(v[i], v[i], v2);
+    q2 = fma(q[i], q[i], q2);
+    w2 = fma(w[i], w[i], w2);
+    y2 = fma(y[i], y[i], y2);
+  }
+  p2 = bsum(p2, sh);
+  v2 = bsum(v2, sh);
+  q2 = bsum(q2, sh);
+  w2 = bsum(w2, sh);
+  y2 = bsum(y2, sh);
+  const bool qok = q2 > 0.0 && isfinite(q2), yok = y2 > 0.0 && isfinite(y2);
+  const double sq = qok ? 1.0 / sqrt(q2) : 0.0, sy = yok ? 1.0 / sqrt(y2) : 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    if (qok) v_out[i] = q[i] * sq;
+    if (yok) x_out[i] = y[i] * sy;
+  }
+  if (threadIdx.x == 0) {
+    if (v2 > 0.0 && isfinite(p2)) st->normest = fmax(st->normest, sqrt(p2 / v2));
+    if (yok && isfinite(w2)) st->smin_ub = fmin(st->smin_ub, sqrt(w2 / y2));
+    st->condest = (st->smin_ub > 0.0) ? st->normest / st->smin_ub : 0.0;
+  }
+}
+
+// start vectors: v = x = (1, -2/3, 2/4, ...) (components in every singular direction); the diag(R)
+// bounds (k_diag_bounds) seed the running maximum and minimum
+__global__ __launch_bounds__(VNT) void k_bound_init(int n, double* __restrict__ v, double* __restrict__ x) {
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    const double e = ((i & 1) ? -1.0 : 1.0) / (1.0 + 0.5 * i);
+    v[i] = e;
+    x[i] = e;
   }
 }
 
@@ -397,6 +589,72 @@ __global__ __launch_bounds__(VNT) void k_rollback(int n, const double* __restric
     st->iters = jj + 1;
     st->stop = 1;
     st->converged = 1;
+  }
+}
+
+// A KW checkpoint of the second step recorded while the SVD of R is still running (skipped, like
+// every kernel of an iteration, once the stop flag is set).
+__global__ __launch_bounds__(VNT) void k_kw_record(int c, int j, int n, const double* __restrict__ dy,
+                                                   const double* __restrict__ g, double* __restrict__ kdy,
+                                                   double* __restrict__ kg, double* __restrict__ ks,
+                                                   DevState* __restrict__ st) {
+  if (st->stop) return;
+  for (int i = threadIdx.x; i < n; i += VNT) {
+    kdy[(int64_t)c * n + i] = dy[i];
+    kg[(int64_t)c * n + i] = g[i];
+  }
+  if (threadIdx.x == 0) {
+    ks[4 * c + 0] = st->r2;
+    ks[4 * c + 1] = st->x2;
+    ks[4 * c + 2] = (double)j;
+    st->kw_pending = c + 1;
+  }
+}
+
+// The recorded checkpoints in order, each with k_kw's formula; the first whose estimate meets the
+// second-step rule ends the step at its iteration.  Runs whether or not the cap stopped the loop.
+__global__ __launch_bounds__(VNT) void k_kw_replay(int n, int ncheck, const double* __restrict__ W,
+                                                   const double* __restrict__ sigma, const double* __restrict__ kdy,
+                                                   const double* __restrict__ ks, double* __restrict__ dy,
+                                                   DevState* __restrict__ st) {
+  __shared__ double sh[VNT / 64];
+  __shared__ int hit;
+  const int C = min(ncheck, st->kw_pending);
+  const double th2 = st->theta2;
+  if (threadIdx.x == 0) hit = -1;
+  __syncthreads();
+  for (int c = 0; c < C; ++c) {
+    const double r2 = ks[4 * c + 0], x2 = ks[4 * c + 1];
+    const double lam = th2 * r2 / (1.0 + th2 * x2);
+    const double* w = W + (int64_t)c * n;
+    double sacc = 0.0;
+    for (int i = threadIdx.x; i < n; i += VNT) {
+      const double si = sigma[i];
+      sacc += w[i] * w[i] / (si * si + lam);
+    }
+    sacc = bsum(sacc, sh);
+    if (threadIdx.x == 0) {
+      const double be = sqrt(th2 / (1.0 + th2 * x2)) * sqrt(sacc);
+      st->be_sk = be;
+      st->kw_evals += 1;
+      st->x2 = x2;
+      st->r2 = r2;
+      if (be < st->fro_u) hit = c;
+    }
+    __syncthreads();
+    if (hit >= 0) break;
+  }
+  if (hit >= 0) {
+    for (int i = threadIdx.x; i < n; i += VNT) dy[i] = kdy[(int64_t)hit * n + i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (hit >= 0) {
+      st->iters = (int)ks[4 * hit + 2] + 1;
+      st->stop = 1;
+      st->converged = 1;
+    }
+    st->kw_pending = 0;
   }
 }
 
@@ -463,7 +721,29 @@ __global__ __launch_bounds__(VNT) void k_scaling(int n, const double* __restrict
 }
 
 // normest, condest from sigma (descending); rank for truncation (Alg 4).
+__global__ __launch_bounds__(VNT) void k_kw_upper(int n, const double* __restrict__ h, double margin,
+                                                  DevState* __restrict__ st) {
+  if (st->stop) return;
+  __shared__ double sh[VNT / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += VNT) s = fma(h[i], h[i], s);
+  s = bsum(s, sh);
+  if (threadIdx.x == 0) {
+    const double th2 = st->theta2, x2 = st->x2;
+    const double bound = sqrt(th2 / (1.0 + th2 * x2)) * sqrt(s);
+    if (margin * bound < st->fro_u) {
+      st->be_sk = bound;
+      st->kw_evals += 1;
+      st->stop = 1;
+      st->converged = 1;
+      __hip_atomic_store(&st->svd_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 __global__ void k_sigma_stats(int n, const double* __restrict__ sigma, double tau_factor, DevState* __restrict__ st) {
+  // an SVD abandoned by the refinement (st->svd_abort) leaves the bounds in place
+  if (__hip_atomic_load(&st->svd_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
   if (threadIdx.x == 0) {
     const double s1 = sigma[0], sn = sigma[n - 1];
     st->normest = s1;
@@ -516,6 +796,10 @@ __global__ __launch_bounds__(VNT) void k_kw(int n, const double* __restrict__ w,
   }
 }
 
+__global__ void k_fill_ints(int* p, int count, int v) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = v;
+}
+
 __global__ void k_set_int(int* p, int v) {
   if (threadIdx.x == 0) *p = v;
 }
@@ -548,6 +832,34 @@ hipError_t fs_launch_trsv(const double* R, int64_t ldr, int n, bool transpose, c
   }
   hipLaunchKernelGGL(k_trsv, dim3(1), dim3(VNT), sh, s, R, ldr, n, transpose ? 1 : 0, y, x, yscale, xscale, stop,
                      (int64_t)0, (int64_t)0);
+  return hipGetLastError();
+}
+
+size_t fs_trsv_flow_bytes(int n) {
+  const int nb = (n + TF_B - 1) / TF_B;
+  return sizeof(double) * (size_t)n + sizeof(int) * ((size_t)nb + 8) + 64;
+}
+
+// xbuf (n doubles) then the flag words: cleared by fs_trsv_flow_reset before the first launch
+hipError_t fs_trsv_flow_reset(int n, void* ws, hipStream_t s) {
+  const int nb = (n + TF_B - 1) / TF_B;
+  int* flags = (int*)((double*)ws + n);
+  hipLaunchKernelGGL(k_fill_ints, dim3(1), dim3(256), 0, s, flags, nb + 2, 0);
+  return hipGetLastError();
+}
+
+int* fs_trsv_flow_err_word(int n, void* ws) {
+  const int nb = (n + TF_B - 1) / TF_B;
+  return (int*)((double*)ws + n) + nb + 1;
+}
+
+hipError_t fs_launch_trsv_flow(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
+                               const double* yscale, const double* xscale, const int* stop, void* ws, hipStream_t s) {
+  const int nb = (n + TF_B - 1) / TF_B;
+  double* xbuf = (double*)ws;
+  int* flags = (int*)(xbuf + n);
+  hipLaunchKernelGGL(k_trsv_flow, dim3((unsigned)nb), dim3(TF_NT), 0, s, R, ldr, n, transpose ? 1 : 0, y, x, yscale,
+                     xscale, stop, xbuf, flags);
   return hipGetLastError();
 }
 
@@ -588,9 +900,47 @@ hipError_t fs_vec_diag_bounds(int n, const double* R, int64_t ldr, DevState* st,
   hipLaunchKernelGGL(k_diag_bounds, dim3(1), dim3(VNT), 0, s, n, R, ldr, st);
   return hipGetLastError();
 }
+hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, int iters, double* work, double* part,
+                                  void* trsv_ws, DevState* st, hipStream_t s) {
+  double* v = work;          // power-iteration vector
+  double* x = work + n;      // inverse-iteration vector
+  double* p = work + 2 * n;  // R v
+  double* q = work + 3 * n;  // R^T R v
+  double* w = work + 4 * n;  // R^{-T} x
+  double* y = work + 5 * n;  // R^{-1} R^{-T} x
+  hipLaunchKernelGGL(k_bound_init, dim3(1), dim3(VNT), 0, s, n, v, x);
+  const int cs = 64, ns = (n + cs - 1) / cs;
+  for (int k = 0; k < iters; ++k) {
+    hipLaunchKernelGGL(k_trmv_part, dim3((n + 255) / 256, ns), dim3(256), 0, s, R, ldr, n, v, part, cs);
+    hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, s, part, ns, n, (const double*)nullptr,
+                       (const double*)nullptr, p, (const int*)nullptr);
+    hipLaunchKernelGGL(k_trmv_t, dim3(n), dim3(256), 0, s, R, ldr, n, p, q);
+    hipError_t e = fs_launch_trsv_flow(R, ldr, n, true, x, w, nullptr, nullptr, nullptr, trsv_ws, s);
+    if (e != hipSuccess) return e;
+    e = fs_launch_trsv_flow(R, ldr, n, false, w, y, nullptr, nullptr, nullptr, trsv_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bound_step, dim3(1), dim3(VNT), 0, s, n, p, v, q, w, y, v, x, st);
+  }
+  return hipGetLastError();
+}
+
 hipError_t fs_vec_record_iter(int j, int n, const double* dy, double* hist_dy, double* hist_dn, const DevState* st,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_record_iter, dim3(1), dim3(VNT), 0, s, j, n, dy, hist_dy, hist_dn, st);
+  return hipGetLastError();
+}
+hipError_t fs_vec_kw_upper(int n, const double* h, double margin, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_kw_upper, dim3(1), dim3(VNT), 0, s, n, h, margin, st);
+  return hipGetLastError();
+}
+hipError_t fs_vec_kw_record(int c, int j, int n, const double* dy, const double* g, double* kdy, double* kg,
+                            double* ks, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_kw_record, dim3(1), dim3(VNT), 0, s, c, j, n, dy, g, kdy, kg, ks, st);
+  return hipGetLastError();
+}
+hipError_t fs_vec_kw_replay(int n, int ncheck, const double* W, const double* sigma, const double* kdy,
+                            const double* ks, double* dy, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_kw_replay, dim3(1), dim3(VNT), 0, s, n, ncheck, W, sigma, kdy, ks, dy, st);
   return hipGetLastError();
 }
 hipError_t fs_vec_rollback(int n, const double* hist_dy, const double* hist_dn, double* dy, DevState* st,

@@ -21,13 +21,15 @@ struct DevState {
   double b2;             // ||b||^2
   double l_alpha, l_beta;       // LSQR: alpha_i, beta_i of the Golub-Kahan bidiagonalization
   double l_phibar, l_rhobar;    // LSQR: the rotated right-hand side and diagonal
+  double smin_ub;        // upper bound of sigma_min(R) (inverse iteration), for the condest bound
   int stop;              // inner-loop stop flag
   int iters;             // inner iterations in the current step
   int converged;         // the current step stopped by its rule (not by the cap)
   int max_inner;         // iteration cap per step
   int rank_trunc;        // #{sigma_i > tau normest}
   int kw_evals;          // sketched-KW evaluations
-  int pad[2];
+  int kw_pending;        // second step beside the SVD: KW checkpoints recorded, not yet evaluated
+  int svd_abort;         // the SVD beside the refinement is no longer needed (its sweeps stop)
 };
 
 hipError_t fs_vec_gemv_v(const double* V, int64_t ldv, int n, int k, const double* y, const double* ydiv,
@@ -40,10 +42,23 @@ hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, do
 // First step overlapped with the SVD of R: per-iteration record of dy and ||Delta||^2, and the
 // rollback to the first recorded iteration that meets the first-step rule once thr_first is known.
 hipError_t fs_vec_diag_bounds(int n, const double* R, int64_t ldr, DevState* st, hipStream_t s);
+// Sharper bounds for the same purpose (after fs_vec_diag_bounds): `iters` steps of power iteration
+// on R^T R (normest from below) and of inverse iteration (sigma_min from above, condest from below).
+// work: 4 n doubles; trsv_ws: the workspace of the triangular solves across work-groups.
+hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, int iters, double* work, double* part,
+                                  void* trsv_ws, DevState* st, hipStream_t s);
 hipError_t fs_vec_record_iter(int j, int n, const double* dy, double* hist_dy, double* hist_dn, const DevState* st,
                               hipStream_t s);
 hipError_t fs_vec_rollback(int n, const double* hist_dy, const double* hist_dn, double* dy, DevState* st,
                            hipStream_t s);
+// Second step beside the SVD of R: a KW checkpoint (Alg 4's second-step rule) cannot be evaluated
+// before Sigma and V exist, so it is recorded (dy, g = A_s^T r_hat, ||r_hat||^2, ||x_hat||^2, j) into
+// slot c; once they exist, the recorded checkpoints are evaluated in order (W: slot c holds
+// V^T g_c) and the first that meets the rule ends the step there (dy and the count rolled back).
+hipError_t fs_vec_kw_record(int c, int j, int n, const double* dy, const double* g, double* kdy, double* kg,
+                            double* ks, DevState* st, hipStream_t s);
+hipError_t fs_vec_kw_replay(int n, int ncheck, const double* W, const double* sigma, const double* kdy,
+                            const double* ks, double* dy, DevState* st, hipStream_t s);
 // LSQR form of SPIR: start of a step (needs st->r2 = ||r||^2 and c = P^T A_s^T r), one bidiagonalization
 // and rotation step (h = P^T A_s^T (alpha u - A_s P v), st->r2 its squared residual), and the
 // m-vector ubar = alpha u from the stored residual r (sign -1 inside the iteration).
@@ -61,6 +76,11 @@ hipError_t fs_vec_add_norm(int n, const double* x, const double* z, double* out,
 hipError_t fs_vec_mul(int n, const double* a, const double* b, double* out, const int* stop, hipStream_t s);
 hipError_t fs_vec_scaling(int n, const double* colnorm2, bool use_scaling, double* dinv, DevState* st, hipStream_t s);
 hipError_t fs_vec_sigma_stats(int n, const double* sigma, double tau_factor, DevState* st, hipStream_t s);
+// The second step beside the SVD: an upper bound of the sketched KW estimate from R alone,
+// ||(Sigma^2 + lambda I)^{-1/2} V^T g|| <= ||Sigma^{-1} V^T g|| = ||R^{-T} g|| (h = R^{-T} g given).  When
+// `margin` times the bound meets the second-step rule, the rule is met: the step stops there and the
+// SVD is told to stop (st->svd_abort).
+hipError_t fs_vec_kw_upper(int n, const double* h, double margin, DevState* st, hipStream_t s);
 hipError_t fs_vec_first_threshold(int n, const double* x0, double gamma, double rho, DevState* st, hipStream_t s);
 hipError_t fs_vec_kw(int n, const double* w, const double* sigma, DevState* st, hipStream_t s);
 hipError_t fs_vec_set_int(int* p, int v, hipStream_t s);

@@ -30,3 +30,17 @@ def empty_colmajor(rows, cols, ld=None):
 
     ld = ld or rows
     return torch.zeros((cols, ld), dtype=torch.float64, device="cuda").t()[:rows, :]
+
+
+def assert_stats(info, condest, normest=None, rel=1e-9):
+    """normest / condest of a GPU solve against reference values.  Exact (to `rel`) when the SVD of R
+    finished; when the solve stopped before needing it (FS_FLAG_SVD_ABANDONED) they are lower bounds
+    from diag(R) and a few power / inverse iteration steps: at most the true value, within 4x."""
+    abandoned = bool(info.flags & 16)
+    for got, ref in ((info.condest, condest), (info.normest, normest)):
+        if ref is None:
+            continue
+        if abandoned:
+            assert ref / 4 <= got <= ref * (1 + 1e-6), (got, ref, "lower bound")
+        else:
+            assert abs(got - ref) <= rel * ref, (got, ref)

@@ -131,7 +131,9 @@ def test_solo_vs_mix(ctx):
         fm, fs = mix_info[i].flags & binding.FS_FLAG_FP64_SKETCH, solo_info[i].flags & binding.FS_FLAG_FP64_SKETCH
         if abs(np.log2(max(solo_info[i].condest, 1.0) * 2.0**-24)) > 0.5:  # away from the mixed threshold
             assert fm == fs, (i, mix_info[i].to_dict(), solo_info[i].to_dict())
-        assert abs(mix_info[i].condest - solo_info[i].condest) <= 1e-6 * solo_info[i].condest
+        # condest moves with the rounding of the sketch's atomic sums: |d sigma_min| <~ u ||S A||_F
+        cs = solo_info[i].condest
+        assert abs(mix_info[i].condest - cs) <= 50 * U * np.sqrt(P.A.shape[1]) * cs**2 + 1e-10 * cs
         assert abs(mix_info[i].iters[0] - solo_info[i].iters[0]) <= 2, (i, mix_info[i].iters, solo_info[i].iters)
         if P.kappa < 1e12:
             assert abs(mix_info[i].iters[1] - solo_info[i].iters[1]) <= 5, (i, mix_info[i].iters, solo_info[i].iters)
