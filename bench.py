@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--pass-only", action="store_true",
                     help="profiling mode: a 1 GiB device copy (counter calibration) then the fused pass "
                          "A^T(A z) at m=1e6, n=1000, --pass-repeats times; prints one JSON line")
+    ap.add_argument("--sketch-profile", action="store_true",
+                    help="profiling mode: two FP64 and two mixed-precision solves (FP32 copy resident) of the "
+                         "1e6 x 1000, kappa 1e6 problem, so that the FP64 and FP32-copy sketch kernels run under "
+                         "a counter profiler; prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slot-sweep", type=lambda v: [int(t) for t in v.split(",") if t], default=[1, 2, 4, 8, 16],
                     help="slot counts of the saturated-throughput sweep (comma separated; empty: skip)")
@@ -329,6 +333,31 @@ def pass_only(args):
     ctx.close()
 
 
+def sketch_profile(args):
+    """Counter workload for the sketch kernels: the kappa = 1e6 problem of the mixed-precision line
+    (its FP32-copy sketch is kept), solved twice in FP64 and twice in the mixed form with A32 resident."""
+    import torch
+
+    from paper_2406_03468_amd import binding
+    from synth import make_problem_torch
+
+    dev = torch.device("cuda:0")
+    P = make_problem_torch(M, N, 1e6, RESID[1], seed=4)
+    A32 = torch.empty((N, M), dtype=torch.float32, device=dev).t()
+    ctx = binding.Context(0)
+    binding.fs_to_fp32(ctx, P.A, A32)
+    x = torch.zeros(N, dtype=torch.float64, device=dev)
+    out = {"mode": "sketch-profile", "fp64_sketch_ms": [], "mixed_sketch_ms": []}
+    for _ in range(2):
+        _, i64 = binding.fossils_solve(ctx, P.A, P.b, x)
+        _, im = binding.fossils_solve_mixed(ctx, P.A, P.b, x, A32)
+        out["fp64_sketch_ms"].append(round(i64.phase_ms[0], 3))
+        out["mixed_sketch_ms"].append(round(im.phase_ms[0], 3))
+        out["mixed_kept_fp32_sketch"] = not bool(im.flags & binding.FS_FLAG_FP64_SKETCH)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def prony_bench(ctx, args, dev):
     """Complex least squares at the paper's Prony shape (Section 5.2, Appendix B): the first solve of
     Prony's method, m = 5e5, n = 1000, Toeplitz A = (f_{n-1+i-j}), b = (f_{n-1+i}), f_j the sum of
@@ -454,6 +483,8 @@ def main():
     args = parse()
     if args.pass_only:
         return pass_only(args)
+    if args.sketch_profile:
+        return sketch_profile(args)
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: the row-sharded multi-GPU form is a design, "
                                    "not built", "n_gpus": args.gpus}))
