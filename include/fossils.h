@@ -202,6 +202,19 @@ fs_status fossils_solve_mixed(fs_context ctx, int64_t m, int32_t n, const double
 /* A32 = fl32(A) on the context's stream (for callers that keep an FP32 copy resident). */
 fs_status fs_to_fp32(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, float* A32, int64_t lda32);
 
+/* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): fossils_solve with the same arguments and results, whose every
+ * device buffer is a slice of one array of 256 MiB that the library holds on each GPU it runs on until
+ * the process ends (its device address is looked up on the first call on a device).  Nothing is
+ * allocated or freed; the solve runs in the serial order (opts->overlap_svd and opts->graph_sweeps are
+ * treated as 0).  FS_ERR_TOO_LARGE, before any device work, when the solve's workspace (about
+ * m (2 zeta + 8) + 8 d (n + 1) + 40 n^2 bytes plus the QR and SVD exchange buffers) exceeds the array:
+ * with n = 1000, d = 12000 it fits m up to about 2.9e6.  All calls on one GPU share the array, so calls
+ * that overlap in time on one GPU (two threads, or two streams in flight) race: the caller serializes
+ * them.  Nothing carries over between calls: every buffer is initialized by the call's own kernels. */
+fs_status fossils_solve_noalloc(fs_context ctx, int64_t m, int32_t n, const double* A, int64_t lda, const double* b,
+                                double* x, const fs_options* opts, fs_info* info);
+
 /* ---------------- sparse sign embedding (Section 4.2, "Choice of embedding") ---------------- */
 
 /* Sketch handle for S (d x m, zeta nonzeros per column).  The index stream is generated on the

@@ -106,6 +106,8 @@ _SIGS = [
                                      ctypes.POINTER(FsInfo)]),
     ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
+    ("fossils_solve_noalloc", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
+                                        ctypes.POINTER(FsInfo)]),
     ("fossils_solve_mixed", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64, c_vp, c_vp,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
     ("fs_to_fp32", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64]),
@@ -238,6 +240,13 @@ def _solve(fn, ctx: Context, A, b, x, opts: Optional[FsOptions]):
 
 def fossils_solve(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
     s, info = _solve(load().fossils_solve, ctx, A, b, x, opts)
+    _check(s)
+    return s, info
+
+
+def fossils_solve_noalloc(ctx: Context, A, b, x, opts: Optional[FsOptions] = None):
+    """fossils_solve on the library's preallocated device array (allocates nothing)."""
+    s, info = _solve(load().fossils_solve_noalloc, ctx, A, b, x, opts)
     _check(s)
     return s, info
 
