@@ -334,14 +334,20 @@ def pass_only(args):
 
 
 def sketch_profile(args):
-    """Counter workload for the sketch kernels: the kappa = 1e6 problem of the mixed-precision line
-    (its FP32-copy sketch is kept), solved twice in FP64 and twice in the mixed form with A32 resident."""
+    """Counter workload for the sketch kernels: a plain 1 GiB device copy (the calibration of the
+    byte counters), then the kappa = 1e6 problem of the mixed-precision line (its FP32-copy sketch is
+    kept), solved twice in FP64 and twice in the mixed form with A32 resident."""
     import torch
 
     from paper_2406_03468_amd import binding
     from synth import make_problem_torch
 
     dev = torch.device("cuda:0")
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB copy: counter calibration
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     P = make_problem_torch(M, N, 1e6, RESID[1], seed=4)
     A32 = torch.empty((N, M), dtype=torch.float32, device=dev).t()
     ctx = binding.Context(0)
