@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-precision line")
     ap.add_argument("--no-prony", dest="prony", action="store_false", help="skip the complex (Prony) line")
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
+    ap.add_argument("--batch-sizes", type=lambda v: [int(t) for t in v.split(",") if t], default=[128, 512],
+                    help="batch sizes of the fossils_solve_batched comparison (comma separated; empty: skip)")
     return ap.parse_args()
 
 
@@ -233,7 +235,109 @@ def serve_bench(ctx, args, dev):
             sv.close()
         slot_sweep.append({"slots": ns, "solves_per_s": round(rate, 1)})
         print(f"# serving slot sweep: {ns} slots {rate:.1f} solves/s", file=sys.stderr, flush=True)
+    # FOSSILS in FP64 only (the form of the batched entry point) on the first 512 requests of the same
+    # stream: the server (all submitted at once), then fossils_solve_batched on consecutive chunks
+    batched = None
+    if args.batch_sizes:
+        nreq = min(R, 512)
+        fp = [(P, x) for (P, _, _), x in zip(reqs[:nreq], outs[:nreq])]
+        sv = binding.Server(ctx, hbm_budget=32 << 30, max_slots=args.serve_slots)
+        try:
+            wt = [binding.batched_submit(sv, P.A, P.b, x) for P, x in fp[: 2 * args.serve_slots]]
+            for t in wt:
+                binding.fs_server_wait(sv, t)
+            ts = time.perf_counter()
+            tks = [binding.batched_submit(sv, P.A, P.b, x) for P, x in fp]
+            for t in tks:
+                binding.fs_server_wait(sv, t)
+            srv_rate = nreq / (time.perf_counter() - ts)
+        finally:
+            sv.close()
+        print(f"# FP64 FOSSILS stream, server {args.serve_slots} slots: {srv_rate:.1f} solves/s", file=sys.stderr,
+              flush=True)
+        rates = []
+        for bs in args.batch_sizes:
+            chunks = [fp[i:i + bs] for i in range(0, nreq, bs)]
+            binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in chunks[0]])  # warm-up
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            worst = 0
+            loop_ms = []
+            for ch in chunks:
+                st_, sts, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in ch], check=False)
+                worst = min(worst, st_)
+                loop_ms.append(infs[0].phase_ms[4])
+            rate = nreq / (time.perf_counter() - ts)
+            rates.append({"batch": bs, "solves_per_s": round(rate, 1), "worst_status": int(worst),
+                          "refinement_ms_mean": round(float(np.mean(loop_ms)), 2)})
+            print(f"# FP64 FOSSILS stream, fossils_solve_batched in batches of {bs}: {rate:.1f} solves/s "
+                  f"(refinement {np.mean(loop_ms):.1f} ms per batch), worst status {worst}", file=sys.stderr,
+                  flush=True)
+        bes_b = []
+        if not args.no_check:
+            from oracle import backward_error as be
+            for i in (0, nreq - 1):
+                P, x = fp[i]
+                A_h, b_h, x_h = P.A.cpu().numpy(), P.b.cpu().numpy(), x.cpu().numpy()
+                fro = np.sqrt(np.sum(A_h * A_h))
+                bes_b.append(float(be.kw_known_svd(A_h, b_h, x_h, P.sigma, P.V, fro / np.linalg.norm(b_h)) / fro))
+            print(f"# batched accuracy sample: BE {bes_b}", file=sys.stderr, flush=True)
+        # a stream of small problems (m ~ U[2e3, 2e4], n ~ U[10, 100], m >= 20 n, the same kappa and
+        # residual laws), where the per-solve latency of the factorization dominates
+        srng = np.random.default_rng(7)
+        spool = []
+        for i in range(64):
+            n_s = int(srng.integers(10, 101))
+            m_s = int(srng.integers(max(20 * n_s, 2000), 20001))
+            spool.append(make_problem_torch(m_s, n_s, 10.0 ** srng.uniform(2, 12), 10.0 ** srng.uniform(-12, 0),
+                                            seed=5000 + i))
+        nsm = 1024
+        sreq = [(spool[i % len(spool)], torch.zeros(spool[i % len(spool)].A.shape[1], dtype=torch.float64, device=dev))
+                for i in range(nsm)]
+        torch.cuda.synchronize()
+        sv = binding.Server(ctx, hbm_budget=32 << 30, max_slots=args.serve_slots)
+        try:
+            wt = [binding.batched_submit(sv, P.A, P.b, x) for P, x in sreq[: 2 * args.serve_slots]]
+            for t in wt:
+                binding.fs_server_wait(sv, t)
+            ts = time.perf_counter()
+            tks = [binding.batched_submit(sv, P.A, P.b, x) for P, x in sreq]
+            for t in tks:
+                binding.fs_server_wait(sv, t)
+            small_srv = nsm / (time.perf_counter() - ts)
+        finally:
+            sv.close()
+        small_rates = []
+        for bs in (256, 1024):
+            binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in sreq[:bs]])  # warm-up
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            worst = 0
+            for c0 in range(0, nsm, bs):
+                st_, _, _ = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in sreq[c0:c0 + bs]],
+                                                          check=False)
+                worst = min(worst, st_)
+            small_rates.append({"batch": bs, "solves_per_s": round(nsm / (time.perf_counter() - ts), 1),
+                                "worst_status": int(worst)})
+        bes_s = []
+        if not args.no_check:
+            from oracle import backward_error as be
+            for i in (0, nsm - 1):
+                P, x = sreq[i]
+                A_h, b_h, x_h = P.A.cpu().numpy(), P.b.cpu().numpy(), x.cpu().numpy()
+                fro = np.sqrt(np.sum(A_h * A_h))
+                bes_s.append(float(be.kw_known_svd(A_h, b_h, x_h, P.sigma, P.V, fro / np.linalg.norm(b_h)) / fro))
+        print(f"# small-problem stream ({nsm} requests): server {small_srv:.1f} solves/s, batched {small_rates}, "
+              f"BE sample {bes_s}", file=sys.stderr, flush=True)
+        batched = {"requests": nreq, "server_solves_per_s": round(srv_rate, 1), "server_slots": args.serve_slots,
+                   "batched": rates, "be_sample": bes_b,
+                   "workload": "the serving stream's first requests, every one FOSSILS in FP64",
+                   "small_stream": {"requests": nsm, "server_solves_per_s": round(small_srv, 1),
+                                    "batched": small_rates, "be_sample": bes_s,
+                                    "workload": "m~U[2e3,2e4], n~U[10,100], m>=20n, kappa=10^U[2,12], "
+                                                "||r|| log-U[1e-12,1], FOSSILS FP64, 64 distinct problems"}}
     return {"requests": R, "slots": args.serve_slots, "plain_solves_per_s": round(plain_thr, 1),
+            "fp64_fossils_batched": batched,
             "plain_requests": nplain, "plain_errors": plain_bad, "plain_be_sample": plain_be,
             "served_over_plain": round(thr / plain_thr, 3), "slot_sweep": slot_sweep, "pool": len(pool), "saturated_solves_per_s": round(thr, 1),
             "saturated_GBps_of_A": round(gbytes / sat_s, 1), "mean_service_ms": round(service_ms, 2),

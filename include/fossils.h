@@ -190,6 +190,39 @@ fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, const double
                               const double* B, int64_t ldb, double* X, int64_t ldx, const fs_options* opts,
                               fs_info* info);
 
+/* One problem of a batch: A (m x n, lda >= m), b (m) and x (n, output), device arrays. */
+typedef struct fs_problem {
+  int64_t m;
+  int32_t n;
+  const double* A;
+  int64_t lda;
+  const double* b;
+  double* x;
+} fs_problem;
+
+/* FOSSILS (Algorithm 4, P = V Sigma^{-1}) for count (1..65535) independent problems of any shapes,
+ * each with the result fossils_solve gives it in the serial order (opts->overlap_svd = 0), up to the
+ * order of floating-point sums: the same iterations, stopping rules and d = 12 n.  opts, if not NULL,
+ * applies to every problem except d, which is 12 n_i for each (zeta <= d), and the form: FP64,
+ * sketch-and-solve start, adaptive steps.  The sketch, QR, SVD and x_0 of the problems run in problem
+ * order on up to eight internal streams of the context (their grid-synchronizing kernels reserve
+ * compute units so that concurrent grids fit).  The two refinement steps run in lockstep on the
+ * context's stream for waves of consecutive problems (a quarter of the batch, 8 to 64 problems) as soon
+ * as their setup is done, beside the setup of the next waves: each phase of an inner iteration is one
+ * launch for the whole wave (the passes over A as one grid whose work-groups are shared out among the
+ * problems in proportion to their m n), and a problem that has met its stopping rule skips the rest.
+ * Problems with n > 1024 (or 16 lda (512 / H) >= 2^32 bytes, H the pass tile height), a numerically
+ * rank-deficient sketch, or b = 0, are solved by fossils_solve after the batch, with the caller's
+ * options (overlap_svd as given, default on).
+ * statuses[i] receives problem i's status; infos (if not NULL) count records, where phase_ms[0] is
+ * that problem's setup time on its stream and phase_ms[4] its wave's refinement time (other phases
+ * 0).  Inputs must be complete on the context's stream (the call waits for it); on return every x is
+ * written.  Returns FS_OK, the largest warning of the problems, or the first error among them.
+ * Workspace: about 8 n_i^2 + 8 G_i n_i bytes per problem kept for the batch, plus eight per-stream
+ * workspaces sized like fossils_solve's for the largest problem.  The context's thread only. */
+fs_status fossils_solve_batched(fs_context ctx, int32_t count, const fs_problem* problems, const fs_options* opts,
+                                fs_info* infos, fs_status* statuses);
+
 /* Mixed-precision form: the sketch S [A_s b] is taken of the single-precision copy of A (A32 =
  * fl32(A), column-major lda32 >= m, when A32 is not NULL, else A rounded to FP32 as it is read), with
  * FP64 sums; QR, SVD and the whole refinement (every pass over A) stay FP64 on A.  The FP32 copy

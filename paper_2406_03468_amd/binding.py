@@ -69,6 +69,10 @@ class FsInfo(ctypes.Structure):
         }
 
 
+class FsProblem(ctypes.Structure):
+    _fields_ = [("m", c_int64), ("n", c_int32), ("A", c_vp), ("lda", c_int64), ("b", c_vp), ("x", c_vp)]
+
+
 class FsRequest(ctypes.Structure):
     _fields_ = [("method", c_int32), ("m", c_int64), ("n", c_int32), ("A", c_vp), ("lda", c_int64), ("b", c_vp),
                 ("x", c_vp), ("opts", ctypes.POINTER(FsOptions)), ("stream", c_vp)]
@@ -106,6 +110,8 @@ _SIGS = [
                                      ctypes.POINTER(FsInfo)]),
     ("fossils_solve_multi", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64,
                                       ctypes.POINTER(FsOptions), ctypes.POINTER(FsInfo)]),
+    ("fossils_solve_batched", c_int32, [c_vp, c_int32, ctypes.POINTER(FsProblem), ctypes.POINTER(FsOptions),
+                                        ctypes.POINTER(FsInfo), ctypes.POINTER(c_int32)]),
     ("fossils_solve_noalloc", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, ctypes.POINTER(FsOptions),
                                         ctypes.POINTER(FsInfo)]),
     ("fossils_solve_mixed", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_int64, c_vp, c_vp,
@@ -314,6 +320,25 @@ def fossils_solve_multi(ctx: Context, A, B, X, opts: Optional[FsOptions] = None)
                                    ctypes.byref(opts) if opts is not None else None, infos)
     _check(s)
     return s, list(infos)
+
+
+def fossils_solve_batched(ctx: Context, problems, opts: Optional[FsOptions] = None, check: bool = True):
+    """problems: a list of (A, b, x) device tensors (A column-major (m_i, n_i), b (m_i,), x (n_i,) output).
+    Returns (status, [status_i], [FsInfo_i]); with check, an error status raises FossilsError."""
+    k = len(problems)
+    arr = (FsProblem * k)()
+    for i, (A, b, x) in enumerate(problems):
+        m, n = A.shape
+        if b.shape[0] != m or x.shape[0] != n:
+            raise ValueError("shape mismatch in problem %d" % i)
+        arr[i] = FsProblem(int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(x)))
+    infos = (FsInfo * k)()
+    sts = (c_int32 * k)()
+    s = load().fossils_solve_batched(ctx.h, int(k), arr, ctypes.byref(opts) if opts is not None else None, infos,
+                                     sts)
+    if check:
+        _check(s)
+    return s, list(sts), list(infos)
 
 
 class Server:

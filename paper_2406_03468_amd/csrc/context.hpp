@@ -33,6 +33,7 @@ struct Workspace {
   DevBuf hist;                  // first step beside the SVD: iterates and ||Delta||^2 per iteration
   DevBuf cplx;                  // complex problems: the realified A (2m x 2n), b and x
   DevBuf trsv;                  // triangular solves across work-groups: published x and block flags
+  DevBuf batch;                 // fossils_solve_batched: per-problem factors, vectors and work-lists
 };
 
 struct fs_context_s {
@@ -54,6 +55,7 @@ struct fs_context_s {
   std::map<std::pair<int, int>, std::pair<int, int>> pass_tuned;  // -> (H, G)
   bool pass_force = false;     // while tuning: every pass uses pass_force_cfg
   int pass_force_H = 0, pass_force_G = 0;
+  struct BatchHelpers* batch = nullptr;  // fossils_solve_batched: setup contexts (created on first use)
 };
 
 // Cooperative kernels (QR, SVD) need every work-group of their grid resident at once.  Slots of a
@@ -117,6 +119,8 @@ size_t fs_carve_workspace(Workspace& w, unsigned char* base, int64_t m, int32_t 
 fs_status fs_fossils_solve_fixed(fs_context ctx, unsigned char* base, size_t cap, int64_t m, int32_t n,
                                  const double* A, int64_t lda, const double* b, double* x, const fs_options& opts,
                                  fs_info* info);
+// Destroys the setup contexts of fossils_solve_batched (if any).
+void fs_batch_helpers_destroy(fs_context_s* c);
 fs_status fs_validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, const void* b, const void* x);
 fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o);
 inline bool fs_idx16_ok(int d) { return d <= 32767; }

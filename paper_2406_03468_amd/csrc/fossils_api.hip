@@ -74,7 +74,7 @@ void fs_free_buf(DevBuf& b) {
 std::vector<DevBuf*> fs_workspace_buffers(Workspace& w) {
   return {&w.idx, &w.Y,       &w.colnorm2, &w.dinv,  &w.qrwork, &w.svdwork, &w.sigma, &w.V,    &w.UR,
           &w.partial, &w.pr2, &w.wscratch, &w.gemvpart, &w.vecs, &w.state, &w.mwork, &w.mvecs, &w.mstate,
-          &w.lsqr, &w.hist, &w.cplx, &w.trsv};
+          &w.lsqr, &w.hist, &w.cplx, &w.trsv, &w.batch};
 }
 
 size_t fs_workspace_bytes(Workspace& w) {
@@ -259,6 +259,7 @@ fs_status fs_context_destroy(fs_context c) {
     (void)hipStreamDestroy(c->aux_stream);
   }
   if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
+  fs_batch_helpers_destroy(c);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (c->st_host) (void)hipHostFree(c->st_host);
@@ -753,11 +754,13 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
                                   true, ctx->lds_bytes, s));
     FS_K(fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, s));
     FS_HIP(hipEventRecord(ev[1], s));
-    // grid-synchronizing kernels: work-groups reserved against other slots of a server
-    CoopSection coop(ctx, defer_svd ? fs_qr_grid_size(d, ctx->num_cu)
-                                    : std::max(fs_qr_grid_size(d, ctx->num_cu), fs_svd_grid_size(n, ctx->num_cu, false)));
-    FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
-    FS_HIP(hipEventRecord(ev[2], s));
+    // grid-synchronizing kernels: work-groups reserved against other slots of a server, the QR's and
+    // the (smaller, longer-running) SVD's one after the other
+    {
+      CoopSection coop(ctx, fs_qr_grid_size(d, ctx->num_cu));
+      FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
+      FS_HIP(hipEventRecord(ev[2], s));
+    }
     bool bounds_done = false;
     if (fp32) {
       // A lower bound of cond(R) (diag(R), then power and inverse iteration, about 0.5 ms at n = 1000)
@@ -786,6 +789,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
         FS_K(fs_vec_spectral_bounds(n, R, ldr, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st, s));
       }
     } else {
+      CoopSection coop(ctx, fs_svd_grid_size(n, ctx->num_cu, false));
       FS_K(fs_launch_svd_full(R, ldr, n, sigma, V, n, nullptr, n, W.svdwork.p, ctx->num_cu, o.max_sweeps,
                               svd_sweeps_dev, s));
       FS_K(fs_vec_sigma_stats(n, sigma, o.tau_factor, st, s));

@@ -17,6 +17,24 @@ struct PassArgs {
   const int* stop;       // device stop flag (may be null)
   double* rout = nullptr;  // m, residual mode only: receives r = b - A zs (may be null)
 };
+// One problem of a batched pass (fs_launch_pass_batched): its operands, the slice of the grid that
+// works on it (G work-groups from wg0) and where its reduced result goes.
+struct BatchPass {
+  const double* A;
+  int64_t lda;
+  int64_t m;
+  int n;
+  const double* zs;      // n, pre-scaled vector
+  const double* b;       // m (residual passes)
+  double* partial;       // [G][n]
+  double* partial_r2;    // [G]
+  const int* stop;       // the problem's stop flag
+  int wg0, G;
+  double* out;           // n: out_scale .* (A^T w)
+  const double* out_scale;
+  double* r2_out;        // ||w||^2 (residual passes)
+};
+
 struct PassConfig {
   int H;  // tile rows (0 = unfused fallback)
   int G;  // work-groups
@@ -25,6 +43,13 @@ PassConfig fs_pass_config(int64_t m, int n, int num_cu);
 // out = out_scale .* (A^T w), w = A zs (normal) or b - A zs (residual, r2_out = ||w||^2).
 hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out, const double* out_scale,
                           double* r2_out, double* w_scratch, hipStream_t s);
+// Passes of many problems in two launches per (H, L, vec) group: list (device) holds `count` problems
+// that all use tile height H and L column slots per lane (L = ceil(n / (512 / (H / 2)))), their
+// work-group slices consecutive from 0 to total_wgs; vec: every A 16-byte aligned with even lda (16-byte
+// loads), else 8-byte loads.  resid: residual passes (b used, r2_out written).  max_n: the largest n of
+// the list (grid of the reduction).
+hipError_t fs_launch_pass_batched(const BatchPass* list, int count, int H, int L, bool vec, bool resid,
+                                  int total_wgs, int max_n, hipStream_t s);
 // Only the fused kernel (per-work-group partials, no final reduction); fused configurations only.
 hipError_t fs_launch_pass_kernel_only(const PassArgs& a, const PassConfig& cfg, hipStream_t s);
 

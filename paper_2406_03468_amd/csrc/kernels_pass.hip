@@ -25,11 +25,14 @@ namespace {
 
 typedef double fs_v2d __attribute__((ext_vector_type(2)));
 
-template <int H, int NT, int L, bool RESID, bool VEC, bool PF = true>
-__global__ __launch_bounds__(NT, PF ? 1 : 2) void k_fused_pass(const double* __restrict__ A, int64_t lda, int64_t m, int n,
-                                                   const double* __restrict__ zs, const double* __restrict__ b,
-                                                   double* __restrict__ partial, double* __restrict__ partial_r2,
-                                                   const int* __restrict__ stop, double* __restrict__ rout) {
+// The pass of one problem by work-group g of the G work-groups that share it (the whole grid in the
+// single-problem kernel; a slice of the grid in the batched one).
+template <int H, int NT, int L, bool RESID, bool VEC, bool PF>
+__device__ __forceinline__ void fused_pass_body(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+                                                const double* __restrict__ zs, const double* __restrict__ b,
+                                                double* __restrict__ partial, double* __restrict__ partial_r2,
+                                                const int* __restrict__ stop, double* __restrict__ rout,
+                                                const int g, const int G) {
   static_assert(H >= 2 && (H & (H - 1)) == 0 && H <= 128, "H must be a power of two in [2,128]");
   constexpr int RP = H / 2;           // row pairs per tile == lanes per column segment
   constexpr int CPR = NT / RP;        // columns per round
@@ -46,7 +49,6 @@ __global__ __launch_bounds__(NT, PF ? 1 : 2) void k_fused_pass(const double* __r
   const int lane = tid & 63, wv = tid >> 6;
   const int rp = tid % RP;
   const int cb = tid / RP;
-  const int G = gridDim.x, g = blockIdx.x;
 
   // XCD banding of the full row tiles; a ragged last tile (m % H rows) is done at the end.
   const int64_t T = m / H;
@@ -197,6 +199,28 @@ __global__ __launch_bounds__(NT, PF ? 1 : 2) void k_fused_pass(const double* __r
   }
 }
 
+template <int H, int NT, int L, bool RESID, bool VEC, bool PF = true>
+__global__ __launch_bounds__(NT, PF ? 1 : 2) void k_fused_pass(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+                                                   const double* __restrict__ zs, const double* __restrict__ b,
+                                                   double* __restrict__ partial, double* __restrict__ partial_r2,
+                                                   const int* __restrict__ stop, double* __restrict__ rout) {
+  fused_pass_body<H, NT, L, RESID, VEC, PF>(A, lda, m, n, zs, b, partial, partial_r2, stop, rout, (int)blockIdx.x,
+                                            (int)gridDim.x);
+}
+
+// Many problems in one launch: a work-list of problems (all of this instantiation's H and L), each
+// with G_k work-groups starting at wg0[k] (multiples of 8, so a problem's XCD bands stay whole).
+// Work-group -> (problem, local index) by a scan of the list; each problem's partials as above.
+template <int H, int NT, int L, bool RESID, bool VEC>
+__global__ __launch_bounds__(NT, 1) void k_fused_pass_batched(const BatchPass* __restrict__ list, int count) {
+  const int gw = (int)blockIdx.x;
+  int k = 0;
+  while (k + 1 < count && list[k + 1].wg0 <= gw) ++k;
+  const BatchPass& p = list[k];
+  fused_pass_body<H, NT, L, RESID, VEC, true>(p.A, p.lda, p.m, p.n, p.zs, RESID ? p.b : nullptr, p.partial,
+                                               p.partial_r2, p.stop, nullptr, gw - p.wg0, p.G);
+}
+
 // out[c] = scale[c] * sum_g partial[g][c]; optionally r2 = sum_g partial_r2[g].  A work-group
 // takes 64 columns; its 16 row groups each sum every 16th partial, then the 16 sums are added in a
 // fixed order (deterministic, and 16 independent loads in flight per thread instead of G).
@@ -244,6 +268,55 @@ __global__ __launch_bounds__(1024) void k_reduce_partials(const double* __restri
       double t = 0.0;
       for (int q = 0; q < 16; ++q) t += sr[q];
       *r2 = t;
+    }
+  }
+}
+
+// The reduction of k_reduce_partials for each problem of a batched pass (blockIdx.y = problem).
+__global__ __launch_bounds__(1024) void k_reduce_partials_batched(const BatchPass* __restrict__ list) {
+  const BatchPass& p = list[blockIdx.y];
+  if (fs_stopped(p.stop)) return;
+  const int n = p.n, G = p.G;
+  if ((int)blockIdx.x * 64 >= n && blockIdx.x > 0) return;
+  __shared__ double sh[16][65], she[16][65];
+  __shared__ double sr[16];
+  const int cl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
+  double s = 0.0, e = 0.0;
+  if (c < n) {
+#pragma unroll 8
+    for (int gi = grp; gi < G; gi += 16) {
+      double t, d;
+      two_sum(s, p.partial[(int64_t)gi * n + c], t, d);
+      s = t;
+      e += d;
+    }
+  }
+  sh[grp][cl] = s;
+  she[grp][cl] = e;
+  __syncthreads();
+  if (grp == 0 && c < n) {
+    double t = 0.0, te = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      double u, d;
+      two_sum(t, sh[q][cl], u, d);
+      t = u;
+      te += d + she[q][cl];
+    }
+    t += te;
+    p.out[c] = p.out_scale ? t * p.out_scale[c] : t;
+  }
+  if (p.r2_out && blockIdx.x == 0) {
+    double v = 0.0;
+    for (int gi = threadIdx.x; gi < G; gi += 1024) v += p.partial_r2[gi];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sr[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int q = 0; q < 16; ++q) t += sr[q];
+      *p.r2_out = t;
     }
   }
 }
@@ -324,13 +397,37 @@ hipError_t launch_L(const PassArgs& a, int G, bool vec, hipStream_t s) {
 
 template <bool RESID>
 hipError_t launch_fused(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
-  const bool vec = ((a.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0);
+  const bool vec = ((a.lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.A) & 15) == 0) &&
+                   ((reinterpret_cast<uintptr_t>(a.b) & 15) == 0);
   switch (cfg.H) {
     case 64: return launch_L<64, 512, RESID>(a, cfg.G, vec, s);
     case 32: return launch_L<32, 512, RESID>(a, cfg.G, vec, s);
     case 16: return launch_L<16, 512, RESID>(a, cfg.G, vec, s);
     case 8: return launch_L<8, 512, RESID>(a, cfg.G, vec, s);
     case 4: return launch_L<4, 512, RESID>(a, cfg.G, vec, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int H, bool RESID, bool VEC, int LO, int HI>
+hipError_t launch_batched_exact(const BatchPass* list, int count, int L, int total, hipStream_t s) {
+  if constexpr (LO > HI) {
+    return hipErrorInvalidValue;
+  } else {
+    if (L == LO) {
+      hipLaunchKernelGGL((k_fused_pass_batched<H, 512, LO, RESID, VEC>), dim3(total), dim3(512), 0, s, list, count);
+      return hipGetLastError();
+    }
+    return launch_batched_exact<H, RESID, VEC, LO + 1, HI>(list, count, L, total, s);
+  }
+}
+
+template <bool RESID, bool VEC>
+hipError_t launch_batched(const BatchPass* list, int count, int H, int L, int total, hipStream_t s) {
+  switch (H) {
+    case 64: return launch_batched_exact<64, RESID, VEC, 1, 4>(list, count, L, total, s);
+    case 32: return launch_batched_exact<32, RESID, VEC, 1, 8>(list, count, L, total, s);
+    case 16: return launch_batched_exact<16, RESID, VEC, 1, 16>(list, count, L, total, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -384,4 +481,17 @@ hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out,
 hipError_t fs_launch_pass_kernel_only(const PassArgs& a, const PassConfig& cfg, hipStream_t s) {
   if (!cfg.H) return hipErrorInvalidValue;
   return a.b ? launch_fused<true>(a, cfg, s) : launch_fused<false>(a, cfg, s);
+}
+
+hipError_t fs_launch_pass_batched(const BatchPass* list, int count, int H, int L, bool vec, bool resid,
+                                  int total_wgs, int max_n, hipStream_t s) {
+  if (count < 1 || total_wgs < 1) return hipSuccess;
+  hipError_t e = resid ? (vec ? launch_batched<true, true>(list, count, H, L, total_wgs, s)
+                              : launch_batched<true, false>(list, count, H, L, total_wgs, s))
+                       : (vec ? launch_batched<false, true>(list, count, H, L, total_wgs, s)
+                              : launch_batched<false, false>(list, count, H, L, total_wgs, s));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_partials_batched, dim3((unsigned)((max_n + 63) / 64), (unsigned)count), dim3(1024), 0, s,
+                     list);
+  return hipGetLastError();
 }

@@ -129,3 +129,40 @@ hipError_t fs_m_gemm_P(const double* V, int64_t ldv, int n, int nr, int k, const
 // U: nr x k (ld nr).
 hipError_t fs_m_gemm_PT(const double* V, int64_t ldv, int n, int nr, int k, const double* sigma, const double* G,
                         double* U, const int* stop, hipStream_t s);
+
+// One problem of a batched refinement (fossils_solve_batched): its n-vectors, V and Sigma of its
+// sketch, the column scaling, the slices of its V products and its control block.
+struct BatchVec {
+  int n;
+  int done;  // finished before the refinement (nothing to iterate)
+  const double* V;
+  const double* sigma;
+  const double* dinv;
+  double *x, *x0, *c, *dy, *dy_old, *zs, *v, *u, *g, *xh, *w;
+  double* gpart;  // ceil(n / 64) x n
+  double* x_out;  // the caller's x
+  DevState* st;
+};
+enum class BatchOp { SCALE, FIRST_THRESHOLD, STEP_INIT, POLYAK, XH_NORM, KW, FINAL };
+// P dy for every problem (mode 0: zs = D^{-1} P dy; 1: xh = x + P dy; 2: x = x + P dy) and P^T
+// (mode 0: c = P^T g; 1: u = P^T v; 2: w = V^T g), P = V Sigma^{-1}; max_n: the largest n.
+hipError_t fs_b_gemv_P(const BatchVec* list, int count, int max_n, int mode, hipStream_t s);
+hipError_t fs_b_gemv_PT(const BatchVec* list, int count, int max_n, int mode, hipStream_t s);
+// One-work-group-per-problem steps: SCALE (arg 0: zs = D^{-1} x, 1: zs = D^{-1} xh), FIRST_THRESHOLD
+// (gamma, rho), STEP_INIT, POLYAK (arg: first step), XH_NORM, KW, FINAL (x_out = D^{-1} x).
+hipError_t fs_b_vec(const BatchVec* list, int count, BatchOp op, int arg, double gamma, double rho, hipStream_t s);
+// Everything the host reads back after one problem's setup, gathered on the device for one copy.
+struct BatchReport {
+  DevState st;
+  int sweeps;   // Jacobi sweeps of the SVD
+  int err;      // a grid barrier (QR, SVD) or a block flag (substitution) gave up waiting
+  int nan;      // a column norm (or ||b||^2) is NaN: A or b holds NaN or Inf
+  int inf;      // a column norm is +Inf: finite entries whose squares overflow
+  double b2;    // ||b||^2
+};
+hipError_t fs_b_report(const DevState* st, const int* sweeps, const int* qr_err, const int* svd_err,
+                       const int* trsv_err, const double* colnorm2, int n, BatchReport* out, hipStream_t s);
+// out[k] = *list[k].st for the count problems
+hipError_t fs_b_gather(const BatchVec* list, int count, DevState* out, hipStream_t s);
+// theta^2 and ||b||^2 of one problem from the sketch's column norms (colnorm2[n] = ||b||^2).
+hipError_t fs_b_prep(const double* colnorm2, int n, DevState* st, hipStream_t s);
