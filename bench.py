@@ -43,8 +43,8 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per launch of the fused pass at 1e6 x 1000 from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
 # by a 1 GiB copy (profiles/fused_pass_1e6x1000_hbm_traffic.md); valid only for the kernel source
 # with this hash (reported as null otherwise).
-PASS_TRAFFIC_BYTES = 8.0081e9
-PASS_TRAFFIC_SHA256 = "bbacb874cbada7af009d0cd529cd957f7313bfff9fed99d6ce89f1a6a86c93f7"
+PASS_TRAFFIC_BYTES = 8.0080e9
+PASS_TRAFFIC_SHA256 = "f4bd409364bf8690db3a2d48dbf9e68b7867e3217676687e660c1dd4385e06b7"
 
 
 def parse():
