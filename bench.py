@@ -67,6 +67,9 @@ def parse():
                     help="profiling mode: two FP64 and two mixed-precision solves (FP32 copy resident) of the "
                          "1e6 x 1000, kappa 1e6 problem, so that the FP64 and FP32-copy sketch kernels run under "
                          "a counter profiler; prints one JSON line")
+    ap.add_argument("--batched-profile", action="store_true",
+                    help="profiling mode: one fossils_solve_batched call on 256 FP64 requests of the serving "
+                         "stream (after a warm-up call); prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slot-sweep", type=lambda v: [int(t) for t in v.split(",") if t], default=[1, 2, 4, 8, 16],
                     help="slot counts of the saturated-throughput sweep (comma separated; empty: skip)")
@@ -468,6 +471,40 @@ def sketch_profile(args):
     ctx.close()
 
 
+def batched_profile(args):
+    """Profiling workload of fossils_solve_batched: 256 FP64 FOSSILS requests cycling through the 32-problem
+    pool of the serving stream (C5 shapes, the serving line's seeds), solved by one batched call after a
+    warm-up call on the same requests; prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2406_03468_amd import binding
+    from synth import make_problem_torch
+
+    rng = np.random.default_rng(2024)
+    pool = []
+    for i in range(args.serve_pool):
+        while True:
+            m = int(rng.integers(5000, 300001))
+            n = int(rng.integers(20, 501))
+            if m >= 20 * n:
+                break
+        pool.append(make_problem_torch(m, n, 10.0 ** rng.uniform(2, 12), 10.0 ** rng.uniform(-12, 0), seed=1000 + i))
+    reqs = [pool[i % len(pool)] for i in range(256)]
+    outs = [torch.zeros(P.A.shape[1], dtype=torch.float64, device="cuda") for P in reqs]
+    ctx = binding.Context(0)
+    torch.cuda.synchronize()
+    binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in zip(reqs, outs)])  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, sts, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in zip(reqs, outs)])
+    sec = time.perf_counter() - t0
+    print(json.dumps({"mode": "batched-profile", "requests": len(reqs), "status": st, "seconds": round(sec, 4),
+                      "solves_per_s": round(len(reqs) / sec, 1), "refinement_ms": round(infs[0].phase_ms[4], 2),
+                      "setup_ms_mean": round(float(np.mean([f.phase_ms[0] for f in infs])), 2)}), flush=True)
+    ctx.close()
+
+
 def prony_bench(ctx, args, dev):
     """Complex least squares at the paper's Prony shape (Section 5.2, Appendix B): the first solve of
     Prony's method, m = 5e5, n = 1000, Toeplitz A = (f_{n-1+i-j}), b = (f_{n-1+i}), f_j the sum of
@@ -593,6 +630,9 @@ def main():
     args = parse()
     if args.pass_only:
         return pass_only(args)
+    if args.batched_profile:
+        batched_profile(args)
+        return
     if args.sketch_profile:
         return sketch_profile(args)
     if args.gpus != 1:

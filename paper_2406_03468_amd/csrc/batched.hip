@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <condition_variable>
 #include <mutex>
 #include <thread>
@@ -133,27 +134,35 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
   hipStream_t s = ctx->stream;
   if (infos) memset(infos, 0, sizeof(fs_info) * (size_t)count);
 
-  // ---- work-group slices of the batched pass: proportional to each problem's bytes of A, multiples of 8
+  // ---- work-group slices of the batched passes.  The problems are grouped by pass instantiation (tile
+  // height H, column slots L, load width); each group's passes are one launch, and the groups' launches
+  // follow each other, so each group's grid is sized to fill the GPU (about two work-groups per CU, the
+  // pass holding a CU's registers), shared out in proportion to each problem's m n in multiples of 8
   std::vector<int> idx;  // batched problems
-  double work = 0.0;
   for (int i = 0; i < count; ++i)
-    if (batched[i]) {
-      idx.push_back(i);
-      work += (double)probs[i].m * probs[i].n;
-    }
+    if (batched[i]) idx.push_back(i);
   const int nb = (int)idx.size();
   std::vector<ProbLayout> lay(count);
+  std::vector<PassConfig> pcs(count);
+  std::vector<int> keyv(count, 0);
+  std::map<int, double> group_work;
+  for (int i : idx) {
+    pcs[i] = fs_pass_config(probs[i].m, probs[i].n, ctx->num_cu);
+    const int cpr = 512 / (pcs[i].H / 2);
+    const int L = (probs[i].n + cpr - 1) / cpr;
+    const bool vec = ((probs[i].lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(probs[i].A) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(probs[i].b) & 15) == 0);
+    keyv[i] = (pcs[i].H * 64 + L) * 2 + (vec ? 1 : 0);
+    group_work[keyv[i]] += (double)probs[i].m * probs[i].n;
+  }
   size_t total = 0;
   for (int i : idx) {
-    const PassConfig pc = fs_pass_config(probs[i].m, probs[i].n, ctx->num_cu);
-    const int cpr = 512 / (pc.H / 2);
-    const int L = (probs[i].n + cpr - 1) / cpr;
-    const double share = 4.0 * ctx->num_cu * ((double)probs[i].m * probs[i].n) / std::max(work, 1.0);
-    int G = (int)std::min<double>(pc.G, std::max(8.0, ceil(share / 8.0) * 8.0));
+    const int key = keyv[i];
+    const double share = 2.0 * ctx->num_cu * ((double)probs[i].m * probs[i].n) / std::max(group_work[key], 1.0);
+    int G = (int)std::min<double>(pcs[i].G, std::max(8.0, ceil(share / 8.0) * 8.0));
     G = std::max(8, G / 8 * 8);
-    lay[i] = layout(probs[i].n, G, pc.H, L);
-    lay[i].vec = ((probs[i].lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(probs[i].A) & 15) == 0) &&
-                 ((reinterpret_cast<uintptr_t>(probs[i].b) & 15) == 0);
+    lay[i] = layout(probs[i].n, G, pcs[i].H, (key / 2) % 64);
+    lay[i].vec = (key & 1) != 0;
     total += lay[i].bytes;
   }
   // descriptors: the problems' vectors, three pass work-lists (normal, residual, step heads) and the
