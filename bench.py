@@ -76,7 +76,7 @@ def parse():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false", help="skip the mixed-precision line")
     ap.add_argument("--no-prony", dest="prony", action="store_false", help="skip the complex (Prony) line")
     ap.add_argument("--serve-pool", type=int, default=32, help="distinct problems the requests cycle through")
-    ap.add_argument("--batch-sizes", type=lambda v: [int(t) for t in v.split(",") if t], default=[128, 512],
+    ap.add_argument("--batch-sizes", type=lambda v: [int(t) for t in v.split(",") if t], default=[256, 512],
                     help="batch sizes of the fossils_solve_batched comparison (comma separated; empty: skip)")
     return ap.parse_args()
 
@@ -266,16 +266,22 @@ def serve_bench(ctx, args, dev):
             ts = time.perf_counter()
             worst = 0
             loop_ms = []
+            loop_bytes = 0.0
             for ch in chunks:
                 st_, sts, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in ch], check=False)
                 worst = min(worst, st_)
                 loop_ms.append(infs[0].phase_ms[4])
+                # passes over A in the refinement: two step heads, one per inner iteration, one per KW check
+                loop_bytes += sum((2 + f.iters[0] + f.iters[1] + f.kw_evals) * P.A.shape[0] * P.A.shape[1] * 8
+                                  for (P, _), f in zip(ch, infs))
             rate = nreq / (time.perf_counter() - ts)
+            ref_gbps = loop_bytes / (sum(loop_ms) / 1e3) / 1e9
             rates.append({"batch": bs, "solves_per_s": round(rate, 1), "worst_status": int(worst),
-                          "refinement_ms_mean": round(float(np.mean(loop_ms)), 2)})
+                          "refinement_ms_mean": round(float(np.mean(loop_ms)), 2),
+                          "refinement_GBps": round(ref_gbps, 1)})
             print(f"# FP64 FOSSILS stream, fossils_solve_batched in batches of {bs}: {rate:.1f} solves/s "
-                  f"(refinement {np.mean(loop_ms):.1f} ms per batch), worst status {worst}", file=sys.stderr,
-                  flush=True)
+                  f"(refinement {np.mean(loop_ms):.1f} ms per batch, {ref_gbps:.0f} GB/s of passes over A), "
+                  f"worst status {worst}", file=sys.stderr, flush=True)
         bes_b = []
         if not args.no_check:
             from oracle import backward_error as be
@@ -499,8 +505,11 @@ def batched_profile(args):
     t0 = time.perf_counter()
     st, sts, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in zip(reqs, outs)])
     sec = time.perf_counter() - t0
+    loop_bytes = sum((2 + f.iters[0] + f.iters[1] + f.kw_evals) * P.A.shape[0] * P.A.shape[1] * 8
+                     for P, f in zip(reqs, infs))
     print(json.dumps({"mode": "batched-profile", "requests": len(reqs), "status": st, "seconds": round(sec, 4),
                       "solves_per_s": round(len(reqs) / sec, 1), "refinement_ms": round(infs[0].phase_ms[4], 2),
+                      "refinement_GBps": round(loop_bytes / (infs[0].phase_ms[4] / 1e3) / 1e9, 1),
                       "setup_ms_mean": round(float(np.mean([f.phase_ms[0] for f in infs])), 2)}), flush=True)
     ctx.close()
 
