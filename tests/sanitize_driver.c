@@ -37,6 +37,14 @@ int main(void) {
   EXPECT(fossils_solve_complex(NULL, 10, 2, dummy, 10, dummy, dummy, NULL, NULL) == FS_ERR_INVALID_ARG);
   EXPECT(fossils_solve_multi(NULL, 10, 2, dummy, 10, 3, dummy, 10, dummy, 2, NULL, NULL) < 0);
   EXPECT(fossils_solve_mixed(NULL, 10, 2, dummy, 10, NULL, 0, dummy, dummy, NULL, NULL) < 0);
+  EXPECT(fossils_solve_noalloc(NULL, 10, 2, dummy, 10, dummy, dummy, NULL, NULL) == FS_ERR_INVALID_ARG);
+  {
+    fs_problem pr = {10, 2, dummy, 10, dummy, dummy};
+    fs_status sts[1] = {FS_OK};
+    EXPECT(fossils_solve_batched(NULL, 1, &pr, NULL, NULL, sts) == FS_ERR_INVALID_ARG);
+    EXPECT(fossils_solve_batched(NULL, 0, &pr, NULL, NULL, sts) == FS_ERR_INVALID_ARG);
+    EXPECT(fossils_solve_batched(NULL, 1, NULL, NULL, NULL, sts) == FS_ERR_INVALID_ARG);
+  }
   EXPECT(fs_context_destroy(NULL) == FS_ERR_INVALID_ARG);
   EXPECT(fs_context_create(0, NULL, NULL) == FS_ERR_INVALID_ARG);
   EXPECT(sketch_create(NULL, 10, 5, 2, 1, NULL) == FS_ERR_INVALID_ARG);

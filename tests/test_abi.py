@@ -69,6 +69,20 @@ def test_validation_before_device_work(clib):
     assert clib.fs_options_default(5, 2, None) == binding.FS_ERR_INVALID_ARG
     assert clib.sketch_create(None, 10, 5, 2, 1, None) == binding.FS_ERR_INVALID_ARG
     assert clib.fs_sketch_qr(None, 10, 2, None, 10) == binding.FS_ERR_INVALID_ARG
+    # the batched and no-allocation entry points validate before any device work
+    probs = (binding.FsProblem * 1)()
+    sts = (ctypes.c_int32 * 1)()
+    assert clib.fossils_solve_batched(None, 1, probs, None, None, sts) == binding.FS_ERR_INVALID_ARG
+    assert clib.fossils_solve_batched(None, 0, probs, None, None, sts) == binding.FS_ERR_INVALID_ARG
+    assert clib.fossils_solve_noalloc(None, 10, 2, None, 10, None, None, None, None) == binding.FS_ERR_INVALID_ARG
+
+
+def test_problem_struct_layout():
+    """fs_problem's ctypes layout matches the header's C layout (offsets of every field)."""
+    from paper_2406_03468_amd import binding
+    offs = {name: getattr(binding.FsProblem, name).offset for name, _ in binding.FsProblem._fields_}
+    assert offs == {"m": 0, "n": 8, "A": 16, "lda": 24, "b": 32, "x": 40}
+    assert ctypes.sizeof(binding.FsProblem) == 48
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -152,3 +152,46 @@ def test_batched_large_uneven(ctx):
         ss, si, xs = _solo(ctx, A, b, P.A.shape[1])
         print("checking", shapes[i], flush=True)
         _check_pair(P, host(x), xs, infos[i], si, sts[i], ss, ("large", i, shapes[i]), qr=hh.qr_lstsq_lapack)
+
+
+def test_batched_edge_cases(ctx):
+    """Per-problem failures stay per problem (NaN input -> FS_ERR_NONFINITE, overflowing column norms ->
+    FS_ERR_TOO_LARGE, their x untouched) while the rest of the batch is solved; a square problem, a
+    one-column problem with fewer rows than a pass tile, the same problem twice (the two x agree), and a
+    batch of one problem."""
+    import torch
+    from paper_2406_03468_amd import binding
+    sq = make_problem(40, 40, 1e3, 0.0, seed=81)
+    one = make_problem(20, 1, 1.0, 1e-2, seed=82)
+    dup = make_problem(7001, 33, 1e8, 1e-4, seed=83)
+    bad = make_problem(3000, 20, 1e3, 1e-3, seed=84)
+    A_nan = bad.A.copy()
+    A_nan[17, 3] = np.nan
+    A_big = bad.A.copy()
+    A_big[:, 4] *= 1e160
+    entries = [(dev_colmajor(sq.A), dev_vec(sq.b)), (dev_colmajor(one.A), dev_vec(one.b)),
+               (dev_colmajor(dup.A), dev_vec(dup.b)), None, (dev_colmajor(A_nan), dev_vec(bad.b)),
+               (dev_colmajor(A_big), dev_vec(bad.b))]
+    entries[3] = entries[2]
+    xs = [torch.full((A.shape[1],), np.nan, dtype=torch.float64, device="cuda") for A, _ in entries]
+    torch.cuda.synchronize()
+    print("batched edge cases", flush=True)
+    s, sts, infos = binding.fossils_solve_batched(ctx, [(A, b, x) for (A, b), x in zip(entries, xs)], check=False)
+    assert sts[4] == binding.FS_ERR_NONFINITE and sts[5] == binding.FS_ERR_TOO_LARGE, sts
+    assert s == binding.FS_ERR_NONFINITE, s  # the first error among the problems
+    assert np.all(np.isnan(host(xs[4]))) and np.all(np.isnan(host(xs[5])))
+    for i, P in ((0, sq), (1, one), (2, dup), (3, dup)):
+        ss, si, x_s = _solo(ctx, entries[i][0], entries[i][1], P.A.shape[1])
+        assert sts[i] == ss, (i, sts, ss)
+        xb = host(xs[i])
+        assert np.all(np.isfinite(xb)), i
+        assert be.relative_backward_error(P.A, P.b, xb, P.sigma, P.V) <= 1e-14, i
+        ref = max(np.linalg.norm(hh.qr_lstsq(P.A, P.b) - P.x_true) / np.linalg.norm(P.x_true), P.kappa * U)
+        assert np.linalg.norm(xb - x_s) / np.linalg.norm(P.x_true) <= 10 * ref, (i, ref)
+    ref_dup = max(np.linalg.norm(hh.qr_lstsq(dup.A, dup.b) - dup.x_true) / np.linalg.norm(dup.x_true), dup.kappa * U)
+    assert np.linalg.norm(host(xs[2]) - host(xs[3])) / np.linalg.norm(dup.x_true) <= 10 * ref_dup
+    # a batch of one
+    x1 = torch.full((33,), np.nan, dtype=torch.float64, device="cuda")
+    s1, sts1, inf1 = binding.fossils_solve_batched(ctx, [(entries[2][0], entries[2][1], x1)])
+    assert s1 == sts1[0] == sts[2] and inf1[0].iters[0] > 0
+    assert np.linalg.norm(host(x1) - host(xs[2])) / np.linalg.norm(dup.x_true) <= 10 * ref_dup
