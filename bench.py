@@ -69,7 +69,7 @@ def parse():
                          "a counter profiler; prints one JSON line")
     ap.add_argument("--batched-profile", action="store_true",
                     help="profiling mode: one fossils_solve_batched call on 256 FP64 requests of the serving "
-                         "stream (after a warm-up call); prints one JSON line")
+                         "stream, FOSSILS and SPIR alternating (after a warm-up call); prints one JSON line")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--slot-sweep", type=lambda v: [int(t) for t in v.split(",") if t], default=[1, 2, 4, 8, 16],
                     help="slot counts of the saturated-throughput sweep (comma separated; empty: skip)")
@@ -238,55 +238,62 @@ def serve_bench(ctx, args, dev):
             sv.close()
         slot_sweep.append({"slots": ns, "solves_per_s": round(rate, 1)})
         print(f"# serving slot sweep: {ns} slots {rate:.1f} solves/s", file=sys.stderr, flush=True)
-    # FOSSILS in FP64 only (the form of the batched entry point) on the first 512 requests of the same
-    # stream: the server (all submitted at once), then fossils_solve_batched on consecutive chunks
+    # The first 512 requests of the same stream in FP64 (FOSSILS and SPIR alternating, as in the stream):
+    # the server (all submitted at once), then fossils_solve_batched on consecutive chunks (each request
+    # with its own method)
     batched = None
     if args.batch_sizes:
         nreq = min(R, 512)
-        fp = [(P, x) for (P, _, _), x in zip(reqs[:nreq], outs[:nreq])]
+        fp = [(P, meth, x) for (P, meth, _), x in zip(reqs[:nreq], outs[:nreq])]
         sv = binding.Server(ctx, hbm_budget=32 << 30, max_slots=args.serve_slots)
         try:
-            wt = [binding.batched_submit(sv, P.A, P.b, x) for P, x in fp[: 2 * args.serve_slots]]
+            wt = [binding.batched_submit(sv, P.A, P.b, x, method=meth) for P, meth, x in fp[: 2 * args.serve_slots]]
             for t in wt:
                 binding.fs_server_wait(sv, t)
             ts = time.perf_counter()
-            tks = [binding.batched_submit(sv, P.A, P.b, x) for P, x in fp]
+            tks = [binding.batched_submit(sv, P.A, P.b, x, method=meth) for P, meth, x in fp]
             for t in tks:
                 binding.fs_server_wait(sv, t)
             srv_rate = nreq / (time.perf_counter() - ts)
         finally:
             sv.close()
-        print(f"# FP64 FOSSILS stream, server {args.serve_slots} slots: {srv_rate:.1f} solves/s", file=sys.stderr,
-              flush=True)
+        print(f"# FP64 stream (FOSSILS / SPIR), server {args.serve_slots} slots: {srv_rate:.1f} solves/s",
+              file=sys.stderr, flush=True)
+
+        def run_chunk(ch):
+            """One chunk as one batched call (each request's method); returns (status, refinement ms, bytes)."""
+            st_, _, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x, meth) for P, meth, x in ch],
+                                                         check=False)
+            # passes over A in the refinement: two step heads, one per inner iteration, one per KW check
+            nbytes = sum((2 + f.iters[0] + f.iters[1] + f.kw_evals) * P.A.shape[0] * P.A.shape[1] * 8
+                         for (P, _, _), f in zip(ch, infs))
+            return st_, infs[0].phase_ms[4], nbytes
+
         rates = []
         for bs in args.batch_sizes:
             chunks = [fp[i:i + bs] for i in range(0, nreq, bs)]
-            binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in chunks[0]])  # warm-up
+            run_chunk(chunks[0])  # warm-up
             torch.cuda.synchronize()
             ts = time.perf_counter()
-            worst = 0
-            loop_ms = []
-            loop_bytes = 0.0
+            worst, loop_ms, loop_bytes = 0, [], 0.0
             for ch in chunks:
-                st_, sts, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in ch], check=False)
-                worst = min(worst, st_)
-                loop_ms.append(infs[0].phase_ms[4])
-                # passes over A in the refinement: two step heads, one per inner iteration, one per KW check
-                loop_bytes += sum((2 + f.iters[0] + f.iters[1] + f.kw_evals) * P.A.shape[0] * P.A.shape[1] * 8
-                                  for (P, _), f in zip(ch, infs))
+                w_, ms_, b_ = run_chunk(ch)
+                worst = min(worst, w_)
+                loop_ms.append(ms_)
+                loop_bytes += b_
             rate = nreq / (time.perf_counter() - ts)
             ref_gbps = loop_bytes / (sum(loop_ms) / 1e3) / 1e9
             rates.append({"batch": bs, "solves_per_s": round(rate, 1), "worst_status": int(worst),
                           "refinement_ms_mean": round(float(np.mean(loop_ms)), 2),
                           "refinement_GBps": round(ref_gbps, 1)})
-            print(f"# FP64 FOSSILS stream, fossils_solve_batched in batches of {bs}: {rate:.1f} solves/s "
-                  f"(refinement {np.mean(loop_ms):.1f} ms per batch, {ref_gbps:.0f} GB/s of passes over A), "
-                  f"worst status {worst}", file=sys.stderr, flush=True)
+            print(f"# FP64 stream, batched calls on chunks of {bs}: {rate:.1f} solves/s (refinement "
+                  f"{np.mean(loop_ms):.1f} ms per chunk, {ref_gbps:.0f} GB/s of passes over A), worst status {worst}",
+                  file=sys.stderr, flush=True)
         bes_b = []
         if not args.no_check:
             from oracle import backward_error as be
             for i in (0, nreq - 1):
-                P, x = fp[i]
+                P, _, x = fp[i]
                 A_h, b_h, x_h = P.A.cpu().numpy(), P.b.cpu().numpy(), x.cpu().numpy()
                 fro = np.sqrt(np.sum(A_h * A_h))
                 bes_b.append(float(be.kw_known_svd(A_h, b_h, x_h, P.sigma, P.V, fro / np.linalg.norm(b_h)) / fro))
@@ -340,13 +347,13 @@ def serve_bench(ctx, args, dev):
               f"BE sample {bes_s}", file=sys.stderr, flush=True)
         batched = {"requests": nreq, "server_solves_per_s": round(srv_rate, 1), "server_slots": args.serve_slots,
                    "batched": rates, "be_sample": bes_b,
-                   "workload": "the serving stream's first requests, every one FOSSILS in FP64",
+                   "workload": "the serving stream's first requests in FP64 (FOSSILS and SPIR alternating)",
                    "small_stream": {"requests": nsm, "server_solves_per_s": round(small_srv, 1),
                                     "batched": small_rates, "be_sample": bes_s,
                                     "workload": "m~U[2e3,2e4], n~U[10,100], m>=20n, kappa=10^U[2,12], "
                                                 "||r|| log-U[1e-12,1], FOSSILS FP64, 64 distinct problems"}}
     return {"requests": R, "slots": args.serve_slots, "plain_solves_per_s": round(plain_thr, 1),
-            "fp64_fossils_batched": batched,
+            "fp64_batched": batched,
             "plain_requests": nplain, "plain_errors": plain_bad, "plain_be_sample": plain_be,
             "served_over_plain": round(thr / plain_thr, 3), "slot_sweep": slot_sweep, "pool": len(pool), "saturated_solves_per_s": round(thr, 1),
             "saturated_GBps_of_A": round(gbytes / sat_s, 1), "mean_service_ms": round(service_ms, 2),
@@ -478,9 +485,9 @@ def sketch_profile(args):
 
 
 def batched_profile(args):
-    """Profiling workload of fossils_solve_batched: 256 FP64 FOSSILS requests cycling through the 32-problem
-    pool of the serving stream (C5 shapes, the serving line's seeds), solved by one batched call after a
-    warm-up call on the same requests; prints one JSON line."""
+    """Profiling workload of fossils_solve_batched: 256 FP64 requests (FOSSILS and SPIR alternating) cycling
+    through the 32-problem pool of the serving stream (C5 shapes, the serving line's seeds), solved by one
+    batched call after a warm-up call on the same requests; prints one JSON line."""
     import numpy as np
     import torch
 
@@ -498,12 +505,13 @@ def batched_profile(args):
         pool.append(make_problem_torch(m, n, 10.0 ** rng.uniform(2, 12), 10.0 ** rng.uniform(-12, 0), seed=1000 + i))
     reqs = [pool[i % len(pool)] for i in range(256)]
     outs = [torch.zeros(P.A.shape[1], dtype=torch.float64, device="cuda") for P in reqs]
+    batch = [(P.A, P.b, x, ("fossils", "spir")[i % 2]) for i, (P, x) in enumerate(zip(reqs, outs))]
     ctx = binding.Context(0)
     torch.cuda.synchronize()
-    binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in zip(reqs, outs)])  # warm-up
+    binding.fossils_solve_batched(ctx, batch)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st, sts, infs = binding.fossils_solve_batched(ctx, [(P.A, P.b, x) for P, x in zip(reqs, outs)])
+    st, sts, infs = binding.fossils_solve_batched(ctx, batch)
     sec = time.perf_counter() - t0
     loop_bytes = sum((2 + f.iters[0] + f.iters[1] + f.kw_evals) * P.A.shape[0] * P.A.shape[1] * 8
                      for P, f in zip(reqs, infs))

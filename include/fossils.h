@@ -190,7 +190,8 @@ fs_status fossils_solve_multi(fs_context ctx, int64_t m, int32_t n, const double
                               const double* B, int64_t ldb, double* X, int64_t ldx, const fs_options* opts,
                               fs_info* info);
 
-/* One problem of a batch: A (m x n, lda >= m), b (m) and x (n, output), device arrays. */
+/* One problem of a batch: A (m x n, lda >= m), b (m) and x (n, output), device arrays; method: the inner
+ * solver, FS_METHOD_FOSSILS (0: heavy ball, Algorithm 4) or FS_METHOD_SPIR (1: CG, Algorithm 3). */
 typedef struct fs_problem {
   int64_t m;
   int32_t n;
@@ -198,11 +199,13 @@ typedef struct fs_problem {
   int64_t lda;
   const double* b;
   double* x;
+  int32_t method;
 } fs_problem;
 
-/* FOSSILS (Algorithm 4, P = V Sigma^{-1}) for count (1..65535) independent problems of any shapes,
- * each with the result fossils_solve gives it in the serial order (opts->overlap_svd = 0), up to the
- * order of floating-point sums: the same iterations, stopping rules and d = 12 n.  opts, if not NULL,
+/* FOSSILS (Algorithm 4, P = V Sigma^{-1}) or SPIR (Algorithm 3 with the same preconditioner), as each
+ * problem's method says, for count (1..65535) independent problems of any shapes, each with the result
+ * fossils_solve (spir_solve) gives it in the serial order (opts->overlap_svd = 0), up to the order of
+ * floating-point sums: the same iterations, stopping rules and d = 12 n.  opts, if not NULL,
  * applies to every problem except d, which is 12 n_i for each (zeta <= d), and the form: FP64,
  * sketch-and-solve start, adaptive steps.  The sketch, QR, SVD and x_0 of the problems run in problem
  * order on up to eight internal streams of the context (their grid-synchronizing kernels reserve
@@ -212,8 +215,9 @@ typedef struct fs_problem {
  * launch for the whole wave (the passes over A as one grid whose work-groups are shared out among the
  * problems in proportion to their m n), and a problem that has met its stopping rule skips the rest.
  * Problems with n > 1024 (or 16 lda (512 / H) >= 2^32 bytes, H the pass tile height), a numerically
- * rank-deficient sketch, or b = 0, are solved by fossils_solve after the batch, with the caller's
- * options (overlap_svd as given, default on).
+ * rank-deficient sketch, or b = 0, are solved by fossils_solve (spir_solve) after the batch, with the
+ * caller's options (overlap_svd as given, default on).  A method other than FOSSILS or SPIR gives that
+ * problem FS_ERR_UNSUPPORTED.
  * statuses[i] receives problem i's status; infos (if not NULL) count records, where phase_ms[0] is
  * that problem's setup time on its stream and phase_ms[4] its wave's refinement time (other phases
  * 0).  Inputs must be complete on the context's stream (the call waits for it); on return every x is

@@ -70,7 +70,8 @@ class FsInfo(ctypes.Structure):
 
 
 class FsProblem(ctypes.Structure):
-    _fields_ = [("m", c_int64), ("n", c_int32), ("A", c_vp), ("lda", c_int64), ("b", c_vp), ("x", c_vp)]
+    _fields_ = [("m", c_int64), ("n", c_int32), ("A", c_vp), ("lda", c_int64), ("b", c_vp), ("x", c_vp),
+                ("method", c_int32)]
 
 
 class FsRequest(ctypes.Structure):
@@ -322,16 +323,22 @@ def fossils_solve_multi(ctx: Context, A, B, X, opts: Optional[FsOptions] = None)
     return s, list(infos)
 
 
-def fossils_solve_batched(ctx: Context, problems, opts: Optional[FsOptions] = None, check: bool = True):
-    """problems: a list of (A, b, x) device tensors (A column-major (m_i, n_i), b (m_i,), x (n_i,) output).
+def fossils_solve_batched(ctx: Context, problems, opts: Optional[FsOptions] = None, check: bool = True,
+                          method="fossils"):
+    """problems: a list of (A, b, x) or (A, b, x, method) device tensors (A column-major (m_i, n_i), b (m_i,),
+    x (n_i,) output); method "fossils" / "spir" (or an FS_METHOD_* value) for the problems that give none.
     Returns (status, [status_i], [FsInfo_i]); with check, an error status raises FossilsError."""
     k = len(problems)
     arr = (FsProblem * k)()
-    for i, (A, b, x) in enumerate(problems):
+    codes = {"fossils": FS_METHOD_FOSSILS, "spir": FS_METHOD_SPIR}
+    for i, pr in enumerate(problems):
+        A, b, x = pr[:3]
+        meth = pr[3] if len(pr) > 3 else method
         m, n = A.shape
         if b.shape[0] != m or x.shape[0] != n:
             raise ValueError("shape mismatch in problem %d" % i)
-        arr[i] = FsProblem(int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(x)))
+        arr[i] = FsProblem(int(m), int(n), c_vp(_ptr(A)), int(_colmajor(A)), c_vp(_ptr(b)), c_vp(_ptr(x)),
+                           int(codes.get(meth, meth)))
     infos = (FsInfo * k)()
     sts = (c_int32 * k)()
     s = load().fossils_solve_batched(ctx.h, int(k), arr, ctypes.byref(opts) if opts is not None else None, infos,

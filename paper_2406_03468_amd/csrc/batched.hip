@@ -1,5 +1,5 @@
-// fossils_solve_batched: FOSSILS (Algorithm 4, P = V Sigma^{-1}) for many independent problems of uneven
-// m and n in one call.
+// fossils_solve_batched: FOSSILS (Algorithm 4, P = V Sigma^{-1}) or SPIR (Algorithm 3 with the same
+// preconditioner), each problem's choice, for many independent problems of uneven m and n in one call.
 //
 //   setup      each problem's sketch, QR of the sketch, SVD of R, sketch-and-solve start x_0 and column
 //              scaling, in problem order on kSetupSlots helper contexts (own stream and scratch each, host
@@ -9,7 +9,7 @@
 //   refinement the two refinement steps of a wave of set-up problems in lockstep on the caller's stream,
 //              beside the setup of the next waves: each phase of an inner iteration is one launch for the
 //              whole wave -- the passes over A as one work-list of (problem, row tiles) per tile
-//              configuration, the products with V Sigma^{-1} and the heavy-ball and KW steps with one
+//              configuration, the products with V Sigma^{-1} and the heavy-ball / CG and KW steps with one
 //              work-group (or a slice of the grid) per problem.  A problem whose rule has stopped it skips
 //              the kernels of the following iterations (its stop flag), and the host polls all flags once
 //              per kw_every iterations.
@@ -105,6 +105,10 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
     const fs_problem& P = probs[i];
     statuses[i] = fs_validate_problem(P.m, P.n, P.A, P.lda, P.b, P.x);
     if (statuses[i] != FS_OK) continue;
+    if (P.method != FS_METHOD_FOSSILS && P.method != FS_METHOD_SPIR) {
+      statuses[i] = FS_ERR_UNSUPPORTED;
+      continue;
+    }
     fs_options o;
     statuses[i] = fs_options_default(P.m, P.n, &o);
     if (statuses[i] != FS_OK) continue;
@@ -361,6 +365,9 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
       b.gpart = ptr(i, lay[i].off_gpart);
       b.x_out = probs[i].x;
       b.st = state_of(i);
+      b.spir = probs[i].method == FS_METHOD_SPIR ? 1 : 0;
+      b.res = vec + 11 * n;
+      b.p = vec + 4 * n;  // (SPIR has no dy_old)
       if (std::find(keys.begin(), keys.end(), key_of(i)) == keys.end()) keys.push_back(key_of(i));
     }
     // pass work-lists: per (H, L, vec) group, the normal pass (v = D^{-1} A^T A zs), the residual pass
@@ -435,10 +442,10 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
       bool all_stopped = false;
       const int cap = o0.max_inner;
       for (int j = 0; j < cap && !all_stopped; ++j) {
-        FS_K(fs_b_gemv_P(dbv, na, max_n, 0, s));    // zs = D^{-1} V Sigma^{-1} dy
+        FS_K(fs_b_gemv_P(dbv, na, max_n, 0, s));    // zs = D^{-1} V Sigma^{-1} dy (SPIR: p)
         FS_TRY(passes(dln, false));                // v = D^{-1} A^T A zs
         FS_K(fs_b_gemv_PT(dbv, na, max_n, 1, s));   // u = Sigma^{-1} V^T v
-        FS_K(fs_b_vec(dbv, na, BatchOp::POLYAK, step == 0 ? 1 : 0, 0, 0, s));
+        FS_K(fs_b_vec(dbv, na, BatchOp::UPDATE, step == 0 ? 1 : 0, 0, 0, s));  // heavy ball or CG
         if (step == 1 && j % o0.kw_every == 0) {  // sketched KW at x_hat = x + P dy (second-step rule)
           FS_K(fs_b_gemv_P(dbv, na, max_n, 1, s));
           FS_K(fs_b_vec(dbv, na, BatchOp::XH_NORM, 0, 0, 0, s));
@@ -518,7 +525,8 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
     fs_options o = opt[i];
     o.overlap_svd = opts_in ? opts_in->overlap_svd : 1;
     fs_info f{};
-    statuses[i] = fossils_solve(ctx, P.m, P.n, P.A, P.lda, P.b, P.x, &o, &f);
+    statuses[i] = (P.method == FS_METHOD_SPIR ? spir_solve : fossils_solve)(ctx, P.m, P.n, P.A, P.lda, P.b, P.x, &o,
+                                                                           &f);
     if (infos) infos[i] = f;
   }
   fs_status result = FS_OK;

@@ -16,7 +16,8 @@ constexpr int GEMV_CS = 64;  // columns per slice of the V products
 __device__ __forceinline__ double bbsum(double v, double* sh) { return block_sum<BNT>(v, sh); }
 __device__ __forceinline__ bool b_stopped(const BatchVec& p) { return p.st->stop != 0; }
 
-// P y partial sums: part[slice][i] = sum_{j in slice} V[i, j] y[j] / sigma[j], y = dy
+// P y partial sums: part[slice][i] = sum_{j in slice} V[i, j] y[j] / sigma[j], y = dy (or p for SPIR in
+// the iteration's product, stop_aware = 2); stop_aware 0: the final update, run for every problem
 __global__ __launch_bounds__(256) void k_b_gemv_v_part(const BatchVec* __restrict__ list, int stop_aware) {
   const BatchVec& p = list[blockIdx.z];
   if (stop_aware && b_stopped(p)) return;
@@ -24,8 +25,9 @@ __global__ __launch_bounds__(256) void k_b_gemv_v_part(const BatchVec* __restric
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int j0 = blockIdx.y * GEMV_CS, j1 = min(n, j0 + GEMV_CS);
   if (i >= n || j0 >= n) return;
+  const double* y = (stop_aware == 2 && p.spir) ? p.p : p.dy;  // the direction of the iteration (mode 0)
   double s = 0.0;
-  for (int j = j0; j < j1; ++j) s = fma(p.V[(int64_t)j * n + i], p.dy[j] / p.sigma[j], s);
+  for (int j = j0; j < j1; ++j) s = fma(p.V[(int64_t)j * n + i], y[j] / p.sigma[j], s);
   p.gpart[(int64_t)blockIdx.y * n + i] = s;
 }
 
@@ -88,15 +90,21 @@ __global__ __launch_bounds__(BNT) void k_b_first_threshold(const BatchVec* __res
   }
 }
 
-// start of a step: dy = dy_old = c, as k_step_init (FOSSILS)
+// start of a step, as k_step_init: FOSSILS dy = dy_old = c; SPIR res = p = c, dy = 0
 __global__ __launch_bounds__(BNT) void k_b_step_init(const BatchVec* __restrict__ list) {
   const BatchVec& p = list[blockIdx.x];
   __shared__ double sh[BNT / 64];
   double s = 0.0;
   for (int i = threadIdx.x; i < p.n; i += BNT) {
     const double v = p.c[i];
-    p.dy[i] = v;
-    p.dy_old[i] = v;
+    if (p.spir) {
+      p.res[i] = v;
+      p.p[i] = v;
+      p.dy[i] = 0.0;
+    } else {
+      p.dy[i] = v;
+      p.dy_old[i] = v;
+    }
     s = fma(v, v, s);
   }
   s = bbsum(s, sh);
@@ -111,11 +119,8 @@ __global__ __launch_bounds__(BNT) void k_b_step_init(const BatchVec* __restrict_
 }
 
 // the heavy-ball update with the first-step rule, as k_polyak
-__global__ __launch_bounds__(BNT) void k_b_polyak(const BatchVec* __restrict__ list, int first_step) {
-  const BatchVec& p = list[blockIdx.x];
+__device__ __forceinline__ void polyak_one(const BatchVec& p, int first_step, double* sh) {
   DevState* st = p.st;
-  if (st->stop) return;
-  __shared__ double sh[BNT / 64];
   const double al = st->alpha, be = st->beta;
   double s = 0.0;
   for (int i = threadIdx.x; i < p.n; i += BNT) {
@@ -135,6 +140,56 @@ __global__ __launch_bounds__(BNT) void k_b_polyak(const BatchVec* __restrict__ l
     }
     if (st->iters >= st->max_inner) st->stop = 1;
   }
+}
+
+// CG on the preconditioned normal equations (SPIR), as k_cg: q = u = P^T A_s^T A_s P p given;
+// a = rho / p^T q; Delta = a p; dy += Delta; res -= a q; p = res + (rho' / rho) p; the first-step rule
+__device__ __forceinline__ void cg_one(const BatchVec& b, int first_step, double* sh) {
+  DevState* st = b.st;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < b.n; i += BNT) s = fma(b.p[i], b.u[i], s);
+  const double pq = bbsum(s, sh);
+  const double rho = st->rho_cg;
+  if (!(pq > 0.0) || rho == 0.0) {
+    if (threadIdx.x == 0) {
+      st->stop = 1;
+      if (rho == 0.0) st->converged = 1;
+    }
+    return;
+  }
+  const double a = rho / pq;
+  double s2 = 0.0, sd = 0.0;
+  for (int i = threadIdx.x; i < b.n; i += BNT) {
+    const double D = a * b.p[i];
+    b.dy[i] += D;
+    const double r = b.res[i] - a * b.u[i];
+    b.res[i] = r;
+    s2 = fma(r, r, s2);
+    sd = fma(D, D, sd);
+  }
+  const double rho2 = bbsum(s2, sh);
+  const double dn2 = bbsum(sd, sh);
+  const double bet = rho2 / rho;
+  for (int i = threadIdx.x; i < b.n; i += BNT) b.p[i] = b.res[i] + bet * b.p[i];
+  if (threadIdx.x == 0) {
+    st->rho_cg = rho2;
+    st->dnorm2 = dn2;
+    st->iters += 1;
+    if (first_step && sqrt(dn2) <= st->thr_first) {
+      st->stop = 1;
+      st->converged = 1;
+    }
+    if (st->iters >= st->max_inner) st->stop = 1;
+  }
+}
+
+// one inner-iteration update per problem: heavy ball (FOSSILS) or CG (SPIR), uniform per work-group
+__global__ __launch_bounds__(BNT) void k_b_update(const BatchVec* __restrict__ list, int first_step) {
+  const BatchVec& p = list[blockIdx.x];
+  if (p.st->stop) return;
+  __shared__ double sh[BNT / 64];
+  if (p.spir) cg_one(p, first_step, sh);
+  else polyak_one(p, first_step, sh);
 }
 
 // ||x_hat||^2 (KW check)
@@ -234,7 +289,7 @@ hipError_t fs_b_gather(const BatchVec* list, int count, DevState* out, hipStream
 hipError_t fs_b_gemv_P(const BatchVec* list, int count, int max_n, int mode, hipStream_t s) {
   const int ns = (max_n + GEMV_CS - 1) / GEMV_CS;
   hipLaunchKernelGGL(k_b_gemv_v_part, dim3((unsigned)((max_n + 255) / 256), (unsigned)ns, (unsigned)count), dim3(256),
-                     0, s, list, mode != 2 ? 1 : 0);
+                     0, s, list, mode == 0 ? 2 : (mode == 1 ? 1 : 0));
   hipLaunchKernelGGL(k_b_sum_slices, dim3((unsigned)((max_n + 255) / 256), (unsigned)count), dim3(256), 0, s, list,
                      mode);
   return hipGetLastError();
@@ -251,7 +306,7 @@ hipError_t fs_b_vec(const BatchVec* list, int count, BatchOp op, int arg, double
     case BatchOp::SCALE: hipLaunchKernelGGL(k_b_scale, g, b, 0, s, list, arg); break;
     case BatchOp::FIRST_THRESHOLD: hipLaunchKernelGGL(k_b_first_threshold, g, b, 0, s, list, gamma, rho); break;
     case BatchOp::STEP_INIT: hipLaunchKernelGGL(k_b_step_init, g, b, 0, s, list); break;
-    case BatchOp::POLYAK: hipLaunchKernelGGL(k_b_polyak, g, b, 0, s, list, arg); break;
+    case BatchOp::UPDATE: hipLaunchKernelGGL(k_b_update, g, b, 0, s, list, arg); break;
     case BatchOp::XH_NORM: hipLaunchKernelGGL(k_b_xh_norm, g, b, 0, s, list); break;
     case BatchOp::KW: hipLaunchKernelGGL(k_b_kw, g, b, 0, s, list); break;
     case BatchOp::FINAL: hipLaunchKernelGGL(k_b_final, g, b, 0, s, list); break;

@@ -142,14 +142,18 @@ struct BatchVec {
   double* gpart;  // ceil(n / 64) x n
   double* x_out;  // the caller's x
   DevState* st;
+  int spir;           // CG inner solver (SPIR) instead of heavy ball
+  double *res, *p;    // CG residual and direction (SPIR)
 };
-enum class BatchOp { SCALE, FIRST_THRESHOLD, STEP_INIT, POLYAK, XH_NORM, KW, FINAL };
-// P dy for every problem (mode 0: zs = D^{-1} P dy; 1: xh = x + P dy; 2: x = x + P dy) and P^T
+enum class BatchOp { SCALE, FIRST_THRESHOLD, STEP_INIT, UPDATE, XH_NORM, KW, FINAL };
+// P y for every problem (mode 0: zs = D^{-1} P y with y = dy, or the CG direction p for SPIR; 1: xh =
+// x + P dy; 2: x = x + P dy) and P^T
 // (mode 0: c = P^T g; 1: u = P^T v; 2: w = V^T g), P = V Sigma^{-1}; max_n: the largest n.
 hipError_t fs_b_gemv_P(const BatchVec* list, int count, int max_n, int mode, hipStream_t s);
 hipError_t fs_b_gemv_PT(const BatchVec* list, int count, int max_n, int mode, hipStream_t s);
 // One-work-group-per-problem steps: SCALE (arg 0: zs = D^{-1} x, 1: zs = D^{-1} xh), FIRST_THRESHOLD
-// (gamma, rho), STEP_INIT, POLYAK (arg: first step), XH_NORM, KW, FINAL (x_out = D^{-1} x).
+// (gamma, rho), STEP_INIT, UPDATE (heavy ball or CG by each problem's method; arg: first step), XH_NORM, KW,
+// FINAL (x_out = D^{-1} x).
 hipError_t fs_b_vec(const BatchVec* list, int count, BatchOp op, int arg, double gamma, double rho, hipStream_t s);
 // Everything the host reads back after one problem's setup, gathered on the device for one copy.
 struct BatchReport {

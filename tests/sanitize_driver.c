@@ -39,7 +39,7 @@ int main(void) {
   EXPECT(fossils_solve_mixed(NULL, 10, 2, dummy, 10, NULL, 0, dummy, dummy, NULL, NULL) < 0);
   EXPECT(fossils_solve_noalloc(NULL, 10, 2, dummy, 10, dummy, dummy, NULL, NULL) == FS_ERR_INVALID_ARG);
   {
-    fs_problem pr = {10, 2, dummy, 10, dummy, dummy};
+    fs_problem pr = {10, 2, dummy, 10, dummy, dummy, FS_METHOD_FOSSILS};
     fs_status sts[1] = {FS_OK};
     EXPECT(fossils_solve_batched(NULL, 1, &pr, NULL, NULL, sts) == FS_ERR_INVALID_ARG);
     EXPECT(fossils_solve_batched(NULL, 0, &pr, NULL, NULL, sts) == FS_ERR_INVALID_ARG);

@@ -81,8 +81,8 @@ def test_problem_struct_layout():
     """fs_problem's ctypes layout matches the header's C layout (offsets of every field)."""
     from paper_2406_03468_amd import binding
     offs = {name: getattr(binding.FsProblem, name).offset for name, _ in binding.FsProblem._fields_}
-    assert offs == {"m": 0, "n": 8, "A": 16, "lda": 24, "b": 32, "x": 40}
-    assert ctypes.sizeof(binding.FsProblem) == 48
+    assert offs == {"m": 0, "n": 8, "A": 16, "lda": 24, "b": 32, "x": 40, "method": 48}
+    assert ctypes.sizeof(binding.FsProblem) == 56
 
 
 def test_missing_library_fails_loudly(tmp_path):

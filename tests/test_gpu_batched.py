@@ -37,13 +37,13 @@ def _mix(seed, count, nmax=300, mmax=40000):
     return out
 
 
-def _solo(ctx, A, b, n, overlap=0):
+def _solo(ctx, A, b, n, overlap=0, method="fossils"):
     import torch
     from paper_2406_03468_amd import binding
     o = binding.fs_options_default(A.shape[0], n)
     o.overlap_svd = overlap
     x = torch.zeros(n, dtype=torch.float64, device="cuda")
-    st, info = binding.fossils_solve(ctx, A, b, x, o)
+    st, info = (binding.spir_solve if method == "spir" else binding.fossils_solve)(ctx, A, b, x, o)
     return st, info, host(x)
 
 
@@ -74,19 +74,21 @@ def _check_pair(P, x_b, x_s, ib, is_, sb, ss, tag, same_order=True, qr=hh.qr_lst
         P.kappa >= 1e11, (tag, ib.flags, is_.flags)
 
 
-@pytest.mark.parametrize("seed,count", [(1, 6), (2, 24)])
-def test_batched_matches_solo(ctx, seed, count):
+@pytest.mark.parametrize("seed,count,method", [(1, 6, "fossils"), (2, 24, "alternate"), (3, 16, "spir")])
+def test_batched_matches_solo(ctx, seed, count, method):
+    """FOSSILS, SPIR, or the two alternating inside one batch."""
     import torch
     from paper_2406_03468_amd import binding
     probs = _mix(seed, count)
     dev = [(dev_colmajor(P.A), dev_vec(P.b), torch.full((P.A.shape[1],), np.nan, dtype=torch.float64, device="cuda"))
            for P in probs]
     torch.cuda.synchronize()
-    print("batched: seed", seed, "count", count, [P.A.shape for P in probs], flush=True)
-    s, sts, infos = binding.fossils_solve_batched(ctx, dev)
+    meths = [(("fossils", "spir")[i % 2] if method == "alternate" else method) for i in range(count)]
+    print("batched:", method, "seed", seed, "count", count, [P.A.shape for P in probs], flush=True)
+    s, sts, infos = binding.fossils_solve_batched(ctx, [(A, b, x, mt) for (A, b, x), mt in zip(dev, meths)])
     assert s in (0, binding.FS_WARN_NOT_CONVERGED), sts
     for i, (P, (A, b, x)) in enumerate(zip(probs, dev)):
-        ss, si, xs = _solo(ctx, A, b, P.A.shape[1])
+        ss, si, xs = _solo(ctx, A, b, P.A.shape[1], method=meths[i])
         assert infos[i].phase_ms[0] > 0 and infos[i].phase_ms[4] > 0
         _check_pair(P, host(x), xs, infos[i], si, sts[i], ss, (seed, i, P.A.shape, P.kappa, P.resid_norm))
 
