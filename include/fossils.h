@@ -208,7 +208,7 @@ typedef struct fs_problem {
  * floating-point sums: the same iterations, stopping rules and d = 12 n.  opts, if not NULL,
  * applies to every problem except d, which is 12 n_i for each (zeta <= d), and the form: FP64,
  * sketch-and-solve start, adaptive steps.  The sketch, QR, SVD and x_0 of the problems run in problem
- * order on up to eight internal streams of the context (their grid-synchronizing kernels reserve
+ * order on up to 32 internal streams of the context (their grid-synchronizing kernels reserve
  * compute units so that concurrent grids fit).  The two refinement steps run in lockstep on the
  * context's stream for waves of consecutive problems (a quarter of the batch, 8 to 64 problems) as soon
  * as their setup is done, beside the setup of the next waves: each phase of an inner iteration is one
@@ -222,7 +222,7 @@ typedef struct fs_problem {
  * that problem's setup time on its stream and phase_ms[4] its wave's refinement time (other phases
  * 0).  Inputs must be complete on the context's stream (the call waits for it); on return every x is
  * written.  Returns FS_OK, the largest warning of the problems, or the first error among them.
- * Workspace: about 8 n_i^2 + 8 G_i n_i bytes per problem kept for the batch, plus eight per-stream
+ * Workspace: about 8 n_i^2 + 8 G_i n_i bytes per problem kept for the batch, plus 32 per-stream
  * workspaces sized like fossils_solve's for the largest problem.  The context's thread only. */
 fs_status fossils_solve_batched(fs_context ctx, int32_t count, const fs_problem* problems, const fs_options* opts,
                                 fs_info* infos, fs_status* statuses);

@@ -37,7 +37,7 @@
 
 namespace {
 
-constexpr int kSetupSlots = 16;
+constexpr int kSetupSlots = 32;
 constexpr double U_ROUND = FS_U_ROUND;
 
 struct ProbLayout {
