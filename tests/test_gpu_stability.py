@@ -9,9 +9,9 @@ The methods, all built from the library's kernels through fs_options:
                                   sketch-and-solve x_0 (steps 1).
 Problems follow Figure 1's recipe (log-spaced singular values, Haar singular vectors, a uniformly
 random residual of the given norm).  The one-step variants are not backward stable, so their errors
-depend on the rounding of each run: the GPU and the oracle are compared within 30x (the oracle's own
-spread across sketch seeds is about 10x) and the qualitative claims are checked as the paper states
-them: the two-step methods stay backward stable at every difficulty, the one-step ones do not, and all
+depend on the rounding of each run (the GPU's sketch sums in a run-dependent order): the GPU and the
+oracle are compared within 100x for them (the oracle's own spread across sketch seeds is about 10x) and
+within 30x for the two-step methods, and the qualitative claims are checked as the paper states them: the two-step methods stay backward stable at every difficulty, the one-step ones do not, and all
 but sketch-and-precondition from zero are forward stable."""
 
 import numpy as np
@@ -95,7 +95,8 @@ def test_figure3_difficulty_sweep(ctx):
               " ".join(f"{k} {v['be']:.1e}/{v['fe']:.1e}" for k, v in r.items()))
         for name, v in r.items():
             # the same variant lands near the oracle's backward error (or both at the rounding floor)
-            assert v["be"] <= 30 * max(v["be_oracle"], 1e-15) and v["be_oracle"] <= 30 * max(v["be"], 1e-15), \
+            w = 30 if name in ("fossils", "spir") else 100
+            assert v["be"] <= w * max(v["be_oracle"], 1e-15) and v["be_oracle"] <= w * max(v["be"], 1e-15), \
                 (dexp, name, v["be"], v["be_oracle"])
         # the two-step methods: backward stable (Householder QR's level) at every difficulty; past
         # 1/(30 u) the sketch is numerically rank deficient and the truncated preconditioner is used
@@ -132,7 +133,8 @@ def test_figure4_grid(ctx):
                 bg = be.relative_backward_error(P.A, P.b, x, P.sigma, P.V)
                 bo = be.relative_backward_error(P.A, P.b, ref.x, P.sigma, P.V)
                 store[(kexp, rexp)] = bg
-                assert bg <= 30 * max(bo, 1e-15) and bo <= 30 * max(bg, 1e-15), (name, kexp, rexp, bg, bo)
+                w = 30 if name == "spir" else 100  # (iterative sketching with momentum is not backward stable)
+                assert bg <= w * max(bo, 1e-15) and bo <= w * max(bg, 1e-15), (name, kexp, rexp, bg, bo)
     print("SPIR BE", {k: f"{v:.1e}" for k, v in spir.items()})
     print("ISM  BE", {k: f"{v:.1e}" for k, v in ism.items()})
     for (kexp, rexp), v in spir.items():
