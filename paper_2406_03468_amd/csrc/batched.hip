@@ -94,8 +94,10 @@ void fs_batch_helpers_destroy(fs_context c) {
   c->batch = nullptr;
 }
 
-extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const fs_problem* probs,
-                                           const fs_options* opts_in, fs_info* infos, fs_status* statuses) {
+namespace {
+
+fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, const fs_options* opts_in,
+                        fs_info* infos, fs_status* statuses) {
   if (!ctx || !probs || count < 1 || !statuses) return FS_ERR_INVALID_ARG;
   if (count > 65535) return FS_ERR_TOO_LARGE;
   // ---- validation and per-problem options (every field from opts_in except d = 12 n)
@@ -190,21 +192,36 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
   // ---- setup on the helper contexts (host threads), in problem order, while the main thread refines
   // waves of problems whose setup is complete
   if (!ctx->batch) {
+    // all helpers or none: a partial set is torn down again
     ctx->batch = new BatchHelpers();
-    for (int k = 0; k < kSetupSlots; ++k) {
+    fs_status r = FS_OK;
+    for (int k = 0; k < kSetupSlots && r == FS_OK; ++k) {
       hipStream_t st = nullptr;
-      FS_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        fs_set_last_hip_error(e, "hipStreamCreateWithFlags", __FILE__, __LINE__);
+        r = FS_ERR_DEVICE;
+        break;
+      }
       fs_context c = nullptr;
-      const fs_status r = fs_context_create(ctx->device, st, &c);
+      r = fs_context_create(ctx->device, st, &c);
       if (r != FS_OK) {
         (void)hipStreamDestroy(st);
-        return r;
+        break;
       }
       ctx->batch->ctx.push_back(c);
       ctx->batch->streams.push_back(st);
       BatchReport* rep = nullptr;
-      FS_HIP(hipHostMalloc((void**)&rep, sizeof(BatchReport), hipHostMallocDefault));
-      ctx->batch->report.push_back(rep);
+      e = hipHostMalloc((void**)&rep, sizeof(BatchReport), hipHostMallocDefault);
+      ctx->batch->report.push_back(e == hipSuccess ? rep : nullptr);
+      if (e != hipSuccess) {
+        fs_set_last_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+        r = FS_ERR_NOMEM;
+      }
+    }
+    if (r != FS_OK) {
+      fs_batch_helpers_destroy(ctx);
+      return r;
     }
   }
   CoopBudget budget;
@@ -535,4 +552,19 @@ extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const 
     if (statuses[i] > result) result = statuses[i];
   }
   return result;
+}
+
+}  // namespace
+
+// (every C++ exception stops at the C boundary: allocation or thread creation failures become FS_ERR_NOMEM,
+// after the setup threads started so far have been joined)
+extern "C" fs_status fossils_solve_batched(fs_context ctx, int32_t count, const fs_problem* probs,
+                                           const fs_options* opts, fs_info* infos, fs_status* statuses) {
+  try {
+    return solve_batched(ctx, count, probs, opts, infos, statuses);
+  } catch (...) {
+    fs_set_last_hip_error(hipErrorOutOfMemory, "host allocation or thread creation in fossils_solve_batched",
+                          __FILE__, __LINE__);
+    return FS_ERR_NOMEM;
+  }
 }

@@ -11,6 +11,7 @@ import pytest
 from gpu_util import dev_colmajor, dev_vec, host
 from oracle import backward_error as be
 from oracle import householder as hh
+from oracle import solvers
 from synth import make_problem
 
 pytestmark = pytest.mark.gpu
@@ -74,7 +75,8 @@ def _check_pair(P, x_b, x_s, ib, is_, sb, ss, tag, same_order=True, qr=hh.qr_lst
         P.kappa >= 1e11, (tag, ib.flags, is_.flags)
 
 
-@pytest.mark.parametrize("seed,count,method", [(1, 6, "fossils"), (2, 24, "alternate"), (3, 16, "spir")])
+@pytest.mark.parametrize("seed,count,method", [(1, 6, "fossils"), (4, 6, "spir"), (2, 24, "alternate"),
+                                               (3, 16, "spir")])
 def test_batched_matches_solo(ctx, seed, count, method):
     """FOSSILS, SPIR, or the two alternating inside one batch."""
     import torch
@@ -91,6 +93,15 @@ def test_batched_matches_solo(ctx, seed, count, method):
         ss, si, xs = _solo(ctx, A, b, P.A.shape[1], method=meths[i])
         assert infos[i].phase_ms[0] > 0 and infos[i].phase_ms[4] > 0
         _check_pair(P, host(x), xs, infos[i], si, sts[i], ss, (seed, i, P.A.shape, P.kappa, P.resid_norm))
+        if count <= 6:
+            # and against the oracle's run of the same method (Algorithm 4 with the SVD preconditioner)
+            ref = solvers.solve(P.A, P.b, meths[i], solvers.Options(precond="svd"))
+            xb = host(x)
+            fq = max(np.linalg.norm(hh.qr_lstsq(P.A, P.b) - P.x_true) / np.linalg.norm(P.x_true), P.kappa * U)
+            assert np.linalg.norm(xb - ref.x) / np.linalg.norm(P.x_true) <= 10 * fq, (seed, i, "oracle")
+            assert abs(infos[i].iters[0] - ref.iters[0]) <= 2, (seed, i, infos[i].iters, ref.iters)
+            if P.kappa < 1e12:
+                assert abs(infos[i].iters[1] - ref.iters[1]) <= 5, (seed, i, infos[i].iters, ref.iters)
 
 
 def test_batched_fallbacks_and_errors(ctx):
