@@ -99,11 +99,15 @@ def test_high_kappa_larger_n(ctx, m, n, kappa, precond):
 
 
 def test_table2_norm_of_c_gpu(ctx):
-    """Table 2 magnitudes on the GPU: ||c_0|| ~ 3e-7, ||c_1|| ~ 1.9e-11 (within 10x)."""
+    """Table 2 magnitudes on the GPU (within 10x): ||c|| ~ 3e-7 from the sketch-and-solve start, ~1.9e-11 from
+    x_1, and ~2.0e-1 from the zero start (the first step's c with x_0 = 0)."""
+    from paper_2406_03468_amd import binding
     P = make_problem(4000, 50, 1e12, 1e-6, seed=1)
     status, info, x = _solve(ctx, P)
     assert 3.0e-8 <= info.cnorm[0] <= 3.0e-6
     assert 1.9e-12 <= info.cnorm[1] <= 1.9e-10
+    status, info, x = _solve(ctx, P, init=binding.FS_INIT_ZERO)
+    assert 2.0e-2 <= info.cnorm[0] <= 2.0, info.cnorm[0]
 
 
 def test_fixed_q_algorithm2_gpu(ctx):
