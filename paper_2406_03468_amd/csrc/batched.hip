@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <map>
 #include <condition_variable>
 #include <mutex>
@@ -81,6 +82,36 @@ struct BatchHelpers {
   std::vector<hipStream_t> streams;
   std::vector<BatchReport*> report;  // pinned host copy of each helper's last setup report
 };
+
+namespace {
+
+// Waits for the work enqueued on s so far, sleeping between polls: the setup threads outnumber the host
+// cores, and a spinning wait would hold a core that another thread needs to launch its work.
+hipError_t sync_sleep(hipStream_t s, hipEvent_t ev) {
+  hipError_t e = hipEventRecord(ev, s);
+  if (e != hipSuccess) return e;
+  while ((e = hipEventQuery(ev)) == hipErrorNotReady) std::this_thread::sleep_for(std::chrono::microseconds(50));
+  return e;
+}
+
+// Work-group reservations of the setup's grid-synchronizing kernels (see CoopBudget).
+int coop_acquire(CoopBudget& b, int need) {
+  need = std::max(1, std::min(need, b.total));
+  std::unique_lock<std::mutex> lk(b.mu);
+  b.cv.wait(lk, [&] { return b.avail >= need; });
+  b.avail -= need;
+  return need;
+}
+
+void coop_give_back(CoopBudget& b, int n) {
+  {
+    std::lock_guard<std::mutex> lk(b.mu);
+    b.avail += n;
+  }
+  b.cv.notify_all();
+}
+
+}  // namespace
 
 void fs_batch_helpers_destroy(fs_context c) {
   if (!c->batch) return;
@@ -269,18 +300,24 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
                                  o.column_scaling != 0, true, h->lds_bytes, hs);
     if (e == hipSuccess) e = fs_vec_scaling(n, cn2, o.column_scaling != 0, dinv, st, hs);
     int* sw = (int*)((char*)st + sizeof(DevState));
-    if (e == hipSuccess) {
-      // grid-synchronizing kernels: work-groups reserved against the other setup streams, the QR's and
-      // the (smaller, longer-running) SVD's one after the other
-      {
-        CoopSection coop(h, fs_qr_grid_size(d, h->num_cu));
-        e = fs_launch_qr(Y, d, d, kk, W.qrwork.p, h->num_cu, hs);
-      }
-      CoopSection coop(h, fs_svd_grid_size(n, h->num_cu, false));
-      if (e == hipSuccess)
-        e = fs_launch_svd_full(Y, d, n, sigma, V, n, nullptr, n, W.svdwork.p, h->num_cu, o.max_sweeps, sw, hs);
-      if (e == hipSuccess) e = fs_vec_sigma_stats(n, sigma, o.tau_factor, st, hs);
-    }
+    // grid-synchronizing kernels: work-groups reserved against the other setup streams, the QR's and the
+    // (smaller, longer-running) SVD's one after the other, each held until its kernel has completed
+    auto reserved = [&](int need, auto&& launch) -> hipError_t {
+      const int q = coop_acquire(budget, need);
+      hipError_t el = launch();
+      hipError_t es = sync_sleep(hs, h->ev[2]);
+      if (es != hipSuccess) (void)hipStreamSynchronize(hs);
+      coop_give_back(budget, q);
+      return el != hipSuccess ? el : es;
+    };
+    if (e == hipSuccess)
+      e = reserved(fs_qr_grid_size(d, h->num_cu), [&] { return fs_launch_qr(Y, d, d, kk, W.qrwork.p, h->num_cu, hs); });
+    if (e == hipSuccess)
+      e = reserved(fs_svd_grid_size(n, h->num_cu, false), [&] {
+        hipError_t es = fs_launch_svd_full(Y, d, n, sigma, V, n, nullptr, n, W.svdwork.p, h->num_cu, o.max_sweeps, sw,
+                                           hs);
+        return es == hipSuccess ? fs_vec_sigma_stats(n, sigma, o.tau_factor, st, hs) : es;
+      });
     // x_0 = R^{-1} t (eq:sketch-and-solve-2.3), kept as x and x0; theta^2 and ||b||^2
     if (e == hipSuccess)
       e = fs_launch_trsv_flow(Y, d, n, false, Y + (int64_t)n * d, vec, nullptr, nullptr, nullptr, W.trsv.p, hs);
@@ -293,7 +330,8 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
                       fs_trsv_flow_err_word(n, W.trsv.p), cn2, n, rep_dev, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(rep, rep_dev, sizeof(BatchReport), hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipEventRecord(e1, hs);
-    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e == hipSuccess) e = sync_sleep(hs, h->ev[2]);
+    if (e != hipSuccess) (void)hipStreamSynchronize(hs);  // (the workspace is reused by the next problem)
     if (e != hipSuccess) {
       fs_set_last_hip_error(e, "batched setup", __FILE__, __LINE__);
       fail(FS_ERR_DEVICE);
@@ -328,7 +366,6 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
   for (int k = 0; k < nthreads; ++k)
     joiner.th.emplace_back([&, k]() {
       fs_context h = ctx->batch->ctx[k];
-      h->coop_budget = &budget;
       (void)hipSetDevice(h->device);
       for (int q = k; q < nb; q += nthreads) {
         const int i = idx[q];
@@ -339,7 +376,6 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
         }
         cv.notify_all();
       }
-      h->coop_budget = nullptr;
     });
 
   // ---- lockstep refinement of one wave of set-up problems (act) on the caller's stream
