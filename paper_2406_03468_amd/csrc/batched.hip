@@ -90,7 +90,11 @@ namespace {
 hipError_t sync_sleep(hipStream_t s, hipEvent_t ev) {
   hipError_t e = hipEventRecord(ev, s);
   if (e != hipSuccess) return e;
-  while ((e = hipEventQuery(ev)) == hipErrorNotReady) std::this_thread::sleep_for(std::chrono::microseconds(50));
+  // short waits: polls that only yield the core; longer ones: 20 us sleeps between polls
+  for (int polls = 0; (e = hipEventQuery(ev)) == hipErrorNotReady; ++polls) {
+    if (polls < 64) std::this_thread::yield();
+    else std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
   return e;
 }
 

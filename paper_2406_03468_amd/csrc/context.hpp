@@ -50,6 +50,7 @@ struct fs_context_s {
   hipStream_t cap_stream = nullptr;  // private stream for graph capture (created on first use)
   hipStream_t aux_stream = nullptr;  // second stream: the SVD of R beside the first refinement step
   hipEvent_t ev_aux = nullptr;       // (both created on first use)
+  hipEvent_t ev_wait = nullptr;      // host waits of a server slot (fs_wait; created on first use)
   // Fused-pass configurations picked by fs_tune_pass (or loaded with fs_set_pass_tuning), keyed
   // by (n, floor(log2 m)); used by every pass of that shape instead of the built-in rule.
   std::map<std::pair<int, int>, std::pair<int, int>> pass_tuned;  // -> (H, G)
@@ -70,6 +71,11 @@ struct CoopBudget {
   int total = 0, avail = 0;
 };
 
+// Waits for the work enqueued on s.  A context with a budget is a server slot, one of several host threads
+// that share the host's cores: it polls an event with short sleeps, so that a waiting slot does not hold a
+// core another slot needs to launch its work.  A lone solve synchronizes the stream (lowest latency).
+hipError_t fs_wait(fs_context_s* ctx, hipStream_t s);
+
 // Holds a reservation of `need` work-groups (if the context has a budget) until the stream drains.
 struct CoopSection {
   fs_context_s* ctx;
@@ -85,7 +91,7 @@ struct CoopSection {
   }
   ~CoopSection() {
     if (!need) return;
-    (void)hipStreamSynchronize(strm);
+    if (fs_wait(ctx, strm) != hipSuccess) (void)hipStreamSynchronize(strm);
     CoopBudget* b = ctx->coop_budget;
     {
       std::lock_guard<std::mutex> lk(b->mu);

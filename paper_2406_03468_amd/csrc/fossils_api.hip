@@ -14,8 +14,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fossils.h"
@@ -46,6 +48,19 @@ fs_status validate_problem(int64_t m, int32_t n, const void* A, int64_t lda, con
 }
 fs_status validate_options(int64_t m, int32_t n, const fs_options& o) { return fs_validate_options(m, n, o); }
 }  // namespace
+
+hipError_t fs_wait(fs_context_s* ctx, hipStream_t s) {
+  if (!ctx->coop_budget) return hipStreamSynchronize(s);
+  hipError_t e = hipSuccess;
+  if (!ctx->ev_wait && (e = hipEventCreateWithFlags(&ctx->ev_wait, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventRecord(ctx->ev_wait, s)) != hipSuccess) return e;
+  // short waits: polls that only yield the core; longer ones: 20 us sleeps between polls
+  for (int polls = 0; (e = hipEventQuery(ctx->ev_wait)) == hipErrorNotReady; ++polls) {
+    if (polls < 64) std::this_thread::yield();
+    else std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  return e;
+}
 
 fs_status fs_grow(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
@@ -259,6 +274,7 @@ fs_status fs_context_destroy(fs_context c) {
     (void)hipStreamDestroy(c->aux_stream);
   }
   if (c->ev_aux) (void)hipEventDestroy(c->ev_aux);
+  if (c->ev_wait) (void)hipEventDestroy(c->ev_wait);
   fs_batch_helpers_destroy(c);
   for (auto& ev : c->ev)
     if (ev) (void)hipEventDestroy(ev);
@@ -666,8 +682,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_TRY(validate_options(m, n, o));
   FS_HIP(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  FS_HIP(hipStreamSynchronize(s));  // workspace may be reallocated below
-  if (ctx->aux_stream) FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+  FS_HIP(fs_wait(ctx, s));  // workspace may be reallocated below
+  if (ctx->aux_stream) FS_HIP(fs_wait(ctx, ctx->aux_stream));
   Workspace& W = ctx->ws;
   const int d = o.d, zeta = o.zeta, k = n + 1;
   // The SVD of R beside the first refinement step (see fs_options.overlap_svd).
@@ -770,7 +786,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
       FS_K(fs_vec_spectral_bounds(n, R, ldr, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st, s));
       FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-      FS_HIP(hipStreamSynchronize(s));
+      FS_HIP(fs_wait(ctx, s));
       bounds_done = true;
       if (!(ctx->st_host->condest * FS_MIXED_COND_FACTOR <= FS_MIXED_DISTORTION)) {
         early_fallback = true;
@@ -804,7 +820,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
       FS_HIP(hipMemcpyAsync(&bar_err[1], fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
     }
-    FS_HIP(hipStreamSynchronize(s));
+    FS_HIP(fs_wait(ctx, s));
     if (bar_err[0] || bar_err[1]) {
       fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the QR/SVD kernels gave up waiting", __FILE__,
                             __LINE__);
@@ -840,17 +856,18 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     FS_HIP(hipEventRecord(ev[3], s));
     FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
-    FS_HIP(hipStreamSynchronize(s));
+    FS_HIP(fs_wait(ctx, s));
   }
   // The deferred SVD: on the second stream after the QR, with its work-group reservation held
   // until that stream drains; the guard drains it on every exit path (the workspace is shared).
   std::unique_ptr<CoopSection> svd_coop;
   struct AuxDrain {
+    fs_context c;
     hipStream_t a = nullptr;
     ~AuxDrain() {
-      if (a) (void)hipStreamSynchronize(a);
+      if (a && fs_wait(c, a) != hipSuccess) (void)hipStreamSynchronize(a);
     }
-  } aux_drain;
+  } aux_drain{ctx};
   auto launch_aux_svd = [&]() -> fs_status {
     hipStream_t a = ctx->aux_stream;
     aux_drain.a = a;
@@ -872,7 +889,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   inf.svd_sweeps = svd_sweeps;
   if (b2 == 0.0) {  // b = 0: x = 0
     FS_HIP(hipMemsetAsync(x_out, 0, sizeof(double) * n, s));
-    FS_HIP(hipStreamSynchronize(s));
+    FS_HIP(fs_wait(ctx, s));
     if (info) *info = inf;
     return FS_OK;
   }
@@ -960,13 +977,13 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   // solve restarts (a kept FP32 sketch fails its condest, or R is numerically rank deficient).
   auto join_svd = [&](int& restarted) -> fs_status {
     restarted = 0;
-    FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+    FS_HIP(fs_wait(ctx, ctx->aux_stream));
     svd_coop.reset();
     int bar_err = 0;
     FS_HIP(hipMemcpyAsync(&bar_err, fs_svd_err_word(W.svdwork.p, n), sizeof(int), hipMemcpyDeviceToHost, s));
     FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-    FS_HIP(hipStreamSynchronize(s));
+    FS_HIP(fs_wait(ctx, s));
     if (bar_err) {
       fs_set_last_hip_error(hipErrorLaunchTimeOut, "grid barrier of the SVD kernel gave up waiting", __FILE__,
                             __LINE__);
@@ -1087,7 +1104,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     };
     auto poll_stop = [&]() -> fs_status {
       FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
-      FS_HIP(hipStreamSynchronize(s));
+      FS_HIP(fs_wait(ctx, s));
       if (ctx->st_host->stop) stopped = true;
       return FS_OK;
     };
@@ -1176,7 +1193,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
     FS_K(fs_vec_mul(n, v.z, nullptr, v.x, nullptr, s));
     FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     FS_HIP(hipEventRecord(ev[6 + (step > 0 ? 1 : 0)], s));
-    FS_HIP(hipStreamSynchronize(s));
+    FS_HIP(fs_wait(ctx, s));
     iters[step] = ctx->st_host->iters;
     cnorm[step] = sqrt(ctx->st_host->cnorm2);
     conv_last = ctx->st_host->converged != 0 || fixed;
@@ -1194,7 +1211,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   }
   if (svd_abandoned) {
     // the SVD stops at its next sweep boundary; normest and condest stay the lower bounds
-    FS_HIP(hipStreamSynchronize(ctx->aux_stream));
+    FS_HIP(fs_wait(ctx, ctx->aux_stream));
     svd_coop.reset();
     FS_HIP(hipMemcpyAsync(&svd_sweeps, svd_sweeps_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     inf.svd_sweeps = svd_sweeps;
@@ -1205,7 +1222,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
   int trsv_err = 0;
   FS_HIP(hipMemcpyAsync(&trsv_err, fs_trsv_flow_err_word(n, W.trsv.p), sizeof(int), hipMemcpyDeviceToHost, s));
-  FS_HIP(hipStreamSynchronize(s));
+  FS_HIP(fs_wait(ctx, s));
   if (trsv_err) {
     fs_set_last_hip_error(hipErrorLaunchTimeOut, "triangular solve gave up waiting for a block", __FILE__, __LINE__);
     return FS_ERR_DEVICE;
