@@ -6,26 +6,25 @@
 //              threads), whose cooperative QR / SVD grids reserve work-groups from one budget so that grids
 //              running together always fit on the GPU; results go to the problem's slice of the batch
 //              workspace;
-//   refinement the two refinement steps of a wave of set-up problems in lockstep on the caller's stream,
-//              beside the setup of the next waves: each phase of an inner iteration is one launch for the
-//              whole wave -- the passes over A as one work-list of (problem, row tiles) per tile
+//   refinement once every setup is done, the two refinement steps of all problems in lockstep on the
+//              caller's stream: each phase of an inner iteration is one launch for the whole batch -- the
+//              passes over A as one work-list of (problem, row tiles) per tile
 //              configuration, the products with V Sigma^{-1} and the heavy-ball / CG and KW steps with one
 //              work-group (or a slice of the grid) per problem.  A problem whose rule has stopped it skips
 //              the kernels of the following iterations (its stop flag), and the host polls all flags once
 //              per kw_every iterations.
 // Problems outside the batched envelope -- n above 1024 (narrower tiles than the batched pass is built
 // for), a numerically rank-deficient sketch (truncated preconditioner), b = 0 -- are finished by
-// fossils_solve on the caller's context with the caller's options.
+// fossils_solve / spir_solve on the caller's context with the caller's options.
 #include <math.h>
-
-#include <cmath>
 #include <string.h>
 
 #include <algorithm>
 #include <atomic>
 #include <chrono>
-#include <map>
+#include <cmath>
 #include <condition_variable>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -224,8 +223,8 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
   auto ptr = [&](int i, size_t off) { return (double*)(base + start[i] + off); };
   auto state_of = [&](int i) { return (DevState*)(base + start[i] + lay[i].off_state); };
 
-  // ---- setup on the helper contexts (host threads), in problem order, while the main thread refines
-  // waves of problems whose setup is complete
+  // ---- setup on the helper contexts (host threads), in problem order; the main thread refines a wave of
+  // problems once all of its setups are complete
   if (!ctx->batch) {
     // all helpers or none: a partial set is torn down again
     ctx->batch = new BatchHelpers();
@@ -554,8 +553,8 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
     return FS_OK;
   };
   // one wave after every setup: a refinement beside setup kernels runs its passes on the compute units
-  // they leave free (a pass work-group needs a compute unit's whole register file), measured 3x slower
-  // than alone, which costs more than the overlap gains
+  // they leave free (a pass work-group needs most of a compute unit's registers), measured 3x slower than
+  // alone, which costs more than the overlap gains
   const int wave = std::max(nb, 1);
   for (int w0 = 0; w0 < nb; w0 += wave) {
     const int w1 = std::min(nb, w0 + wave);
