@@ -1,8 +1,9 @@
 // n-vector kernels of the batched refinement (fossils_solve_batched): the heavy-ball iteration of
-// Algorithm 4 with P = V Sigma^{-1} for many problems in lockstep.  Each launch covers every problem
-// of the batch (blockIdx.y or blockIdx.x = problem); a problem whose stop flag is set skips the
-// kernels of an inner iteration, as in the single-problem kernels.  The arithmetic of each problem is
-// that of the single-problem kernels (k_gemv_v_part / k_sum_slices, k_gemv_vt, k_polyak, k_kw, ...).
+// Algorithm 4 (FOSSILS) or the CG iteration of Algorithm 3 (SPIR), each problem's method, with
+// P = V Sigma^{-1}, for many problems in lockstep.  Each launch covers every problem of the batch
+// (blockIdx.y or blockIdx.x = problem); a problem whose stop flag is set skips the kernels of an inner
+// iteration, as in the single-problem kernels.  The arithmetic of each problem is that of the
+// single-problem kernels (k_gemv_v_part / k_sum_slices, k_gemv_vt, k_polyak, k_cg, k_kw, ...).
 #include "common.hpp"
 #include "internal.hpp"
 #include "state.hpp"
