@@ -324,6 +324,13 @@ fs_status fs_clear_pass_tuning(fs_context ctx);
 fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32_t transpose, const double* y,
                   double* x);
 
+/* X = R^{-1} for upper-triangular R (ldr >= n): X is n x n, ld n, zeros below the diagonal; formed
+ * by blocks of 64 (diagonal blocks by back substitution, then the recursive 2 x 2 block form
+ * X12 = -X11 R12 X22).  This is P = R^{-1} of the QR preconditioner (Section 2.3) in explicit form,
+ * the form in which the refinement steps beside the SVD of R apply it.  Synchronous; uses the
+ * context's workspace (n^2 doubles of scratch).  n <= 15000; FS_ERR_SHAPE for n < 1 or ldr < n. */
+fs_status fs_triangular_inverse(fs_context ctx, int32_t n, const double* R, int64_t ldr, double* X);
+
 /* ---------------- serving: many independent solves on one GPU ---------------- */
 
 /* A solve request.  A (m x n, lda >= m), b (m) and x (n) are device arrays owned by the caller;

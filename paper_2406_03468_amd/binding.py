@@ -143,6 +143,7 @@ _SIGS = [
     ("fs_residual_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_vp,
                                    ctypes.POINTER(c_double)]),
     ("fs_trsv", c_int32, [c_vp, c_int32, c_vp, c_int64, c_int32, c_vp, c_vp]),
+    ("fs_triangular_inverse", c_int32, [c_vp, c_int32, c_vp, c_int64, c_vp]),
     ("fs_time_normal_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_int32,
                                       ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     ("fs_tune_pass", c_int32, [c_vp, c_int64, c_int32, c_vp, c_int64, c_vp, c_vp, c_int32,
@@ -510,6 +511,14 @@ def fs_trsv(ctx: Context, R, y, x, transpose: bool = False):
     n = R.shape[1]
     _check(load().fs_trsv(ctx.h, int(n), c_vp(_ptr(R)), int(_colmajor(R)), int(bool(transpose)), c_vp(_ptr(y)),
                           c_vp(_ptr(x))))
+
+
+def fs_triangular_inverse(ctx: Context, R, X):
+    """X = R^{-1} (upper-triangular R); X: n x n, column-major with leading dimension n."""
+    n = R.shape[1]
+    if tuple(X.shape) != (n, n) or _colmajor(X) != n:
+        raise ValueError("X must be n x n, column-major with leading dimension n")
+    _check(load().fs_triangular_inverse(ctx.h, int(n), c_vp(_ptr(R)), int(_colmajor(R)), c_vp(_ptr(X))))
 
 
 def fs_time_normal_pass(ctx: Context, A, z, v, repeats: int = 20):

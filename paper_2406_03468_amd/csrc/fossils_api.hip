@@ -128,11 +128,12 @@ fs_status fs_validate_options(int64_t m, int32_t n, const fs_options& o) {
 
 // History of the solve beside the SVD of R: the first step's iterates and ||Delta||^2 per iteration,
 // then the second step's KW checkpoints recorded before Sigma and V exist (dy, g and V^T g per
-// checkpoint, and four scalars each).
+// checkpoint, and four scalars each); then R^{-1} (n x n, the steps' P while the SVD runs) and the
+// scratch its blocked formation uses (n x n).
 static int fs_kw_slots(const fs_options& o) { return o.max_inner / o.kw_every + 2; }
 size_t fs_hist_bytes(int n, const fs_options& o) {
   const size_t N = (size_t)n, C = (size_t)fs_kw_slots(o);
-  return 8 * ((size_t)o.max_inner * N + (size_t)o.max_inner + 8 + 3 * C * N + 4 * C);
+  return 8 * ((size_t)o.max_inner * N + (size_t)o.max_inner + 8 + 3 * C * N + 4 * C + 2 * N * N);
 }
 
 // Upper bound of the workspace one single-right-hand-side solve (FOSSILS, SPIR, LSQR; FP64 or mixed)
@@ -616,6 +617,18 @@ fs_status fs_trsv(fs_context ctx, int32_t n, const double* R, int64_t ldr, int32
   return FS_OK;
 }
 
+fs_status fs_triangular_inverse(fs_context ctx, int32_t n, const double* R, int64_t ldr, double* X) {
+  if (!ctx || !R || !X) return FS_ERR_INVALID_ARG;
+  if (n < 1 || ldr < n) return FS_ERR_SHAPE;
+  if (n > 15000) return FS_ERR_TOO_LARGE;
+  FS_HIP(hipSetDevice(ctx->device));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  FS_TRY(grow(ctx->ws.UR, sizeof(double) * (size_t)n * n));  // scratch of the block products
+  FS_K(fs_launch_tri_inv(R, ldr, n, X, (double*)ctx->ws.UR.p, ctx->stream));
+  FS_HIP(hipStreamSynchronize(ctx->stream));
+  return FS_OK;
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- the solver
@@ -725,6 +738,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   double* kw_g = defer_fp64 ? kw_dy + (size_t)kw_slots * n : nullptr;
   double* kw_w = defer_fp64 ? kw_g + (size_t)kw_slots * n : nullptr;
   double* kw_s = defer_fp64 ? kw_w + (size_t)kw_slots * n : nullptr;
+  double* rinv = defer_fp64 ? kw_s + 4 * (size_t)kw_slots : nullptr;  // R^{-1} (ld n)
+  double* rinv_scratch = defer_fp64 ? rinv + (size_t)n * n : nullptr;
   const bool lsqr = (method == M_SPIR_LSQR);
   if (lsqr) FS_TRY(grow(W.lsqr, sizeof(double) * 2 * (size_t)m));
   double* rbuf = lsqr ? (double*)W.lsqr.p : nullptr;  // r of the last LSQR pass (m)
@@ -911,9 +926,14 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   int nr = use_svd ? rk : n;  // length of the preconditioned variables dy, c, ...
 
   // P y (into out, n) and P^T v (into out, nr); yscale/xscale fold D^{-1}.
+  // Beside the SVD (and in a second step begun before it ends) P = R^{-1} is applied many times with
+  // the same R: there it is a product with the explicit inverse, formed once after x_0.
+  bool rinv_ok = false;
   auto applyP = [&](const double* y, double* out, const double* oscale, const double* addv, const int* stp) -> fs_status {
     if (use_svd) {
       FS_K(fs_vec_gemv_v(V, n, n, nr, y, sigma, oscale, addv, out, gpart, stp, s));
+    } else if (rinv_ok) {
+      FS_K(fs_vec_gemv_v(rinv, n, n, n, y, nullptr, oscale, addv, out, gpart, stp, s));
     } else {
       FS_K(fs_launch_trsv_flow(R, ldr, n, false, y, out, nullptr, oscale, stp, W.trsv.p, s));
       if (addv) FS_K(fs_vec_add_norm(n, addv, out, out, nullptr, stp, s));
@@ -923,6 +943,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   auto applyPT = [&](const double* vin, double* out, const int* stp) -> fs_status {
     if (use_svd) {
       FS_K(fs_vec_gemv_vt(V, n, n, nr, vin, sigma, out, stp, s));
+    } else if (rinv_ok) {
+      FS_K(fs_vec_gemv_vt(rinv, n, n, n, vin, nullptr, out, stp, s));
     } else {
       FS_K(fs_launch_trsv_flow(R, ldr, n, true, vin, out, nullptr, nullptr, stp, W.trsv.p, s));
     }
@@ -937,6 +959,11 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
     } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
       FS_K(fs_launch_trsv_flow(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, W.trsv.p, s));
+    }
+    rinv_ok = false;
+    if (defer && rinv) {  // the steps beside the SVD use P = R^{-1}
+      FS_K(fs_launch_tri_inv(R, ldr, n, rinv, rinv_scratch, s));
+      rinv_ok = true;
     }
     if (o.init == FS_INIT_ZERO) FS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));  // (not captured)
     FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));

@@ -97,6 +97,9 @@ hipError_t fs_trsv_flow_reset(int n, void* ws, hipStream_t s);
 int* fs_trsv_flow_err_word(int n, void* ws);
 hipError_t fs_launch_trsv_flow(const double* R, int64_t ldr, int n, bool transpose, const double* y, double* x,
                                const double* yscale, const double* xscale, const int* stop, void* ws, hipStream_t s);
+// X = R^{-1} (n x n, ld n, zeros below the diagonal) by blocks of 64 (the recursive 2 x 2 block form);
+// T: n x n doubles of scratch.
+hipError_t fs_launch_tri_inv(const double* R, int64_t ldr, int n, double* X, double* T, hipStream_t s);
 // nrhs independent solves (one work-group each): Xb[:, r] = R^{-1} Yb[:, r] (or R^{-T}).
 hipError_t fs_launch_trsv_batched(const double* R, int64_t ldr, int n, bool transpose, const double* Yb, int64_t ldy,
                                   double* Xb, int64_t ldx, int nrhs, hipStream_t s);

@@ -56,6 +56,7 @@ int main(void) {
   EXPECT(fs_normal_pass(NULL, 10, 2, dummy, 10, dummy, dummy) == FS_ERR_INVALID_ARG);
   EXPECT(fs_residual_pass(NULL, 10, 2, dummy, 10, dummy, dummy, dummy, NULL) == FS_ERR_INVALID_ARG);
   EXPECT(fs_trsv(NULL, 2, dummy, 2, 0, dummy, dummy) == FS_ERR_INVALID_ARG);
+  EXPECT(fs_triangular_inverse(NULL, 2, dummy, 2, dummy) == FS_ERR_INVALID_ARG);
   EXPECT(fs_time_normal_pass(NULL, 10, 2, dummy, 10, dummy, dummy, 1, NULL, NULL) == FS_ERR_INVALID_ARG);
   EXPECT(fs_tune_pass(NULL, 10, 2, dummy, 10, dummy, dummy, 1, NULL, NULL, NULL) == FS_ERR_INVALID_ARG);
   EXPECT(fs_set_pass_tuning(NULL, 10, 2, 16, 256) == FS_ERR_INVALID_ARG);

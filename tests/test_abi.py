@@ -69,6 +69,7 @@ def test_validation_before_device_work(clib):
     assert clib.fs_options_default(5, 2, None) == binding.FS_ERR_INVALID_ARG
     assert clib.sketch_create(None, 10, 5, 2, 1, None) == binding.FS_ERR_INVALID_ARG
     assert clib.fs_sketch_qr(None, 10, 2, None, 10) == binding.FS_ERR_INVALID_ARG
+    assert clib.fs_triangular_inverse(None, 2, None, 2, None) == binding.FS_ERR_INVALID_ARG
     # the batched and no-allocation entry points validate before any device work
     probs = (binding.FsProblem * 1)()
     sts = (ctypes.c_int32 * 1)()

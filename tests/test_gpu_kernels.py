@@ -260,3 +260,32 @@ def test_trsv_matches_substitution(ctx, n, transpose):
     binding.fs_trsv(ctx, dev_colmajor(R, ld=n + 2), dev_vec(y), x, transpose=transpose)
     ref = hh.forward_substitution_transposed(R, y) if transpose else hh.back_substitution(R, y)
     assert np.allclose(host(x), ref, rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------- explicit inverse of R
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (5, 1e2), (64, 1e4), (65, 1e6), (127, 1e8), (200, 1e10),
+                                     (333, 1e12), (333, 1e14), (1000, 1e10)])
+def test_triangular_inverse_matches_substitution(ctx, n, kappa):
+    """X = R^{-1} column by column against the oracle's back substitution of R x = e_c, within the
+    forward-error bound of a triangular inverse, |X^ - X| <= c n u |X| |R| |X| (normwise per column,
+    c = 1); zeros below the diagonal and 1 / r_ii on it exactly.  R is the R factor of a matrix with
+    geometric singular values, stored with ld > n and other data below its diagonal (as in the
+    sketch, whose lower part holds reflectors)."""
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(n + int(np.log10(kappa)))
+    G = rng.standard_normal((2 * n + 3, n)) * np.logspace(0, -np.log10(kappa), n)
+    Ru = np.triu(np.linalg.qr(G, mode="r"))
+    Rs = Ru + np.tril(rng.standard_normal((n, n)), -1)
+    X = empty_colmajor(n, n)
+    binding.fs_triangular_inverse(ctx, dev_colmajor(Rs, ld=n + 5), X)
+    Xg = host(X)
+    assert np.all(np.tril(Xg, -1) == 0.0)
+    assert np.array_equal(np.diag(Xg), 1.0 / np.diag(Ru))
+    cols = list(range(n)) if n <= 333 else sorted({0, 1, 62, 63, 64, 65, 127, 128, 500, 511, 512, 513, 767, 768,
+                                                   958, 959, 960, 998, 999} | set(rng.choice(n, 16, replace=False).tolist()))
+    M = np.abs(Xg) @ np.abs(Ru) @ np.abs(Xg)
+    for c in cols:
+        e = np.zeros(n)
+        e[c] = 1.0
+        ref = hh.back_substitution(Ru, e)
+        assert np.linalg.norm(Xg[:, c] - ref) <= n * U * np.linalg.norm(M[:, c]), c
