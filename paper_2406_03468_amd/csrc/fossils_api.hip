@@ -957,13 +957,13 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       // truncated SVD start (Alg 4): x_0 = V_r Sigma_r^{-1} U_r^T t
       FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));
       FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
-    } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
-      FS_K(fs_launch_trsv_flow(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, W.trsv.p, s));
-    }
-    rinv_ok = false;
-    if (defer && rinv) {  // the steps beside the SVD use P = R^{-1}
+    } else if (defer && rinv) {
+      // full rank, beside the SVD: the steps use P = R^{-1}, formed here, and x_0 = R^{-1} t with it
       FS_K(fs_launch_tri_inv(R, ldr, n, rinv, rinv_scratch, s));
       rinv_ok = true;
+      FS_K(fs_vec_gemv_v(rinv, n, n, n, tvec, nullptr, nullptr, nullptr, v.x, gpart, nullptr, s));
+    } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
+      FS_K(fs_launch_trsv_flow(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, W.trsv.p, s));
     }
     if (o.init == FS_INIT_ZERO) FS_HIP(hipMemsetAsync(v.x, 0, sizeof(double) * n, s));  // (not captured)
     FS_K(fs_vec_mul(n, v.x, nullptr, v.x0, nullptr, s));
@@ -1119,7 +1119,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
           // the step stops here without Sigma and V (the first checkpoint where it holds; the exact
           // rule might have stopped at an earlier one)
           if (kw_bound_ok) {
-            FS_K(fs_launch_trsv_flow(R, ldr, n, true, v.g, v.w, nullptr, nullptr, stop, W.trsv.p, s));
+            FS_TRY(applyPT(v.g, v.w, stop));  // R^{-T} g
             FS_K(fs_vec_kw_upper(n, v.w, 1.25, st, s));
           }
         } else {

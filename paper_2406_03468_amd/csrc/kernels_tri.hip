@@ -4,7 +4,7 @@
 //
 // The inverse is formed by blocks of 64 with the recursive 2 x 2 block form of a triangular inverse:
 //   [R11 R12; 0 R22]^{-1} = [X11, -X11 R12 X22; 0, X22],  X11 = R11^{-1},  X22 = R22^{-1}.
-// The diagonal 64 x 64 blocks are inverted by back substitution, one column per thread.  Then, for
+// The diagonal 64 x 64 blocks are inverted by substitution on the identity.  Then, for
 // block sizes s = 64, 128, 256, ..., the upper-right block X12 of every 2s x 2s diagonal block is
 // formed from blocks the earlier levels finished: T12 = R12 X22, then X12 = -X11 T12.  Every entry of
 // an upper-right tile belongs to exactly one level (the highest bit in which its row and column block
@@ -17,37 +17,59 @@ namespace {
 
 constexpr int TI_B = 64;
 constexpr int TI_NT = 256;
-constexpr int TI_KC = 16;  // inner-dimension chunk of the level products
+constexpr int TI_KC = 64;  // inner-dimension chunk of the level products
 
-// One work-group per diagonal block J: X_JJ by back substitution (thread t solves R_JJ x = e_t:
-// x_i = 0 for i > t, x_t = 1 / r_tt, x_i = -(sum_{i<k<=t} r_ik x_k) / r_ii), then block column J
-// written from row j0 down (the diagonal block, zeros below it).
+// One work-group per diagonal block J: X_JJ = R_JJ^{-1} by right-looking substitution on the identity,
+// all 64 columns at once: for i = 63 .. 0, row i of X is t_i / r_ii, then rows k < i of the
+// right-hand sides take t_k -= r_ki x_i (a rank-1 update).  Thread (g, c) = (tid / 64, tid % 64) holds
+// rows g, g + 4, ..., g + 60 of column c in registers.  Then block column J is written from row j0
+// down (the diagonal block, zeros below it).
 __global__ __launch_bounds__(TI_NT) void k_tri_inv_diag(const double* __restrict__ R, int64_t ldr, int n,
                                                         double* __restrict__ X) {
-  __shared__ double rb[TI_B][TI_B + 1];  // rb[r][c] = R[j0 + r][j0 + c], upper triangle
-  __shared__ double xb[TI_B][TI_B + 1];  // xb[r][t] = X_JJ[r][t]
+  __shared__ double rb[TI_B][TI_B + 1];  // rb[r][c] = R[j0 + r][j0 + c] (upper triangle; 1 on a padded diagonal)
+  __shared__ double xrow[2][TI_B];
   const int j0 = (int)blockIdx.x * TI_B, tid = threadIdx.x;
   const int nb = min(TI_B, n - j0);
-  for (int q = tid; q < TI_B * TI_B; q += TI_NT) {
-    const int r = q & (TI_B - 1), c = q / TI_B;
-    rb[r][c] = (r < nb && c < nb && r <= c) ? R[(int64_t)(j0 + c) * ldr + j0 + r] : 0.0;
-    xb[r][c] = 0.0;
-  }
-  __syncthreads();
-  if (tid < nb) {
-    const int t = tid;
-    xb[t][t] = 1.0 / rb[t][t];
-    for (int i = t - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1; k <= t; ++k) acc = fma(rb[i][k], xb[k][t], acc);
-      xb[i][t] = -acc / rb[i][i];
+  {  // all 16 loads of a thread in flight before the LDS stores
+    double v[TI_B * TI_B / TI_NT];
+#pragma unroll
+    for (int u = 0; u < TI_B * TI_B / TI_NT; ++u) {
+      const int q = tid + TI_NT * u, r = q & (TI_B - 1), c = q / TI_B;
+      v[u] = (r < nb && c < nb && r <= c) ? R[(int64_t)(j0 + c) * ldr + j0 + r] : ((r == c && r >= nb) ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < TI_B * TI_B / TI_NT; ++u) {
+      const int q = tid + TI_NT * u;
+      rb[q & (TI_B - 1)][q / TI_B] = v[u];
     }
   }
+  const int g = tid >> 6, c = tid & (TI_B - 1);
+  double t[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) t[u] = (g + 4 * u == c) ? 1.0 : 0.0;
   __syncthreads();
+#pragma unroll
+  for (int i = TI_B - 1; i >= 0; --i) {
+    const int gi = i & 3, ui = i >> 2;
+    if (g == gi) {
+      const double xv = t[ui] / rb[i][i];
+      t[ui] = xv;
+      xrow[i & 1][c] = xv;
+    }
+    __syncthreads();
+    const double xi = xrow[i & 1][c];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (4 * u + 3 < i || (4 * u < i && g + 4 * u < i)) t[u] = fma(-rb[g + 4 * u][i], xi, t[u]);
+    }
+  }
   const int rows = n - j0;  // rows j0 .. n-1 of the block's columns
-  for (int c = 0; c < nb; ++c) {
+  if (c < nb) {
     double* col = X + (int64_t)(j0 + c) * n + j0;
-    for (int r = tid; r < rows; r += TI_NT) col[r] = (r < TI_B) ? xb[r][c] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (g + 4 * u < nb) col[g + 4 * u] = t[u];
+    for (int r = TI_B + g; r < rows; r += 4) col[r] = 0.0;
   }
 }
 
@@ -56,7 +78,7 @@ __global__ __launch_bounds__(TI_NT) void k_tri_inv_diag(const double* __restrict
 // output column j takes k <= j only); mode 1: X12 = -X11 T12 (inner dimension s; X11 upper
 // triangular, so output row i takes k >= i only).  64 x 64 output tiles (blockIdx.x: row tile,
 // blockIdx.y: column tile, blockIdx.z: pair), 256 threads with 4 x 4 outputs each, the inner
-// dimension in chunks of 16 staged in LDS.
+// dimension in chunks of 64 staged in LDS.
 __global__ __launch_bounds__(TI_NT) void k_tri_inv_level(const double* __restrict__ R, int64_t ldr, int n, int s,
                                                          int mode, double* __restrict__ X, double* __restrict__ T) {
   const int a = 2 * (int)blockIdx.z * s;
@@ -91,38 +113,46 @@ __global__ __launch_bounds__(TI_NT) void k_tri_inv_level(const double* __restric
   }
   const int64_t ldb = n, ldc = n;
   __shared__ double As[TI_KC][TI_B + 1];  // As[k][r] = A[i0 + r][k0 + k]
-  __shared__ double Bs[TI_KC][TI_B + 1];  // Bs[k][c] = B[k0 + k][j0 + c]
+  __shared__ double Bs[TI_B][TI_KC + 1];  // Bs[c][k] = B[k0 + k][j0 + c]
   const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int k0 = kbeg; k0 < kend; k0 += TI_KC) {
-    // A chunk: 64 rows x 16 (rows i0 + r < s always: s is a multiple of 64)
+  // both 64 x 64 chunks of the next inner-dimension step are loaded (into registers) while the
+  // current one is multiplied out of LDS.  A rows i0 + r < s always (s is a multiple of 64); B
+  // columns j0 + c < s2.
+  double av[16], bv[16];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 16; ++u) {
       const int r = tid & (TI_B - 1), k = (tid >> 6) + 4 * u;
-      As[k][r] = (k0 + k < kend) ? A[(int64_t)(k0 + k) * lda + i0 + r] : 0.0;
+      av[u] = (k0 + k < kend) ? A[(int64_t)(k0 + k) * lda + i0 + r] : 0.0;
+      const int kb = tid & (TI_KC - 1), cb = (tid >> 6) + 4 * u;
+      bv[u] = (k0 + kb < kend && j0 + cb < s2) ? B[(int64_t)(j0 + cb) * ldb + k0 + kb] : 0.0;
     }
-    // B chunk: 16 x 64 columns (columns j0 + c < s2)
+  };
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += TI_KC) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int k = tid & (TI_KC - 1), c = (tid >> 4) + 16 * u;
-      Bs[k][c] = (k0 + k < kend && j0 + c < s2) ? B[(int64_t)(j0 + c) * ldb + k0 + k] : 0.0;
+    for (int u = 0; u < 16; ++u) {
+      As[(tid >> 6) + 4 * u][tid & (TI_B - 1)] = av[u];
+      Bs[(tid >> 6) + 4 * u][tid & (TI_KC - 1)] = bv[u];
     }
     __syncthreads();
-#pragma unroll
+    if (k0 + TI_KC < kend) load(k0 + TI_KC);
+#pragma unroll 8
     for (int k = 0; k < TI_KC; ++k) {
-      double av[4], bv[4];
+      double a4[4], b4[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = As[k][tr + 16 * u];
+      for (int u = 0; u < 4; ++u) a4[u] = As[k][tr + 16 * u];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = Bs[k][tc + 16 * v];
+      for (int v = 0; v < 4; ++v) b4[v] = Bs[tc + 16 * v][k];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a4[u], b4[v], acc[u][v]);
     }
     __syncthreads();
   }

@@ -239,18 +239,32 @@ __global__ __launch_bounds__(TF_NT) void k_trsv_flow(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------- dense products with V (n x k, ld)
-// out[i] = oscale[i] * sum_j V[i, j] (y[j] * yscale[j])  -- partial over column slices
+// out[i] = oscale[i] * sum_j V[i, j] (y[j] / ydiv[j])  -- partials over column slices of cs columns:
+// a work-group takes 64 rows of one slice, each of its four waves a quarter of the slice's columns
+// (two accumulators), the quarters summed in LDS
 __global__ __launch_bounds__(256) void k_gemv_v_part(const double* __restrict__ V, int64_t ldv, int n, int k,
                                                      const double* __restrict__ y, const double* __restrict__ ydiv,
                                                      double* __restrict__ part, int cs, const int* __restrict__ stop) {
   if (fs_stopped(stop)) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   const int slice = blockIdx.y;
-  const int j0 = slice * cs, j1 = min(k, j0 + cs);
-  if (i >= n) return;
-  double s = 0.0;
-  for (int j = j0; j < j1; ++j) s = fma(V[(int64_t)j * ldv + i], ydiv ? y[j] / ydiv[j] : y[j], s);
-  part[(int64_t)slice * n + i] = s;
+  const int qc = cs / 4;
+  const int j0 = slice * cs + w * qc, j1 = min(k, j0 + qc);
+  double s0 = 0.0, s1 = 0.0;
+  if (i < n) {
+    int j = j0;
+#pragma unroll 4
+    for (; j + 1 < j1; j += 2) {
+      s0 = fma(V[(int64_t)j * ldv + i], ydiv ? y[j] / ydiv[j] : y[j], s0);
+      s1 = fma(V[(int64_t)(j + 1) * ldv + i], ydiv ? y[j + 1] / ydiv[j + 1] : y[j + 1], s1);
+    }
+    if (j < j1) s0 = fma(V[(int64_t)j * ldv + i], ydiv ? y[j] / ydiv[j] : y[j], s0);
+  }
+  red[w][lane] = s0 + s1;
+  __syncthreads();
+  if (w == 0 && i < n) part[(int64_t)slice * n + i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 __global__ __launch_bounds__(256) void k_sum_slices(const double* __restrict__ part, int nslices, int n,
@@ -878,7 +892,7 @@ hipError_t fs_vec_gemv_v(const double* V, int64_t ldv, int n, int k, const doubl
                          hipStream_t s) {
   const int cs = 64;
   const int ns = (k + cs - 1) / cs;
-  hipLaunchKernelGGL(k_gemv_v_part, dim3((n + 255) / 256, ns), dim3(256), 0, s, V, ldv, n, k, y, ydiv, part, cs,
+  hipLaunchKernelGGL(k_gemv_v_part, dim3((n + 63) / 64, ns), dim3(256), 0, s, V, ldv, n, k, y, ydiv, part, cs,
                      stop);
   hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, s, part, ns, n, oscale, addv, out, stop);
   return hipGetLastError();
