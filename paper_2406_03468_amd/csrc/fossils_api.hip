@@ -740,6 +740,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
   double* kw_s = defer_fp64 ? kw_w + (size_t)kw_slots * n : nullptr;
   double* rinv = defer_fp64 ? kw_s + 4 * (size_t)kw_slots : nullptr;  // R^{-1} (ld n)
   double* rinv_scratch = defer_fp64 ? rinv + (size_t)n * n : nullptr;
+  bool rinv_ok = false;  // rinv holds R^{-1} of the current R
   const bool lsqr = (method == M_SPIR_LSQR);
   if (lsqr) FS_TRY(grow(W.lsqr, sizeof(double) * 2 * (size_t)m));
   double* rbuf = lsqr ? (double*)W.lsqr.p : nullptr;  // r of the last LSQR pass (m)
@@ -792,6 +793,14 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       FS_K(fs_launch_qr(Y, d, d, k, W.qrwork.p, ctx->num_cu, s));
       FS_HIP(hipEventRecord(ev[2], s));
     }
+    // with the SVD beside the refinement: R^{-1} for the spectral bounds, x_0 and the steps that run
+    // before Sigma and V exist
+    rinv_ok = false;
+    if (defer_svd && rinv) {
+      FS_K(fs_launch_tri_inv(R, ldr, n, rinv, rinv_scratch, s));
+      rinv_ok = true;
+    }
+    const double* rinv_b = rinv_ok ? rinv : nullptr;
     bool bounds_done = false;
     if (fp32) {
       // A lower bound of cond(R) (diag(R), then power and inverse iteration, about 0.5 ms at n = 1000)
@@ -799,7 +808,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       // u32 condest > 2 drops it at once (the SVD would only confirm); otherwise the SVD's condest
       // decides later.
       FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
-      FS_K(fs_vec_spectral_bounds(n, R, ldr, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st, s));
+      FS_K(fs_vec_spectral_bounds(n, R, ldr, rinv_b, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st,
+                                  s));
       FS_HIP(hipMemcpyAsync(ctx->st_host, st, sizeof(DevState), hipMemcpyDeviceToHost, s));
       FS_HIP(fs_wait(ctx, s));
       bounds_done = true;
@@ -817,7 +827,8 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       FS_HIP(hipEventRecord(ctx->ev_aux, s));
       if (!bounds_done) {
         FS_K(fs_vec_diag_bounds(n, R, ldr, st, s));
-        FS_K(fs_vec_spectral_bounds(n, R, ldr, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st, s));
+        FS_K(fs_vec_spectral_bounds(n, R, ldr, rinv_b, 4, (double*)W.vecs.p + (size_t)16 * n, gpart, W.trsv.p, st,
+                                  s));
       }
     } else {
       CoopSection coop(ctx, fs_svd_grid_size(n, ctx->num_cu, false));
@@ -927,8 +938,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
 
   // P y (into out, n) and P^T v (into out, nr); yscale/xscale fold D^{-1}.
   // Beside the SVD (and in a second step begun before it ends) P = R^{-1} is applied many times with
-  // the same R: there it is a product with the explicit inverse, formed once after x_0.
-  bool rinv_ok = false;
+  // the same R: there it is a product with the explicit inverse, formed once after the QR.
   auto applyP = [&](const double* y, double* out, const double* oscale, const double* addv, const int* stp) -> fs_status {
     if (use_svd) {
       FS_K(fs_vec_gemv_v(V, n, n, nr, y, sigma, oscale, addv, out, gpart, stp, s));
@@ -957,10 +967,7 @@ fs_status solve(fs_context ctx, Method method, int64_t m, int32_t n, const doubl
       // truncated SVD start (Alg 4): x_0 = V_r Sigma_r^{-1} U_r^T t
       FS_K(fs_vec_gemv_vt(UR, n, n, nr, tvec, nullptr, v.tmp, nullptr, s));
       FS_K(fs_vec_gemv_v(V, n, n, nr, v.tmp, sigma, nullptr, nullptr, v.x, gpart, nullptr, s));
-    } else if (defer && rinv) {
-      // full rank, beside the SVD: the steps use P = R^{-1}, formed here, and x_0 = R^{-1} t with it
-      FS_K(fs_launch_tri_inv(R, ldr, n, rinv, rinv_scratch, s));
-      rinv_ok = true;
+    } else if (rinv_ok) {  // full rank, beside the SVD: x_0 = R^{-1} t with the explicit inverse
       FS_K(fs_vec_gemv_v(rinv, n, n, n, tvec, nullptr, nullptr, nullptr, v.x, gpart, nullptr, s));
     } else {  // full rank: V Sigma^{-1} U_R^T t = R^{-1} t (eq:sketch-and-solve-2.3)
       FS_K(fs_launch_trsv_flow(R, ldr, n, false, tvec, v.x, nullptr, nullptr, nullptr, W.trsv.p, s));

@@ -914,8 +914,8 @@ hipError_t fs_vec_diag_bounds(int n, const double* R, int64_t ldr, DevState* st,
   hipLaunchKernelGGL(k_diag_bounds, dim3(1), dim3(VNT), 0, s, n, R, ldr, st);
   return hipGetLastError();
 }
-hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, int iters, double* work, double* part,
-                                  void* trsv_ws, DevState* st, hipStream_t s) {
+hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, const double* Rinv, int iters, double* work,
+                                  double* part, void* trsv_ws, DevState* st, hipStream_t s) {
   double* v = work;          // power-iteration vector
   double* x = work + n;      // inverse-iteration vector
   double* p = work + 2 * n;  // R v
@@ -929,9 +929,16 @@ hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, int iters
     hipLaunchKernelGGL(k_sum_slices, dim3((n + 255) / 256), dim3(256), 0, s, part, ns, n, (const double*)nullptr,
                        (const double*)nullptr, p, (const int*)nullptr);
     hipLaunchKernelGGL(k_trmv_t, dim3(n), dim3(256), 0, s, R, ldr, n, p, q);
-    hipError_t e = fs_launch_trsv_flow(R, ldr, n, true, x, w, nullptr, nullptr, nullptr, trsv_ws, s);
-    if (e != hipSuccess) return e;
-    e = fs_launch_trsv_flow(R, ldr, n, false, w, y, nullptr, nullptr, nullptr, trsv_ws, s);
+    hipError_t e;
+    if (Rinv) {  // products with the explicit inverse (ld n)
+      e = fs_vec_gemv_vt(Rinv, n, n, n, x, nullptr, w, nullptr, s);
+      if (e != hipSuccess) return e;
+      e = fs_vec_gemv_v(Rinv, n, n, n, w, nullptr, nullptr, nullptr, y, part, nullptr, s);
+    } else {
+      e = fs_launch_trsv_flow(R, ldr, n, true, x, w, nullptr, nullptr, nullptr, trsv_ws, s);
+      if (e != hipSuccess) return e;
+      e = fs_launch_trsv_flow(R, ldr, n, false, w, y, nullptr, nullptr, nullptr, trsv_ws, s);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bound_step, dim3(1), dim3(VNT), 0, s, n, p, v, q, w, y, v, x, st);
   }

@@ -44,9 +44,11 @@ hipError_t fs_vec_polyak(int n, const double* c, const double* u, double* dy, do
 hipError_t fs_vec_diag_bounds(int n, const double* R, int64_t ldr, DevState* st, hipStream_t s);
 // Sharper bounds for the same purpose (after fs_vec_diag_bounds): `iters` steps of power iteration
 // on R^T R (normest from below) and of inverse iteration (sigma_min from above, condest from below).
-// work: 4 n doubles; trsv_ws: the workspace of the triangular solves across work-groups.
-hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, int iters, double* work, double* part,
-                                  void* trsv_ws, DevState* st, hipStream_t s);
+// work: 6 n doubles; part: the partials of a product with an n x n matrix.  Rinv (may be null): R^{-1}
+// (ld n), whose products then replace the substitutions; trsv_ws: the workspace of the triangular
+// solves across work-groups.
+hipError_t fs_vec_spectral_bounds(int n, const double* R, int64_t ldr, const double* Rinv, int iters, double* work,
+                                  double* part, void* trsv_ws, DevState* st, hipStream_t s);
 hipError_t fs_vec_record_iter(int j, int n, const double* dy, double* hist_dy, double* hist_dn, const DevState* st,
                               hipStream_t s);
 hipError_t fs_vec_rollback(int n, const double* hist_dy, const double* hist_dn, double* dy, DevState* st,
