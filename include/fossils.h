@@ -92,7 +92,9 @@ typedef struct fs_options {
                              zero start of plain sketch-and-precondition, for the Section 5.1 comparisons) */
   int32_t overlap_svd;    /* 1 (P = V Sigma^{-1}, adaptive FOSSILS or CG-SPIR): the SVD of R runs on a
                              second stream while the refinement iterates with P = R^{-1} (the same
-                             preconditioned system up to an orthogonal change of variables).  Until the
+                             preconditioned system up to an orthogonal change of variables; R^{-1} is
+                             formed once after the QR, see fs_triangular_inverse, and applied as a
+                             product; the workspace holds 2 n^2 doubles more for it).  Until the
                              SVD is done the first-step rule uses lower bounds of normest and condest
                              (diag(R), power and inverse iteration): if the SVD arrives first, the step is
                              cut back to the iteration where the true rule stops; if the step stops on
