@@ -85,7 +85,8 @@ __global__ __launch_bounds__(256) void k_sketch_indices(int64_t col0, int64_t nc
 // One work-group per (column panel, sketch-row chunk).  Columns c < n come from A, columns
 // n <= c < ncols from B (ldb).  PW is the compile-time panel width (columns held in LDS at once);
 // np <= PW columns are active.  Each thread walks RU rows per step with all their loads issued
-// before the LDS atomics (memory-level parallelism); for zeta = 8 with 16-bit entries the eight
+// before the LDS atomics (memory-level parallelism), and, for panels of up to 4 columns (2 with
+// 32-bit entries), the next step's loads before the current step's atomics; for zeta = 8 with 16-bit entries the eight
 // entries of a row come in one 16-byte load.  TA is the element type of A (double, or float for the
 // mixed-precision form's FP32 copy); R32 rounds double inputs to FP32 first (the mixed form without
 // a resident copy).  The LDS accumulator is FP64 in every form: on gfx950 an FP32 LDS atomic add
@@ -136,9 +137,9 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
     }
   };
 
-  for (int64_t i0 = tid; i0 < m; i0 += (int64_t)NT * RU) {
-    double a[RU][PW];
-    uint4 e8[RU];
+  // RU rows per thread and step; with two register buffers the loads of the next step are issued
+  // before the atomics of the current one, so that HBM reads and LDS atomics of a wave overlap.
+  auto load_rows = [&](double (&a)[RU][PW], uint4 (&e8)[RU], int64_t i0) {
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int64_t i = i0 + (int64_t)u * NT;
@@ -149,6 +150,8 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
                                  : 0.0;
       if (Z8) e8[u] = ok ? *reinterpret_cast<const uint4*>(idx + i * 8) : make_uint4(0u, 0u, 0u, 0u);
     }
+  };
+  auto process_rows = [&](const double (&a)[RU][PW], const uint4 (&e8)[RU], int64_t i0) {
 #pragma unroll
     for (int u = 0; u < RU; ++u) {
       const int64_t i = i0 + (int64_t)u * NT;
@@ -168,6 +171,55 @@ __global__ __launch_bounds__(NT) void k_sketch_apply(const TA* __restrict__ A, i
       } else {
         const IDX* e = idx + i * zeta;
         for (int k = 0; k < zeta; ++k) scatter((uint32_t)e[k], a[u]);
+      }
+    }
+  };
+  const int64_t S = (int64_t)NT * RU;
+  if constexpr (PW * sizeof(IDX) <= 8) {  // (wider panels have no registers for a second buffer)
+    double a0[RU][PW], a1[RU][PW];
+    uint4 e0[RU], e1[RU];
+    load_rows(a0, e0, tid);
+    for (int64_t i0 = tid; i0 < m; i0 += 2 * S) {
+      load_rows(a1, e1, i0 + S);
+      process_rows(a0, e0, i0);
+      if (i0 + S >= m) break;
+      load_rows(a0, e0, i0 + 2 * S);
+      process_rows(a1, e1, i0 + S);
+    }
+  } else {
+    for (int64_t i0 = tid; i0 < m; i0 += S) {
+      double a[RU][PW];
+      uint4 e8[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        const bool ok = i < m;
+#pragma unroll
+        for (int p = 0; p < PW; ++p)
+          a[u][p] = (ok && p < np) ? (colA[p] ? (R32 ? (double)(float)colA[p][i] : (double)colA[p][i]) : colB[p][i])
+                                   : 0.0;
+        if (Z8) e8[u] = ok ? *reinterpret_cast<const uint4*>(idx + i * 8) : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int64_t i = i0 + (int64_t)u * NT;
+        if (i >= m) break;
+#pragma unroll
+        for (int p = 0; p < PW; ++p) {
+          ss[p] = fma(a[u][p], a[u][p], ss[p]);
+          bad |= (int)(!isfinite(a[u][p])) << p;
+        }
+        if (Z8) {
+          const uint32_t w4[4] = {e8[u].x, e8[u].y, e8[u].z, e8[u].w};
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            scatter(w4[q] & 0xFFFFu, a[u]);
+            scatter(w4[q] >> 16, a[u]);
+          }
+        } else {
+          const IDX* e = idx + i * zeta;
+          for (int k = 0; k < zeta; ++k) scatter((uint32_t)e[k], a[u]);
+        }
       }
     }
   }
