@@ -322,9 +322,11 @@ __device__ __forceinline__ void wait_flag(unsigned* f, unsigned target, int* err
 }
 
 // NQ: elements per lane of a register-resident column (0: loop over LDS); LP: lanes per pair (16 for
-// n <= 256, so that a wave rotates four pairs at once, else 64).
-template <int NQ, int LP>
-__global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
+// n <= 256, so that a wave rotates four pairs at once, else 64); NT: threads per work-group; SINGLE:
+// one work-group holds every column (two blocks, nothing is exchanged), so the exchange code and its
+// registers are left out and the work-group can have 1024 threads (64 pair groups of 16 lanes).
+template <int NQ, int LP, int NT = SVD_BLOCK_NT, bool SINGLE = false>
+__global__ __launch_bounds__(NT) void k_jacobi_block(double* __restrict__ Gm, int n, int b, int NBLK, int max_sweeps,
                                                       double tol, double* __restrict__ mbox, unsigned* __restrict__ flags,
                                                       int* __restrict__ rotcount, int* __restrict__ sweeps_out,
                                                       GridBarrier bar, unsigned long long* __restrict__ maxcos2,
@@ -349,9 +351,9 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
   // mailbox layout: [P][2 slots][2 parities][b*n]
   auto mb = [&](int wg, int sl, int par) { return (((size_t)wg * 2 + sl) * 2 + par) * blk; };  // element offset
   const auto rmbox = co_rsrc(mbox, sizeof(double) * (size_t)P * 4 * blk);
-  __shared__ int s_nrot[SVD_BLOCK_NT / 16];
-  __shared__ double s_c2[SVD_BLOCK_NT / 16];
-  __shared__ double s_ynorm[SVD_BLOCK_NT / 16];  // b <= groups <= SVD_BLOCK_NT / 16
+  __shared__ int s_nrot[NT / 16];
+  __shared__ double s_c2[NT / 16];
+  __shared__ double s_ynorm[NT / 16];  // b <= groups <= NT / 16
   int sweep = 0;
   unsigned rr = 0;  // global round counter
   for (; sweep < max_sweeps; ++sweep) {
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(SVD_BLOCK_NT) void k_jacobi_block(double* __restric
           __syncthreads();
         }
       }
-      if (NBLK == 2) continue;  // a single work-group holds every column: nothing moves
+      if (SINGLE || NBLK == 2) continue;  // a single work-group holds every column: nothing moves
       // ---- exchange.  In the next round position q >= 2 holds the block now at q + 1... i.e. blocks
       // move from position q to q - 1 (q >= 2), position 1 wraps to NBLK - 1, position 0 is fixed:
       //   top (position p):          p >= 2 -> top of p-1;  p == 1 -> bottom of 0
@@ -826,7 +828,10 @@ hipError_t fs_launch_svd_abortable(const double* R, int64_t ldr, int n, double* 
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const size_t shmem = (size_t)2 * bw * n * sizeof(double);
     // columns of up to 2048 rows are rotated from registers (NQ = elements per lane)
+    // (65..128 columns: one work-group of 1024 threads holds them all, blocks of up to 64 columns)
+    const bool single1k = (n > 64 && n <= 128 && P == 1);
     const void* kfn = (n <= 64)     ? (const void*)k_jacobi_block<4, 16>
+                      : single1k    ? (const void*)k_jacobi_block<8, 16, 1024, true>
                       : (n <= 128)  ? (const void*)k_jacobi_block<8, 16>
                       : (n <= 256)  ? (const void*)k_jacobi_block<16, 16>
                       : (n <= 512)  ? (const void*)k_jacobi_block<8, 64>
@@ -840,7 +845,7 @@ hipError_t fs_launch_svd_abortable(const double* R, int64_t ldr, int n, double* 
     double stop_cos2 = 1e-10;  // a sweep whose cosines all stayed <= 1e-5 ends the iteration
     void* args[] = {&Gm, &n, &bw2, &NB2, &max_sweeps, &tol, &mbox, &flg, &rot, &sweeps_out_dev, &bar_co, &mc2,
                     &stop_cos2, &abort_flag};
-    e = fs_launch_resident(kfn, dim3(P), dim3(SVD_BLOCK_NT), args, shmem, s);
+    e = fs_launch_resident(kfn, dim3(P), dim3(single1k ? 1024 : SVD_BLOCK_NT), args, shmem, s);
     if (e != hipSuccess) return e;
   } else {
     int G = (n + 1) / 2;

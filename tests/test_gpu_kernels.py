@@ -116,7 +116,8 @@ def test_qr_backward_property_ill_conditioned(ctx, d, k, kappa):
 
 # ---------------------------------------------------------------- SVD of R
 @pytest.mark.parametrize("n,kappa", [(50, 1e10), (301, 1e12), (7, 1.0), (1000, 1e10), (1999, 1e6), (130, 1e14),
-                                     (1000, 1e14), (300, 1e13), (200, 1e10), (256, 1e12), (97, 1e8)])
+                                     (1000, 1e14), (300, 1e13), (200, 1e10), (256, 1e12), (97, 1e8),
+                                     (65, 1e12), (111, 1e14), (128, 1e10)])
 def test_svd_of_triangular(ctx, n, kappa):
     from paper_2406_03468_amd import binding
     rng = np.random.default_rng(n)
