@@ -376,6 +376,34 @@ def test_overlapped_svd_rank_deficient_restart(ctx):
     assert abs(np.linalg.norm(r1) - np.linalg.norm(r0)) <= 1e-12 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("method", ["fossils", "spir"])
+def test_zero_column_rank_deficient(ctx, method):
+    """An exactly zero column gives R an exactly zero diagonal entry: the steps run beside the SVD with
+    P = R^{-1} (explicit inverse) carry non-finite values until the SVD reports the rank deficiency; the
+    solve then restarts with the truncated preconditioner and returns the serial order's answer."""
+    import torch
+    from paper_2406_03468_amd import binding
+    rng = np.random.default_rng(11)
+    A = rng.standard_normal((3000, 20)) * np.logspace(0, -3, 20)
+    A[:, 7] = 0.0
+    b = rng.standard_normal(3000)
+    fn = binding.fossils_solve if method == "fossils" else binding.spir_solve
+    res = []
+    for ov in (0, 1):
+        o = binding.fs_options_default(3000, 20)
+        o.overlap_svd = ov
+        x = torch.zeros(20, dtype=torch.float64, device="cuda")
+        st, info = fn(ctx, dev_colmajor(A), dev_vec(b), x, o)
+        assert st == binding.FS_WARN_RANK_DEFICIENT and info.flags & 1 and info.rank == 19, (ov, st, info.to_dict())
+        xh = host(x)
+        assert np.all(np.isfinite(xh)) and abs(xh[7]) <= 1e-10 * np.linalg.norm(xh)
+        res.append(xh)
+    for xh in res:
+        r = b - A @ xh
+        assert np.linalg.norm(A.T @ r) <= 1e-10 * np.linalg.norm(A) * np.linalg.norm(b)
+    assert abs(np.linalg.norm(b - A @ res[1]) - np.linalg.norm(b - A @ res[0])) <= 1e-12 * np.linalg.norm(b)
+
+
 @pytest.mark.parametrize("d_factor,zeta", [(2, 1), (3, 3), (20, 16), (12, 64)])
 def test_embedding_parameters(ctx, d_factor, zeta):
     """Other sketch sizes and sparsities than Alg 4's (d = 12 n, zeta = 8): the non-packed index path
