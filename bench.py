@@ -11,7 +11,9 @@ Printed as one JSON line:
                  bytes: the sketch, the two residual passes, one per inner iteration and one per
                  sketched-KW check) divided by the measured solve time;
   ms_per_step    mean solve time;
-  loop_GBps      the same for the refinement loop alone (passes inside the two steps / their time);
+  loop_GBps      the same for the refinement loop alone (passes inside the two steps / their time),
+                 with its fraction of the 8 TB/s peak; the first step runs beside the SVD of R;
+  loop_serial    the same problems in the serial order (SVD first): the loop with the whole GPU;
   roofline       the fused A^T(A z) kernel timed live with HIP events on the library's stream,
                  against the 8 TB/s HBM peak;
   cpu_baseline   the CPU oracle's own complete FOSSILS solve (oracle.solvers.fossils, Algorithm 4)
@@ -703,6 +705,34 @@ def main():
     loop_ms = sum(inf.phase_ms[3] + inf.phase_ms[4] + inf.phase_ms[5] for _, _, inf in infos)
     loop_gbps = loop_bytes / (loop_ms / 1e3) / 1e9 if loop_ms > 0 else None
 
+    # ---- the refinement loop with the whole GPU: the same problems in the serial order (the SVD of R
+    # before the refinement, opts.overlap_svd = 0), one solve each after a warm-up, outside the timed
+    # region; the overlapped order above trades this loop rate for a shorter solve
+    opts_serial = binding.fs_options_default(M, N)
+    opts_serial.precond = opts.precond
+    opts_serial.overlap_svd = 0
+    xs_serial = [torch.zeros(N, dtype=torch.float64, device=dev) for _ in probs]
+    solve(ctx, probs[0].A, probs[0].b, xs_serial[0], opts_serial)
+    torch.cuda.synchronize()
+    ser_infos, ser_ms = [], []
+    for i, P in enumerate(probs):
+        ts = time.perf_counter()
+        st_s, inf_s = solve(ctx, P.A, P.b, xs_serial[i], opts_serial)
+        ser_ms.append(1e3 * (time.perf_counter() - ts))
+        ser_infos.append((st_s, inf_s))
+    ser_loop_bytes = sum(passes_of(inf) - 1 for _, inf in ser_infos) * bytes_per_pass
+    ser_loop_ms = sum(inf.phase_ms[3] + inf.phase_ms[4] + inf.phase_ms[5] for _, inf in ser_infos)
+    ser_loop_gbps = ser_loop_bytes / (ser_loop_ms / 1e3) / 1e9 if ser_loop_ms > 0 else None
+    loop_serial = {"loop_GBps": None if ser_loop_gbps is None else round(ser_loop_gbps, 1),
+                   "frac_of_peak": None if ser_loop_gbps is None else round(ser_loop_gbps / HBM_PEAK_GBPS, 4),
+                   "solve_ms": [round(t, 2) for t in ser_ms], "status": [int(st_s) for st_s, _ in ser_infos],
+                   "iters": [list(inf.iters) for _, inf in ser_infos],
+                   "phase_ms": [[round(p_, 2) for p_ in inf.phase_ms] for _, inf in ser_infos],
+                   "workload": "the timed problems (one solve each) in the serial order: SVD of R first, "
+                               "then the refinement loop on the whole GPU"}
+    print(f"# serial order: loop {ser_loop_gbps:.0f} GB/s, solves {[round(t, 1) for t in ser_ms]} ms, "
+          f"iters {loop_serial['iters']}", file=sys.stderr, flush=True)
+
     # ---- roofline of the dominant kernel: the fused normal-equation pass, live HIP events
     z = torch.randn(N, dtype=torch.float64, device=dev)
     v = torch.empty(N, dtype=torch.float64, device=dev)
@@ -832,6 +862,8 @@ def main():
                    "method": args.method, "precond": args.precond},
         "solve_ms": [round(1e3 * t, 3) for t in times],
         "loop_GBps": None if loop_gbps is None else round(loop_gbps, 1),
+        "loop_frac_of_peak": None if loop_gbps is None else round(loop_gbps / HBM_PEAK_GBPS, 4),
+        "loop_serial": loop_serial,
         "iters": iters, "kw_evals": [inf.kw_evals for _, _, inf in infos],
         "phase_ms_last": [round(p, 3) for p in infos[-1][2].phase_ms],
         "roofline": roofline, "cpu_baseline": cpu, "accuracy": accuracy, "pass_autotune": autotune_rec,
