@@ -265,7 +265,7 @@ def test_trsv_matches_substitution(ctx, n, transpose):
 
 # ---------------------------------------------------------------- explicit inverse of R
 @pytest.mark.parametrize("n,kappa", [(1, 1.0), (5, 1e2), (64, 1e4), (65, 1e6), (127, 1e8), (200, 1e10),
-                                     (333, 1e12), (333, 1e14), (1000, 1e10)])
+                                     (333, 1e12), (333, 1e14), (513, 1e10), (1000, 1e10), (1500, 1e8)])
 def test_triangular_inverse_matches_substitution(ctx, n, kappa):
     """X = R^{-1} column by column against the oracle's back substitution of R x = e_c, within the
     forward-error bound of a triangular inverse, |X^ - X| <= c n u |X| |R| |X| (normwise per column,
@@ -282,8 +282,10 @@ def test_triangular_inverse_matches_substitution(ctx, n, kappa):
     Xg = host(X)
     assert np.all(np.tril(Xg, -1) == 0.0)
     assert np.array_equal(np.diag(Xg), 1.0 / np.diag(Ru))
-    cols = list(range(n)) if n <= 333 else sorted({0, 1, 62, 63, 64, 65, 127, 128, 500, 511, 512, 513, 767, 768,
-                                                   958, 959, 960, 998, 999} | set(rng.choice(n, 16, replace=False).tolist()))
+    edges = {0, 1, 62, 63, 64, 65, 127, 128, 500, 511, 512, 513, 767, 768, 958, 959, 960, 998, 999, 1023, 1024,
+             1025, 1499}
+    cols = list(range(n)) if n <= 333 else sorted({c for c in edges if c < n}
+                                                  | set(rng.choice(n, 16, replace=False).tolist()))
     M = np.abs(Xg) @ np.abs(Ru) @ np.abs(Xg)
     for c in cols:
         e = np.zeros(n)
