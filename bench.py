@@ -45,8 +45,8 @@ HBM_PEAK_GBPS = 8000.0
 # HBM bytes per launch of the fused pass at 1e6 x 1000 from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
 # by a 1 GiB copy (profiles/fused_pass_1e6x1000_hbm_traffic.md); valid only for the kernel source
 # with this hash (reported as null otherwise).
-PASS_TRAFFIC_BYTES = 8.0080e9
-PASS_TRAFFIC_SHA256 = "f4bd409364bf8690db3a2d48dbf9e68b7867e3217676687e660c1dd4385e06b7"
+PASS_TRAFFIC_BYTES = 8.0094e9
+PASS_TRAFFIC_SHA256 = "a8a8f4b72c243e3c45e65dfff4fae48813d9312c4110eb56f4b93a2460d67cbe"
 
 
 def parse():
@@ -755,7 +755,7 @@ def main():
                 "stream_read_GBps": round(stream_gbps, 1), "frac_of_stream_read": round(achieved / stream_gbps, 4),
                 "frac": round(achieved / HBM_PEAK_GBPS, 4),
                 "traffic": PASS_TRAFFIC_BYTES if same_kernel else None, "algorithmic_bytes": alg_bytes,
-                "kernel": "k_fused_pass (v = A^T(A z), H=16 rows x 1000 cols per tile)",
+                "kernel": "k_fused_pass (v = A^T(A z), H=32 rows x 1000 cols per tile)",
                 "ms_kernel": round(ms_kernel, 4), "ms_pass_with_reduction": round(ms_pass, 4)}
 
     # ---- the fused pass's autotuner at this shape (a context of its own: the numbers above use the

@@ -395,7 +395,7 @@ static bool pass_tile_ok(int H, int n) {
   const int64_t L = ((int64_t)n * H + 1023) / 1024;
   switch (H) {
     case 64: return L >= 1 && L <= 4;
-    case 32: return L >= 1 && L <= 8;
+    case 32: return L >= 1 && L <= 32;  // (residual passes above 8 slots run with 16 rows)
     case 16: return L >= 1 && L <= 16;
     case 8:
     case 4: return L >= 5 && L <= 16;
@@ -420,9 +420,11 @@ static PassConfig pass_config(fs_context ctx, int64_t m, int32_t n, int64_t lda)
   // a cap on the fused pass's work-groups (multiples of 8 keep its XCD banding)
   if (cfg.H && ctx->pass_group_cap > 0 && cfg.G > ctx->pass_group_cap)
     cfg.G = std::max(8, ctx->pass_group_cap / 8 * 8);
-  // 32-bit lane offsets inside a column slot (see the fused-pass kernel)
+  // 32-bit lane offsets inside a column slot (see the fused-pass kernel), for the tile height of the
+  // residual pass too (16 rows where the normal pass takes 32 above 256 columns)
   if (cfg.H) {
-    const int64_t cpr = 512 / (cfg.H / 2);
+    const int hres = (cfg.H == 32 && n > 256) ? 16 : cfg.H;
+    const int64_t cpr = 512 / (hres / 2);
     if ((cpr * lda + cfg.H) * 8 >= (int64_t(1) << 32)) cfg = PassConfig{0, 512};
   }
   return cfg;
