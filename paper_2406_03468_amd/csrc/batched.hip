@@ -165,8 +165,9 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
     if (statuses[i] != FS_OK) continue;
     opt[i] = o;
     // (tile heights 64 / 32 / 16 only, and 32-bit lane offsets inside a column slot)
-    const PassConfig pc = fs_pass_config_batched(P.m, P.n, 256);
-    const int64_t cpr = pc.H ? 512 / (pc.H / 2) : 0;
+    const PassConfig pc = fs_pass_config(P.m, P.n, 256);
+    const int hres = (pc.H == 32 && P.n > 256) ? 16 : pc.H;  // the residual pass's tile height
+    const int64_t cpr = hres ? 512 / (hres / 2) : 0;
     batched[i] = (P.n <= 1024 && pc.H >= 16 && (cpr * P.lda + pc.H) * 8 < (int64_t(1) << 32)) ? 1 : 0;
   }
   FS_HIP(hipSetDevice(ctx->device));
@@ -187,7 +188,7 @@ fs_status solve_batched(fs_context ctx, int32_t count, const fs_problem* probs, 
   std::vector<int> keyv(count, 0);
   std::map<int, double> group_work;
   for (int i : idx) {
-    pcs[i] = fs_pass_config_batched(probs[i].m, probs[i].n, ctx->num_cu);
+    pcs[i] = fs_pass_config(probs[i].m, probs[i].n, ctx->num_cu);
     const int cpr = 512 / (pcs[i].H / 2);
     const int L = (probs[i].n + cpr - 1) / cpr;
     const bool vec = ((probs[i].lda & 1) == 0) && ((reinterpret_cast<uintptr_t>(probs[i].A) & 15) == 0) &&

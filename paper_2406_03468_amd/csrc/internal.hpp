@@ -40,8 +40,6 @@ struct PassConfig {
   int G;  // work-groups
 };
 PassConfig fs_pass_config(int64_t m, int n, int num_cu);
-// The same rule for the batched passes (no 32-row tiles above 256 columns).
-PassConfig fs_pass_config_batched(int64_t m, int n, int num_cu);
 // out = out_scale .* (A^T w), w = A zs (normal) or b - A zs (residual, r2_out = ||w||^2).
 hipError_t fs_launch_pass(const PassArgs& a, const PassConfig& cfg, double* out, const double* out_scale,
                           double* r2_out, double* w_scratch, hipStream_t s);

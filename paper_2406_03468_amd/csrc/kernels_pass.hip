@@ -220,7 +220,7 @@ __global__ __launch_bounds__(NT, 1) void k_fused_pass_batched(const BatchPass* _
   int k = 0;
   while (k + 1 < count && list[k + 1].wg0 <= gw) ++k;
   const BatchPass& p = list[k];
-  fused_pass_body<H, NT, L, RESID, VEC, true>(p.A, p.lda, p.m, p.n, p.zs, RESID ? p.b : nullptr, p.partial,
+  fused_pass_body<H, NT, L, RESID, VEC, !(H == 32 && L > 8)>(p.A, p.lda, p.m, p.n, p.zs, RESID ? p.b : nullptr, p.partial,
                                                p.partial_r2, p.stop, nullptr, gw - p.wg0, p.G);
 }
 
@@ -433,7 +433,7 @@ template <bool RESID, bool VEC>
 hipError_t launch_batched(const BatchPass* list, int count, int H, int L, int total, hipStream_t s) {
   switch (H) {
     case 64: return launch_batched_exact<64, RESID, VEC, 1, 4>(list, count, L, total, s);
-    case 32: return launch_batched_exact<32, RESID, VEC, 1, 8>(list, count, L, total, s);
+    case 32: return launch_batched_exact<32, RESID, VEC, 1, RESID ? 8 : 32>(list, count, L, total, s);
     case 16: return launch_batched_exact<16, RESID, VEC, 1, 16>(list, count, L, total, s);
     default: return hipErrorInvalidValue;
   }
@@ -461,14 +461,6 @@ PassConfig fs_pass_config(int64_t m, int n, int num_cu) {
   if (c.H && T < G) G = (int)((T + 7) / 8 * 8);
   if (G < 1) G = 1;
   c.G = c.H ? G : 512;
-  return c;
-}
-
-// The batched passes' rule: 64 rows up to 64 columns, 32 up to 256, 16 up to 1024 (the prefetching
-// pass body for every problem of a launch).
-PassConfig fs_pass_config_batched(int64_t m, int n, int num_cu) {
-  PassConfig c = fs_pass_config(m, n, num_cu);
-  if (c.H == 32 && n > 256) c.H = 16;
   return c;
 }
 
@@ -503,6 +495,12 @@ hipError_t fs_launch_pass_kernel_only(const PassArgs& a, const PassConfig& cfg, 
 hipError_t fs_launch_pass_batched(const BatchPass* list, int count, int H, int L, bool vec, bool resid,
                                   int total_wgs, int max_n, hipStream_t s) {
   if (count < 1 || total_wgs < 1) return hipSuccess;
+  // the residual pass of a 32-row group above 8 column slots: 16-row tiles (ceil(L / 2) slots for every
+  // problem of the group), the same work-groups and partials
+  if (resid && H == 32 && L > 8) {
+    H = 16;
+    L = (L + 1) / 2;
+  }
   hipError_t e = resid ? (vec ? launch_batched<true, true>(list, count, H, L, total_wgs, s)
                               : launch_batched<true, false>(list, count, H, L, total_wgs, s))
                        : (vec ? launch_batched<false, true>(list, count, H, L, total_wgs, s)
