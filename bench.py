@@ -46,7 +46,7 @@ HBM_PEAK_GBPS = 8000.0
 # by a 1 GiB copy (profiles/fused_pass_1e6x1000_hbm_traffic.md); valid only for the kernel source
 # with this hash (reported as null otherwise).
 PASS_TRAFFIC_BYTES = 8.0094e9
-PASS_TRAFFIC_SHA256 = "a8a8f4b72c243e3c45e65dfff4fae48813d9312c4110eb56f4b93a2460d67cbe"
+PASS_TRAFFIC_SHA256 = "692b9233952d260f41918c6e1ef948ded0b602bbc8e41365f4ee585806ed40ac"
 
 
 def parse():
