@@ -130,12 +130,11 @@ def test_lemma73_polyak_rate():
     M = AR.T @ AR
     c = AR.T @ P.b
     ystar = np.linalg.solve(M, c)
-    dy, dy_old = c.copy(), c.copy()                 # Algorithm 5 start
-    for j in range(1, 40):
+    for j in range(1, 40):                          # the oracle's Algorithm 5 after j - 1 updates
+        dy = solvers.polyak(lambda y: M @ y, c, alpha, beta, j)
         err = np.linalg.norm(dy - ystar)
         bound = 4 * np.sqrt(2) * j * eta ** (j - 2) * np.linalg.norm(c)
         assert err <= bound + 1e-13 * np.linalg.norm(ystar), j
-        dy, dy_old = dy + alpha * (c - M @ dy) + beta * (dy - dy_old), dy
 
 
 def test_one_refinement_step_is_not_backward_stable():
