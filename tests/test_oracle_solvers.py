@@ -137,6 +137,19 @@ def test_lemma73_polyak_rate():
         assert err <= bound + 1e-13 * np.linalg.norm(ystar), j
 
 
+def test_first_step_rule_special_cases():
+    """Alg 4's first-step rule stops at the first iteration with ||Delta|| <= (gamma normest ||x_0|| +
+    rho condest ||r_0||) u: a huge gamma stops it after one update, gamma = rho = 0 never stops it (the
+    cap), and the count cannot grow with gamma."""
+    P = make_problem(3000, 30, 1e8, 1e-4, seed=12)
+    one = solvers.fossils(P.A, P.b, solvers.Options(gamma=1e30, steps=1))
+    assert one.iters[0] == 1
+    cap = solvers.fossils(P.A, P.b, solvers.Options(gamma=0.0, rho=0.0, steps=1, max_inner=37))
+    assert cap.iters[0] == 37
+    counts = [solvers.fossils(P.A, P.b, solvers.Options(gamma=g, steps=1)).iters[0] for g in (1e-2, 1.0, 1e2, 1e4)]
+    assert all(a >= b for a, b in zip(counts, counts[1:])) and counts[0] > counts[-1], counts
+
+
 def test_one_refinement_step_is_not_backward_stable():
     """Section 5.1: FOSSILS (1 step) is forward but not backward stable on hard problems."""
     P = make_problem(4000, 50, 1e12, 1e12 * U, seed=5)
